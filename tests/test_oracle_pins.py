@@ -1,0 +1,423 @@
+"""Pins of the oracle against facts fixed by the paper and by mathematics (CPU only).
+
+Each test checks the oracle against something other than itself: closed forms of special cases, a
+library routine (scipy rotations, Mahalanobis distances and normal densities, torch autograd,
+torch.optim.Adam), brute force over all pairs, exact invariants and finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.distance import mahalanobis
+from scipy.spatial.transform import Rotation
+from scipy.stats import multivariate_normal
+
+import oracle
+from paper_2603_09621_amd import synth
+from tests import cases
+
+EPS = 1e-8
+
+
+def _centres(grid):
+    z, y, x = np.meshgrid(np.arange(grid.nz), np.arange(grid.ny), np.arange(grid.nx), indexing="ij")
+    o, h = np.asarray(grid.origin), np.asarray(grid.spacing)
+    return np.stack([o[0] + h[0] * x, o[1] + h[1] * y, o[2] + h[2] * z], axis=-1).astype(np.float64)
+
+
+def _one(mu, ls, q, A=1.0, r=1.0):
+    return {"mu": np.array([mu], np.float32), "log_scale": np.array([ls], np.float32),
+            "quat": np.array([q], np.float32), "amp": np.array([A], np.float32), "relax": np.array([r], np.float32)}
+
+
+def _cat(*ps):
+    return {k: np.concatenate([p[k] for p in ps]) for k in ps[0]}
+
+
+# ----------------------------------------------------------------------------------------------
+# Forward
+
+
+@pytest.mark.parametrize("eps", [1e-8, 0.05])
+def test_single_isotropic_closed_form(eps):
+    """One isotropic Gaussian: W = r exp(-|p-mu|^2 / 2 sigma^2) [|p-mu|^2 <= 9 sigma^2], S = A W,
+    I = S / (W + eps); the rotation must not matter."""
+    grid = oracle.Grid(17, 14, 11)
+    sigma, A, r = 1.7, 0.3, 0.7
+    mu = [8.31, 6.77, 5.12]
+    q = synth.random_quaternions(np.random.default_rng(0), 1)[0]
+    p = _one(mu, [math.log(sigma)] * 3, q, A, r)
+    I, W, S = oracle.render(p, grid, eps=eps)
+    mu64 = np.asarray(p["mu"][0], np.float64)
+    sig64 = float(np.exp(np.float64(np.float32(math.log(sigma)))))
+    dist2 = ((_centres(grid) - mu64) ** 2).sum(-1)
+    Wx = np.where(dist2 <= 9 * sig64 ** 2, np.float64(np.float32(r)) * np.exp(-dist2 / (2 * sig64 ** 2)), 0.0)
+    Sx = np.float64(np.float32(A)) * Wx
+    np.testing.assert_allclose(W, Wx, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(S, Sx, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(I, Sx / (Wx + eps), rtol=1e-12, atol=1e-300)
+    assert (W > 0).sum() > 100
+
+
+def test_axis_aligned_anisotropic_closed_form():
+    """Identity rotation: d^2 = sum_k (delta_k / sigma_k)^2."""
+    grid = oracle.Grid(21, 15, 13)
+    sig = np.array([2.3, 0.9, 1.4])
+    p = _one([10.2, 7.6, 6.1], np.log(sig), [1, 0, 0, 0], 0.8, 1.0)
+    _, W, _ = oracle.render(p, grid)
+    s64 = np.exp(np.asarray(p["log_scale"][0], np.float64))
+    d2 = (((_centres(grid) - np.asarray(p["mu"][0], np.float64)) / s64) ** 2).sum(-1)
+    np.testing.assert_allclose(W, np.where(d2 <= 9, np.exp(-d2 / 2), 0), rtol=1e-12, atol=1e-300)
+
+
+def test_cutoff_is_inclusive():
+    """A voxel at exactly d^2 = 9 (sigma = 1, delta = (3, 0, 0)) is included; d^2 = 16 is not."""
+    grid = oracle.Grid(12, 12, 12)
+    p = _one([5.5, 5.5, 5.5], [0, 0, 0], [1, 0, 0, 0], 1.0, 1.0)
+    _, W, _ = oracle.render(p, grid)
+    assert W[5, 5, 8] == pytest.approx(math.exp(-4.5), rel=1e-15)
+    assert W[5, 5, 9] == 0.0
+    assert W[5, 5, 2] == pytest.approx(math.exp(-4.5), rel=1e-15)
+
+
+def test_frames_match_scipy():
+    """R from the quaternion (w, x, y, z) equals scipy's rotation (scalar-last order); the columns
+    of R are eigenvectors of Sigma with eigenvalues exp(2 s); P is the inverse of Sigma."""
+    rng = np.random.default_rng(3)
+    q = synth.random_quaternions(rng, 50) * rng.uniform(0.3, 3.0, (50, 1)).astype(np.float32)
+    ls = rng.normal(0.2, 0.7, (50, 3)).astype(np.float32)
+    R, Sig, P = oracle.frames(ls, q)
+    q64 = q.astype(np.float64)
+    Rs = Rotation.from_quat(q64[:, [1, 2, 3, 0]]).as_matrix()
+    np.testing.assert_allclose(R, Rs, atol=1e-12)
+    ev = np.exp(2 * ls.astype(np.float64))
+    for i in range(50):
+        np.testing.assert_allclose(Sig[i] @ Rs[i], Rs[i] * ev[i][None, :], rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(P[i], np.linalg.inv(Sig[i]), rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(Sig[i], Sig[i].T, atol=1e-14)
+
+
+def test_anisotropic_weight_matches_normal_density():
+    """Inside the support, W / r = (2 pi)^{3/2} sqrt(det Sigma) N(p; mu, Sigma) with Sigma built
+    from scipy's rotation; the support is exactly scipy's Mahalanobis distance <= 3."""
+    grid = oracle.Grid(19, 17, 15)
+    rng = np.random.default_rng(5)
+    q = synth.random_quaternions(rng, 1)[0]
+    ls = np.array([0.9, 0.2, -0.1], np.float32)
+    mu = np.array([9.3, 8.1, 7.4], np.float32)
+    p = _one(mu, ls, q, 1.0, 0.6)
+    _, W, _ = oracle.render(p, grid)
+    Rs = Rotation.from_quat(q.astype(np.float64)[[1, 2, 3, 0]]).as_matrix()
+    Sig = Rs @ np.diag(np.exp(2 * ls.astype(np.float64))) @ Rs.T
+    VI = np.linalg.inv(Sig)
+    C = _centres(grid).reshape(-1, 3)
+    dens = multivariate_normal(mean=mu.astype(np.float64), cov=Sig).pdf(C)
+    d = np.array([mahalanobis(c, mu.astype(np.float64), VI) for c in C])
+    expect = np.where(d ** 2 <= 9, np.float64(np.float32(0.6)) * (2 * np.pi) ** 1.5 * np.sqrt(np.linalg.det(Sig))
+                      * dens, 0.0)
+    np.testing.assert_allclose(W.reshape(-1), expect, rtol=1e-9, atol=1e-14)
+    assert (expect > 0).sum() > 200
+
+
+def test_two_gaussian_logistic_edge():
+    """Two equal isotropic Gaussians: where both contribute, I = (A1 + A2 e^z) / (1 + e^z + eps/w1)
+    with z = (p - m).(mu2 - mu1) / sigma^2 + ln(r2 / r1) and m the midpoint."""
+    grid = oracle.Grid(24, 12, 12)
+    sigma = 2.0
+    p = _cat(_one([9.2, 6.1, 5.8], [math.log(sigma)] * 3, [1, 0, 0, 0], 0.2, 0.9),
+             _one([13.7, 6.4, 6.3], [math.log(sigma)] * 3, [1, 0, 0, 0], 0.95, 0.5))
+    I, W, _ = oracle.render(p, grid)
+    mu = p["mu"].astype(np.float64)
+    A = p["amp"].astype(np.float64)
+    r = p["relax"].astype(np.float64)
+    s2 = float(np.exp(2 * np.float64(np.float32(math.log(sigma)))))
+    C = _centres(grid)
+    d1 = ((C - mu[0]) ** 2).sum(-1)
+    d2 = ((C - mu[1]) ** 2).sum(-1)
+    both = (d1 <= 9 * s2) & (d2 <= 9 * s2)
+    z = ((C - (mu[0] + mu[1]) / 2) @ (mu[1] - mu[0])) / s2 + math.log(r[1] / r[0])
+    w1 = r[0] * np.exp(-d1 / (2 * s2))
+    expect = (A[0] + A[1] * np.exp(z)) / (1 + np.exp(z) + EPS / w1)
+    assert both.sum() > 100
+    np.testing.assert_allclose(I[both], expect[both], rtol=1e-12)
+
+
+def test_constant_intensity_partition_of_unity():
+    """A_i = c for all i: I = c W / (W + eps), so |I - c| <= c eps / W wherever W > 0 (§3.2)."""
+    p, grid = cases.small_case(11, n=80, ls_std=0.5, cond=False)
+    c = 0.37
+    p["amp"][:] = c
+    p["relax"] = np.random.default_rng(1).uniform(0.2, 1.0, 80).astype(np.float32)
+    I, W, _ = oracle.render(p, grid)
+    cf = np.float64(np.float32(c))
+    m = W > 0
+    assert m.sum() > 0.5 * W.size
+    assert np.all(np.abs(I[m] - cf) <= cf * EPS / W[m] * (1 + 1e-9) + 1e-15)
+    assert np.all(I[~m] == 0)
+
+
+def test_permutation_invariance():
+    """Order independence (§3.3): permuting the Gaussians leaves I and W unchanged up to rounding and
+    permutes the gradients."""
+    p, grid = cases.small_case(12, n=90, cond=False)
+    perm = np.random.default_rng(2).permutation(90)
+    pp = {k: v[perm] for k, v in p.items()}
+    I1, W1, _ = oracle.render(p, grid)
+    I2, W2, _ = oracle.render(pp, grid)
+    np.testing.assert_allclose(I2, I1, rtol=1e-13, atol=1e-300)
+    np.testing.assert_allclose(W2, W1, rtol=1e-13, atol=1e-300)
+    g = np.random.default_rng(3).standard_normal(grid.shape)
+    g1 = oracle.grad(p, grid, I1, W1, g)
+    g2 = oracle.grad(pp, grid, I2, W2, g)
+    for k in oracle.GROUPS:
+        np.testing.assert_allclose(g2[k], g1[k][perm], rtol=1e-11, atol=1e-13)
+
+
+def _bruteforce(p, grid, cutoff):
+    """All pairs, scipy Mahalanobis distance and normal density; returns (I, W)."""
+    C = _centres(grid).reshape(-1, 3)
+    Wt = np.zeros(C.shape[0])
+    St = np.zeros(C.shape[0])
+    q = p["quat"].astype(np.float64)
+    for i in range(p["amp"].shape[0]):
+        Rs = Rotation.from_quat(q[i, [1, 2, 3, 0]]).as_matrix()
+        Sig = Rs @ np.diag(np.exp(2 * p["log_scale"][i].astype(np.float64))) @ Rs.T
+        mu = p["mu"][i].astype(np.float64)
+        d = C - mu
+        d2 = np.einsum("na,ab,nb->n", d, np.linalg.inv(Sig), d)
+        w = float(p["relax"][i]) * (2 * np.pi) ** 1.5 * np.sqrt(np.linalg.det(Sig)) * \
+            multivariate_normal(mean=mu, cov=Sig).pdf(C)
+        w = np.where(d2 <= cutoff ** 2, w, 0.0)
+        Wt += w
+        St += float(p["amp"][i]) * w
+    return (St / (Wt + EPS)).reshape(grid.shape), Wt.reshape(grid.shape)
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_truncated_and_full_match_bruteforce(threads):
+    """The per-Gaussian index box drops no voxel: truncated and untruncated renders equal brute
+    force over all pairs (any thread split of the z-slabs)."""
+    p, grid = cases.small_case(13, dims=(14, 13, 11), n=25, ls_std=0.5)
+    for cutoff in (3.0, math.inf):
+        I, W, _ = oracle.render(p, grid, cutoff=cutoff, threads=threads)
+        Ib, Wb = _bruteforce(p, grid, cutoff)
+        np.testing.assert_allclose(W, Wb, rtol=1e-9, atol=1e-15)
+        np.testing.assert_allclose(I, Ib, rtol=1e-9, atol=1e-15)
+
+
+def test_truncation_error_bound():
+    """|I_full - I_trunc| <= W_o / (W_full + eps) * max_i |A_i - I_trunc|, W_o the omitted weight."""
+    p, grid = cases.small_case(14, dims=(16, 16, 12), n=40, ls_std=0.4)
+    It, Wt, St = oracle.render(p, grid, cutoff=3.0)
+    If, Wf, Sf = oracle.render(p, grid, cutoff=math.inf)
+    Wo = Wf - Wt
+    amax = np.max(np.abs(p["amp"].astype(np.float64)[:, None, None, None] - It[None]), axis=0)
+    assert np.all(np.abs(If - It) <= Wo / (Wf + EPS) * amax + 1e-13)
+    # the omitted weight of one Gaussian is at most r e^{-4.5} per voxel
+    assert np.all(Wo <= 40 * math.exp(-4.5) + 1e-12)
+
+
+def test_render_points_and_count_pairs_agree():
+    p, grid = cases.small_case(15, dims=(18, 16, 12), n=70, ls_std=0.5)
+    I, W, S = oracle.render(p, grid)
+    vox = np.random.default_rng(4).choice(grid.size, 300, replace=False)
+    Ip, Wp, Sp = oracle.render_points(p, grid, vox)
+    np.testing.assert_allclose(Ip, I.reshape(-1)[vox], rtol=1e-14, atol=1e-300)
+    np.testing.assert_allclose(Wp, W.reshape(-1)[vox], rtol=1e-14, atol=1e-300)
+    # useful pairs: brute count with scipy Mahalanobis distances
+    C = _centres(grid).reshape(-1, 3)
+    brute = 0
+    q = p["quat"].astype(np.float64)
+    for i in range(70):
+        Rs = Rotation.from_quat(q[i, [1, 2, 3, 0]]).as_matrix()
+        Sig = Rs @ np.diag(np.exp(2 * p["log_scale"][i].astype(np.float64))) @ Rs.T
+        d = C - p["mu"][i].astype(np.float64)
+        brute += int((np.einsum("na,ab,nb->n", d, np.linalg.inv(Sig), d) <= 9).sum())
+    assert oracle.count_pairs(p, grid) == brute
+
+
+def test_conditioning_leaves_no_ambiguous_pair():
+    p, grid = cases.small_case(16, dims=(24, 20, 16), n=300, ls_std=0.5, cond=False)
+    before = int((oracle.ambiguous(p, grid, cases.BAND) > 0).sum())
+    pc = cases.condition(p, grid, seed=3)
+    assert int((oracle.ambiguous(pc, grid, cases.BAND) > 0).sum()) == 0
+    assert before > 0  # the band is wide enough to matter at this size
+
+
+def test_long_double_agrees():
+    """FP64 oracle error: rebuilt in long double, the forward agrees to ~1e-15 relative and the
+    gradients to ~1e-12 relative of their scale."""
+    p, grid = cases.small_case(17, dims=(20, 16, 12), n=120, ls_std=0.4)
+    I, W, _ = oracle.render(p, grid)
+    Il, Wl, _ = oracle.render(p, grid, long_double=True)
+    np.testing.assert_allclose(I, Il, rtol=1e-13, atol=1e-300)
+    np.testing.assert_allclose(W, Wl, rtol=1e-13, atol=1e-300)
+    g = np.random.default_rng(5).standard_normal(grid.shape) / grid.size
+    a = oracle.grad(p, grid, I, W, g)
+    b = oracle.grad(p, grid, Il, Wl, g, long_double=True)
+    for k in oracle.GROUPS:
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-9, atol=1e-12 * np.abs(b[k]).max())
+
+
+# ----------------------------------------------------------------------------------------------
+# Backward
+
+
+def _torch_loss(p, grid, g, cutoff, eps=EPS):
+    """Dense masked forward in torch float64: for autograd only (mask has no gradient)."""
+    t = {k: torch.tensor(v.astype(np.float64), requires_grad=True) for k, v in p.items()}
+    q = t["quat"] / t["quat"].norm(dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    R = torch.stack([torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+                     torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+                     torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
+    Sig = R @ torch.diag_embed(torch.exp(2 * t["log_scale"])) @ R.transpose(1, 2)
+    Pm = torch.linalg.inv(Sig)
+    C = torch.tensor(_centres(grid).reshape(-1, 3))
+    d = C[None, :, :] - t["mu"][:, None, :]
+    d2 = torch.einsum("nva,nab,nvb->nv", d, Pm, d)
+    mask = (d2 <= cutoff ** 2).detach().to(torch.float64)
+    wt = t["relax"][:, None] * torch.exp(-0.5 * d2) * mask
+    Wsum = wt.sum(0)
+    I = (t["amp"][:, None] * wt).sum(0) / (Wsum + eps)
+    L = (torch.tensor(g.reshape(-1)) * I).sum()
+    L.backward()
+    return {k: t[k].grad.numpy() for k in t}
+
+
+@pytest.mark.parametrize("cutoff", [3.0, math.inf])
+def test_grad_matches_torch_autograd(cutoff):
+    """The analytic gradient (§3.3) equals autograd through a dense masked formula."""
+    p, grid = cases.small_case(21, dims=(14, 12, 10), n=30, ls_std=0.4)
+    p["relax"] = np.random.default_rng(6).uniform(0.3, 1.0, 30).astype(np.float32)
+    p["quat"] = p["quat"] * np.random.default_rng(7).uniform(0.5, 2.0, (30, 1)).astype(np.float32)
+    g = np.random.default_rng(8).standard_normal(grid.shape)
+    I, W, _ = oracle.render(p, grid, cutoff=cutoff)
+    ours = oracle.grad(p, grid, I, W, g, cutoff=cutoff)
+    ref = _torch_loss(p, grid, g, cutoff)
+    for k in oracle.GROUPS:
+        scale = np.abs(ref[k]).max()
+        np.testing.assert_allclose(ours[k], ref[k], rtol=1e-8, atol=1e-10 * scale, err_msg=k)
+
+
+def test_grad_matches_central_differences():
+    """Untruncated (smooth) case: every gradient entry equals a central difference of L = <g, I>."""
+    p, grid = cases.small_case(22, dims=(10, 9, 8), n=6, ls_std=0.3, cond=False)
+    p["relax"] = np.random.default_rng(9).uniform(0.4, 1.0, 6).astype(np.float32)
+    g = np.random.default_rng(10).standard_normal(grid.shape)
+    I, W, _ = oracle.render(p, grid, cutoff=math.inf)
+    an = oracle.grad(p, grid, I, W, g, cutoff=math.inf)
+
+    def L(pp):
+        return float((oracle.render(pp, grid, cutoff=math.inf)[0] * g).sum())
+
+    h = 2.5e-4
+    for k in oracle.GROUPS:
+        flat = p[k].reshape(-1)
+        for j in range(flat.size):
+            pp = {kk: vv.copy() for kk, vv in p.items()}
+            pm = {kk: vv.copy() for kk, vv in p.items()}
+            pp[k].reshape(-1)[j] = np.float32(flat[j] + h)
+            pm[k].reshape(-1)[j] = np.float32(flat[j] - h)
+            step = float(pp[k].reshape(-1)[j]) - float(pm[k].reshape(-1)[j])
+            fd = (L(pp) - L(pm)) / step
+            a = an[k].reshape(-1)[j]
+            assert abs(fd - a) <= 2e-5 * max(abs(a), 1e-2 * np.abs(an[k]).max()) + 1e-9, (k, j, fd, a)
+
+
+def test_quaternion_invariances():
+    """q -> -q and q -> lambda q leave the render unchanged; q . dq = 0; dq(lambda q) = dq(q) / lambda."""
+    p, grid = cases.small_case(23, dims=(14, 12, 10), n=40)
+    g = np.random.default_rng(11).standard_normal(grid.shape)
+    I, W, _ = oracle.render(p, grid)
+    d = oracle.grad(p, grid, I, W, g)
+    pn = dict(p, quat=-p["quat"])
+    In, _, _ = oracle.render(pn, grid)
+    np.testing.assert_array_equal(In, I)
+    lam = 4.0  # a power of two: lambda q is exact in FP32, so qhat is the same
+    pl = dict(p, quat=(p["quat"] * lam).astype(np.float32))
+    Il, Wl, _ = oracle.render(pl, grid)
+    np.testing.assert_allclose(Il, I, rtol=1e-14, atol=1e-300)
+    dl = oracle.grad(pl, grid, Il, Wl, g)
+    np.testing.assert_allclose(dl["quat"] * lam, d["quat"], rtol=1e-12, atol=1e-9 * np.abs(d["quat"]).max())
+    dots = (d["quat"] * p["quat"].astype(np.float64)).sum(1)
+    assert np.all(np.abs(dots) <= 1e-12 * np.abs(d["quat"]).max() + 1e-300)
+
+
+def test_relaxation_scaling():
+    """Scaling every r by lambda leaves I unchanged up to eps, so sum_i r_i dL/dr_i = O(eps)."""
+    p, grid = cases.small_case(24, dims=(14, 12, 10), n=50)
+    p["relax"] = np.random.default_rng(12).uniform(0.3, 1.0, 50).astype(np.float32)
+    I, W, _ = oracle.render(p, grid)
+    I2, _, _ = oracle.render(dict(p, relax=(p["relax"] * 2).astype(np.float32)), grid)
+    m = W > 0
+    assert np.all(np.abs(I2[m] - I[m]) <= 2 * EPS / W[m] + 1e-15)
+    g = np.random.default_rng(13).standard_normal(grid.shape)
+    d = oracle.grad(p, grid, I, W, g)
+    euler = float((d["relax"] * p["relax"].astype(np.float64)).sum())
+    assert abs(euler) <= 1e-6 * np.abs(d["relax"] * p["relax"]).sum()
+
+
+def test_grad_subset_equals_full():
+    p, grid = cases.small_case(25, dims=(16, 14, 10), n=60)
+    I, W, _ = oracle.render(p, grid)
+    g = np.random.default_rng(14).standard_normal(grid.shape)
+    full = oracle.grad(p, grid, I, W, g)
+    sel = np.array([3, 17, 41, 59])
+    sub = oracle.grad(p, grid, I, W, g, sel=sel)
+    for k in oracle.GROUPS:
+        np.testing.assert_array_equal(sub[k][sel], full[k][sel])
+
+
+# ----------------------------------------------------------------------------------------------
+# Loss, z-mean and Adam
+
+
+def test_zmean_adjoint_dot_product():
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal((16, 5, 7))
+    y = rng.standard_normal((4, 5, 7))
+    assert float((oracle.zmean(x) * y).sum()) == pytest.approx(float((x * oracle.zmean_adjoint(y)).sum()), rel=1e-12)
+    # z-mean of a volume constant along each group of 4 slices returns that constant
+    c = rng.standard_normal((4, 5, 7))
+    np.testing.assert_allclose(oracle.zmean(np.repeat(c, 4, axis=0)), c, rtol=1e-15)
+
+
+def test_losses_match_central_differences():
+    rng = np.random.default_rng(16)
+    I = rng.random((8, 5, 6))
+    T = rng.random((8, 5, 6))
+    O = rng.random((2, 5, 6)).astype(np.float32)
+    L, g = oracle.mse_loss(I, T)
+    L1, g1 = oracle.fit_l1_loss(I, O)
+    h = 1e-6
+    for idx in [(0, 0, 0), (3, 2, 4), (7, 4, 5), (5, 1, 1)]:
+        Ip = I.copy(); Ip[idx] += h
+        Im = I.copy(); Im[idx] -= h
+        assert (oracle.mse_loss(Ip, T)[0] - oracle.mse_loss(Im, T)[0]) / (2 * h) == pytest.approx(g[idx], rel=1e-6)
+        assert (oracle.fit_l1_loss(Ip, O)[0] - oracle.fit_l1_loss(Im, O)[0]) / (2 * h) == pytest.approx(g1[idx],
+                                                                                                     rel=1e-5)
+    assert L == pytest.approx(float(((I - T) ** 2).mean()))
+    assert L1 == pytest.approx(float(np.abs(I.reshape(2, 4, 5, 6).mean(1) - O).mean()))
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(17)
+    n = 7
+    params = {"mu": rng.standard_normal((n, 3)), "log_scale": rng.standard_normal((n, 3)),
+              "quat": rng.standard_normal((n, 4)), "amp": rng.random(n), "relax": np.ones(n)}
+    lr = {"mu": 1e-2, "log_scale": 5e-3, "quat": 1e-3, "amp": 1e-2, "relax": 0.0}
+    tp = {k: torch.tensor(v.copy(), requires_grad=True) for k, v in params.items()}
+    opt = torch.optim.Adam([{"params": [tp[k]], "lr": lr[k]} for k in oracle.GROUPS], betas=(0.9, 0.999), eps=1e-8)
+    m = {k: np.zeros_like(v) for k, v in params.items()}
+    v = {k: np.zeros_like(v) for k, v in params.items()}
+    cur = params
+    for step in range(1, 6):
+        grads = {k: rng.standard_normal(val.shape) for k, val in params.items()}
+        for k in oracle.GROUPS:
+            tp[k].grad = torch.tensor(grads[k])
+        opt.step()
+        cur, m, v = oracle.adam_step(cur, grads, m, v, step, lr)
+        for k in oracle.GROUPS:
+            np.testing.assert_allclose(cur[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-14)
