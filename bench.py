@@ -1,0 +1,212 @@
+"""Benchmark of the rasterizer's hot path on one MI355X.
+
+A step is one iteration of the per-scan zero-shot fit (gs_fit_step): bin (prep, key generation,
+radix sort, brick offsets) -> forward render -> z-mean-of-4 L1 loss -> backward (brick partials,
+reduction, chain rule) -> Adam.  Workload: HR 256x256x128 phantom (60 soft ellipsoids, N(0, 0.01^2)
+noise), LR observation = mean of 4 consecutive z slices, 500k Gaussians initialised on the LR
+lattice.  Inputs are resident in HBM before timing starts.
+
+Metric: Gaussian-voxel evaluations per second (forward + backward): the number of useful pairs
+(voxel, Gaussian with d^2 <= 9) of every timed step's render, summed, over the timed wall time.
+Each useful pair is evaluated once in the forward and once in the backward.  The pair count comes
+from replaying the same steps from a snapshot (the kernels are deterministic) with a counting pass
+after each step.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU lane-instructions per useful pair (forward: delta 3, quadratic form 9, cutoff
+# compare + select 2, exp2 counted as 4 issue slots, two accumulations 2; backward: delta 3,
+# P delta 9, d^2 3, compare/exp/select 6, t, dA, kappa 4, dmu 3, the six second moments 9, dr 1).
+C_FWD, C_BWD = 20, 38
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: FP32 VALU lane-instructions per second (non-packed).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dims", type=int, nargs=3, default=(256, 256, 128))
+    ap.add_argument("--n", type=int, default=500000)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    src = os.path.join(ROOT, "paper_2603_09621_amd", "csrc", "render.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("source_sha256") != sha:
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_09621_amd import gs, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dims = tuple(args.dims)
+    t0 = time.time()
+    print(f"[bench] generating workload {dims} n={args.n}", file=sys.stderr, flush=True)
+    p, lr_obs, _ = synth.workload_fit(args.seed, dims, args.n)
+    print(f"[bench] inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    grid = gs.Grid(*dims)
+    g = gs.Gaussians.from_numpy(p, device=dev)
+    fo = gs.FitOpts(grid)
+    obs = torch.from_numpy(lr_obs).to(dev)
+    bins = gs.plan_bins(g, grid, fo.opts, headroom=1.5)
+    st = gs.FitState(g)
+    buf = gs.FitBuffers(g.n, grid, relax=g.relax is not None, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        gs.gs_fit_step(st, obs, fo, bins, buf)
+
+    for _ in range(args.warmup):
+        step()
+    gs.gs_status(bins)
+    torch.cuda.synchronize()
+    snap = {k: getattr(g, k).clone() for k in gs.GROUPS if getattr(g, k) is not None}
+    snap_m, snap_v, snap_step = st.m.clone(), st.v.clone(), st.step.clone()
+
+    # ---- timed region -------------------------------------------------------------------------
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    status = gs.gs_status(bins, raise_on_error=False)
+    if status["rc"] != 0:
+        print(f"[bench] status after timed steps: {status}", file=sys.stderr, flush=True)
+        sys.exit(3)
+    final = {k: getattr(g, k).clone() for k in snap}
+    loss_end = float(buf.loss.item())
+
+    # ---- replay: useful pairs per step + per-kernel durations (HIP events on the launch stream) ---
+    for k, v in snap.items():
+        getattr(g, k).copy_(v)
+    st.m.copy_(snap_m)
+    st.v.copy_(snap_v)
+    st.step.copy_(snap_step)
+    total_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    gs.profile_reset()
+    gs.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+        gs.profile_enable(False)
+        gs.gs_count_pairs(g, grid, fo.opts, bins, cnt)
+        total_pairs += cnt
+        gs.profile_enable(True)
+    gs.profile_enable(False)
+    prof = gs.profile_read()
+    torch.cuda.synchronize()
+    replay_same = all(torch.equal(getattr(g, k), final[k]) for k in final)
+    U = int(total_pairs.item())
+    t_step = gpu_ms / 1e3 / args.steps
+    value = U / (gpu_ms / 1e3)
+
+    kern = {name: {"launches": n, "avg_ms": tot / n} for name, (n, tot) in prof.items() if n}
+    fwd_ms = kern.get("render_fwd", {}).get("avg_ms", float("nan"))
+    bwd_ms = kern.get("render_bwd", {}).get("avg_ms", float("nan"))
+    U_step = U / args.steps
+    if bwd_ms >= fwd_ms:
+        dom, c, t_k = "render_bwd", C_BWD, bwd_ms
+    else:
+        dom, c, t_k = "render_fwd", C_FWD, fwd_ms
+    achieved = U_step * c / (t_k / 1e3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": traffic_from_profiles(dom)}
+
+    # ---- CPU baseline: the oracle on the host cores, one full fit step of the same workload -------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle.default_threads()
+        print(f"[bench] oracle fit step on {threads} host threads", file=sys.stderr, flush=True)
+        og = oracle.Grid(*dims)
+        lr = dict(zip(oracle.GROUPS, [float(np.float32(x)) for x in fo.adam.lr]))
+        mom = {k: np.zeros(np.shape(p[k])) for k in oracle.GROUPS}
+        vel = {k: np.zeros(np.shape(p[k])) for k in oracle.GROUPS}
+        pairs0 = oracle.count_pairs(p, og, threads=threads)
+        c0 = time.perf_counter()
+        cur = p
+        for s in range(args.cpu_steps):
+            _, newp, mom, vel, _ = oracle.fit_step(cur, lr_obs, og, mom, vel, s + 1, lr, threads=threads)
+            cur = {k: np.asarray(v, np.float32) for k, v in newp.items()}
+        cpu_s = (time.perf_counter() - c0) / args.cpu_steps
+        cpu = {"value": pairs0 / cpu_s, "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_steps} FP64 fit step(s) (render, z-mean L1, gradient, Adam) of the full "
+                         f"{dims[0]}x{dims[1]}x{dims[2]} / {args.n}-Gaussian workload, "
+                         f"{pairs0} useful pairs per step, {cpu_s:.2f} s per step"}
+
+    out = {
+        "metric": "Gaussian-voxel evals/s (fwd+bwd)",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"single-scan zero-shot fit: HR {dims[0]}x{dims[1]}x{dims[2]} phantom, LR = z-mean "
+                               f"of 4, {args.n} Gaussians on the LR lattice, L1 + Adam",
+                   "global_batch": 1, "brick": [fo.opts.bx, fo.opts.by, fo.opts.bz]},
+        "fit_iters_per_s": 1.0 / t_step,
+        "useful_pairs_per_step": U_step,
+        "wall_s_timed": wall,
+        "loss_end": loss_end,
+        "replay_identical": replay_same,
+        "kernels_avg_ms": {k: round(v["avg_ms"], 5) for k, v in sorted(kern.items())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

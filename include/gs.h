@@ -1,0 +1,236 @@
+/*
+ * gs.h — C ABI of the MI355X (gfx950) brick-based Gaussian-to-voxel rasterizer.
+ *
+ * The library renders a voxel grid from 3D anisotropic Gaussians by normalised aggregation and
+ * computes the gradient used by the per-scan fit (paper §3.2–§3.3):
+ *
+ *   w_i(p) = r_i exp(-1/2 (p - mu_i)^T Sigma_i^{-1} (p - mu_i))  if that Mahalanobis d^2 <= cutoff^2
+ *   I(p)   = sum_i A_i w_i(p) / (sum_i w_i(p) + eps)
+ *   Sigma_i = R(q_i) diag(exp(2 s_i)) R(q_i)^T
+ *
+ * (§3.2 Eq. (rendering) and the spatial-weight equation after it; §3.1 for the 12 parameters per
+ * Gaussian: position 3, covariance 7 = 3 log-scales + 4 quaternion entries, amplitude 1,
+ * relaxation factor 1; §3.3 for the 3-sigma truncation, the brick partition and the two gradient
+ * equations.)  The cutoff predicate is per pair (voxel, Gaussian) and inclusive; eps is added to
+ * the denominator (also in the gradient).
+ *
+ * Conventions shared by every call:
+ *  - Pointers named d_* or documented as "device" are device pointers (e.g. torch tensors on the
+ *    GPU); pointers documented as "host" are host memory.  All floating-point data is FP32.
+ *  - The caller owns every buffer, including workspaces; the library allocates no device memory
+ *    and keeps no state between calls.
+ *  - Every call is asynchronous on the given stream (a hipStream_t passed as void*; NULL = the null
+ *    stream) unless documented as synchronising.  Host-detectable argument errors are returned at
+ *    once; errors detected on the device (non-finite input, key-capacity overflow) are latched in
+ *    the workspace's status block and returned by gs_status().
+ *  - Volumes are [nz][ny][nx] with x fastest.  Voxel (ix, iy, iz) has its centre at
+ *    origin + spacing * (ix, iy, iz) in world units.
+ *  - Return value: GS_OK (0) or a negative GS_ERR_* code; gs_last_error() describes the last error
+ *    of the calling thread.  Results are defined only when the status is GS_OK.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+
+enum {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = -1, /* null pointer, negative size, non-positive dims or spacing, bad options */
+  GS_ERR_CAPACITY = -2,    /* more (brick, Gaussian) keys than the workspace's key capacity */
+  GS_ERR_NONFINITE = -3,   /* NaN/Inf parameter, zero quaternion or relaxation factor <= 0 */
+  GS_ERR_HIP = -4,         /* a HIP runtime call failed */
+  GS_ERR_UNSUPPORTED = -5  /* valid but not supported by this build (e.g. a brick shape) */
+};
+
+/* Gaussian set (§3.1): n Gaussians, structure of arrays, device pointers. */
+typedef struct {
+  int64_t n;
+  const float *mu;        /* [n][3] centre, world units */
+  const float *log_scale; /* [n][3] natural log of the standard deviation along each principal axis */
+  const float *quat;      /* [n][4] rotation (w, x, y, z); any nonzero norm, normalised internally */
+  const float *amp;       /* [n]    amplitude A_i */
+  const float *relax;     /* [n]    relaxation factor r_i > 0, or NULL meaning r_i = 1 */
+} gs_gaussians_t;
+
+/* Output grid (any shape and resolution: rendering at an arbitrary target shape, §4.2). */
+typedef struct {
+  int32_t nx, ny, nz;
+  float origin[3];  /* centre of voxel (0,0,0) */
+  float spacing[3]; /* > 0 */
+} gs_grid_t;
+
+/* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4); supported shapes are
+ * listed by gs_brick_supported().  cutoff: Mahalanobis truncation radius (3 = the 3-sigma
+ * ellipsoid).  eps: denominator regulariser (>= 0). */
+typedef struct {
+  int32_t bx, by, bz;
+  float cutoff;
+  float eps;
+  uint32_t flags; /* reserved, must be 0 */
+} gs_opts_t;
+
+/* Binning workspace: caller-owned device memory of gs_workspace_size() bytes for `key_capacity`
+ * (brick, Gaussian) keys.  Holds the per-Gaussian records, the brick-sorted key lists, the brick
+ * offsets, the backward's per-key partial sums and the status block.  One workspace serves one
+ * Gaussian set and grid at a time. */
+typedef struct {
+  void *ws;
+  size_t ws_bytes;
+  int64_t key_capacity;
+} gs_bins_t;
+
+/* Gradient outputs (device, written, not accumulated).  Any pointer may be NULL to skip it. */
+typedef struct {
+  float *d_mu;        /* [n][3] */
+  float *d_log_scale; /* [n][3] */
+  float *d_quat;      /* [n][4] gradient w.r.t. the raw (unnormalised) quaternion */
+  float *d_amp;       /* [n] */
+  float *d_relax;     /* [n] (ignored when the Gaussians have relax == NULL) */
+} gs_grads_t;
+
+/* Adam hyper-parameters; lr per parameter group in the order mu, log_scale, quat, amp, relax. */
+typedef struct {
+  float lr[5];
+  float beta1, beta2, eps;
+} gs_adam_t;
+
+/* Fit state: parameters updated in place, Adam moments and the device step counter. */
+typedef struct {
+  int64_t n;
+  float *mu, *log_scale, *quat, *amp; /* device, [n][3], [n][3], [n][4], [n] */
+  float *relax;                        /* device [n], or NULL (r = 1, not optimised) */
+  float *m, *v;    /* device [12 n] each: groups mu (3n), log_scale (3n), quat (4n), amp (n), relax (n) */
+  int32_t *step;   /* device scalar: Adam steps taken so far (0 before the first step) */
+} gs_fit_state_t;
+
+/* Per-step fit options: HR grid, rasterizer options, z-downsampling factor of the LR observation
+ * (LR slice k = mean of HR slices f*k .. f*k+f-1) and Adam. */
+typedef struct {
+  gs_grid_t hr;
+  gs_opts_t opts;
+  int32_t zdown;
+  int32_t loss; /* 0 = L1 on the z-mean (the only loss of the fit) */
+  gs_adam_t adam;
+} gs_fit_opts_t;
+
+/* Caller-owned per-step buffers of the fit (device). */
+typedef struct {
+  float *I, *W;        /* [nz][ny][nx] forward outputs (kept for the backward) */
+  float *dL_dI;        /* [nz][ny][nx] */
+  gs_grads_t grads;    /* [n]-sized gradient arrays; all of d_mu, d_log_scale, d_quat, d_amp required */
+  void *scratch;       /* >= gs_loss_scratch_bytes(nx*ny*nz) bytes */
+  size_t scratch_bytes;
+  float *loss;         /* device scalar: the step's loss */
+} gs_fit_buffers_t;
+
+/* Device status block (read by gs_status). */
+typedef struct {
+  int64_t n_keys;     /* exact number of (brick, Gaussian) keys of the last binning */
+  int32_t overflow;   /* n_keys > key_capacity: the bins (and everything after) are invalid */
+  int32_t nonfinite;  /* some Gaussian had a non-finite parameter, zero quaternion or r <= 0 */
+} gs_status_t;
+
+/* ---- sizes and capabilities ---------------------------------------------------------------- */
+
+/* Bytes of binning workspace for n Gaussians on `grid` with `opts` and room for key_capacity keys.
+ * Host only; allocates nothing. */
+int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, int64_t key_capacity,
+                      size_t *bytes /* host out */);
+
+/* Bytes of scratch for the loss reductions over nvox voxels. */
+size_t gs_loss_scratch_bytes(int64_t nvox);
+
+/* 1 if the brick shape is supported by the kernels of this build, else 0. */
+int gs_brick_supported(int32_t bx, int32_t by, int32_t bz);
+
+/* ---- binning (§3.3: for each brick, the Gaussians whose 3-sigma ellipsoid meets it) --------- */
+
+/* Count the (brick, Gaussian) keys of `g` on `grid` and return the exact count in *n_keys (host).
+ * Needs a workspace sized for key_capacity >= 0 (0 is enough).  SYNCHRONISES the stream. */
+int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                 void *stream, int64_t *n_keys /* host out */);
+
+/* Build the per-brick Gaussian lists: per-Gaussian records, keys (brick id, Gaussian) for every
+ * brick that may meet the Gaussian's ellipsoid, radix sort on brick id (stable: ascending Gaussian
+ * index within a brick), brick offsets.  Resets the status block.  If the key count exceeds
+ * bins->key_capacity, the overflow flag is latched and every later call on these bins leaves its
+ * outputs unwritten until the next gs_bin. */
+int gs_bin(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+           void *stream);
+
+/* ---- forward (§3.2 Eq. (rendering); §3.3 forward cache) ------------------------------------- */
+
+/* Render I (and the per-voxel weight sum W, the cache the backward reads; may be NULL) on `grid`
+ * from bins built by gs_bin with the same g, grid and opts.  I, W: device [nz][ny][nx].  Each
+ * voxel sums its Gaussians in ascending index order (bitwise deterministic). */
+int gs_render_fwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                  float *I, float *W, void *stream);
+
+/* Number of useful pairs (voxel, Gaussian) with d^2 <= cutoff^2, written to *d_count (device
+ * int64).  Same bins contract as gs_render_fwd.  For measurement. */
+int gs_count_pairs(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                   int64_t *d_count, void *stream);
+
+/* ---- backward (§3.3 gradient equations) ---------------------------------------------------- */
+
+/* Gradients of a loss L w.r.t. every Gaussian parameter, given the forward's I and W and
+ * dL_dI = dL/dI per voxel (all device [nz][ny][nx]).  Per brick, per Gaussian partial sums are
+ * written to the workspace (no atomics); a per-Gaussian fixed-order reduction then applies the
+ * chain rule to (mu, log_scale, quat, amp, relax).  Bitwise deterministic. */
+int gs_render_bwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                  const float *I, const float *W, const float *dL_dI, const gs_grads_t *grads, void *stream);
+
+/* ---- losses of the fit ------------------------------------------------------------------------ */
+
+/* L = mean((I - T)^2) over nvox voxels; dL_dI = 2 (I - T) / nvox.  loss: device scalar. */
+int gs_loss_mse(const float *I, const float *T, int64_t nvox, float *dL_dI, float *loss, void *scratch,
+                size_t scratch_bytes, void *stream);
+
+/* Fit loss: LR = mean of zdown consecutive z slices of I ([nz/zdown][ny][nx], nz % zdown == 0);
+ * L = mean |LR - obs|; dL_dI = sign(LR - obs) / (zdown * nLR) broadcast to the zdown HR slices
+ * (sign(0) = 0).  loss: device scalar. */
+int gs_loss_l1_zmean(const float *I, const float *obs, const gs_grid_t *hr, int32_t zdown, float *dL_dI, float *loss,
+                     void *scratch, size_t scratch_bytes, void *stream);
+
+/* ---- optimiser and fit step ---------------------------------------------------------------- */
+
+/* One Adam step with bias correction on every parameter group of st, from grads (all required
+ * except d_relax; groups with lr 0 keep their values).  Increments *st->step. */
+int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_adam_t *hp, const gs_bins_t *bins,
+                 void *stream);
+
+/* One step of the per-scan zero-shot fit (§3.3 "end-to-end", Fig. 1): bin -> render -> z-mean ->
+ * L1 vs lr_obs -> backward -> Adam.  lr_obs: device [hr.nz/zdown][hr.ny][hr.nx].  No host
+ * synchronisation; check gs_status() for capacity overflow (the step then leaves the parameters
+ * unchanged). */
+int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
+                const gs_fit_buffers_t *buf, void *stream);
+
+/* ---- status, errors, profiling ---------------------------------------------------------------- */
+
+/* Copy the status block of `bins` to *out (host).  SYNCHRONISES the stream.  Returns GS_OK,
+ * GS_ERR_CAPACITY or GS_ERR_NONFINITE according to the latched flags. */
+int gs_status(const gs_bins_t *bins, void *stream, gs_status_t *out /* host */);
+
+/* Thread-local description of the last error returned to this thread. */
+const char *gs_last_error(void);
+
+/* Kernel timing: when enabled, every kernel the library launches is bracketed by HIP events on
+ * the launch stream; gs_profile_read() synchronises, accumulates the elapsed times per kernel name
+ * and returns up to `cap` entries (name, launches, total milliseconds) in host arrays. */
+int gs_profile_enable(int on);
+int gs_profile_read(void *stream, int cap, char (*names)[48], int64_t *launches, double *total_ms,
+                    int *n_out);
+int gs_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

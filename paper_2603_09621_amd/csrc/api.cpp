@@ -1,0 +1,422 @@
+// C ABI of the rasterizer library: argument checks, workspace layout, launch sequences, status,
+// errors and optional kernel timing.  Declared in include/gs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char *where) {
+  return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ---- optional kernel timing ---------------------------------------------------------------------
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof_pending;
+static std::vector<hipEvent_t> g_prof_pool;
+static std::vector<std::pair<std::string, std::pair<int64_t, double>>> g_prof_acc;
+static thread_local hipEvent_t g_prof_open = nullptr;
+
+static hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(hipStream_t s) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_open = prof_event();
+  if (g_prof_open) (void)hipEventRecord(g_prof_open, s);
+}
+
+void prof_end(hipStream_t s, const char *name) {
+  if (!g_prof_on || !g_prof_open) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = prof_event();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  g_prof_pending.push_back(ProfRec{name, g_prof_open, e});
+  g_prof_open = nullptr;
+}
+
+// ---- geometry and workspace layout ---------------------------------------------------------------
+
+static bool brick_supported(int bx, int by, int bz) { return bx == 8 && by == 8 && bz == 4; }
+
+bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg) {
+  bg->nx = grid->nx;
+  bg->ny = grid->ny;
+  bg->nz = grid->nz;
+  bg->bx = opts->bx;
+  bg->by = opts->by;
+  bg->bz = opts->bz;
+  bg->nbx = (grid->nx + opts->bx - 1) / opts->bx;
+  bg->nby = (grid->ny + opts->by - 1) / opts->by;
+  bg->nbz = (grid->nz + opts->bz - 1) / opts->bz;
+  bg->nbricks = (int64_t)bg->nbx * bg->nby * bg->nbz;
+  bg->ox = grid->origin[0];
+  bg->oy = grid->origin[1];
+  bg->oz = grid->origin[2];
+  bg->hx = grid->spacing[0];
+  bg->hy = grid->spacing[1];
+  bg->hz = grid->spacing[2];
+  return true;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout make_layout(int64_t n, const BrickGrid &bg, int64_t cap) {
+  WsLayout L;
+  L.n = n;
+  L.cap = cap;
+  L.nbricks = bg.nbricks;
+  L.sort_blocks = (int)((cap + kSortTile - 1) / kSortTile);
+  int bits = 0;
+  while (bits < 32 && ((int64_t)1 << bits) < bg.nbricks) ++bits;
+  L.sort_passes = bits == 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.status = take(sizeof(DevStatus));
+  L.evalrec = take(sizeof(EvalRec) * (size_t)n);
+  L.cullrec = take(sizeof(CullRec) * (size_t)n);
+  L.off = take(sizeof(uint32_t) * (size_t)(n + 1));
+  L.key_brick = take(sizeof(uint32_t) * (size_t)cap);
+  L.key_gid = take(sizeof(uint32_t) * (size_t)cap);
+  L.keys_alt = take(sizeof(uint32_t) * (size_t)cap);
+  L.vals_a = take(sizeof(uint32_t) * (size_t)cap);
+  L.vals_b = take(sizeof(uint32_t) * (size_t)cap);
+  L.sorted_gid = take(sizeof(uint32_t) * (size_t)cap);
+  L.brick_off = take(sizeof(uint32_t) * (size_t)(bg.nbricks + 1));
+  L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
+  int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
+  L.scan_tmp = take(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
+  L.partials = take(sizeof(float) * 12 * (size_t)cap);
+  L.total = o;
+  // the sorted slot list ends in vals_a after an odd number of passes, vals_b after an even number
+  L.sorted_slot = (L.sort_passes & 1) ? L.vals_a : L.vals_b;
+  return L;
+}
+
+// ---- argument checks -------------------------------------------------------------------------------
+
+static int check_grid(const gs_grid_t *grid) {
+  if (!grid) return fail(GS_ERR_INVALID_ARG, "grid is NULL");
+  if (grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0)
+    return fail(GS_ERR_INVALID_ARG, "grid dims must be positive (got %d x %d x %d)", grid->nx, grid->ny, grid->nz);
+  if ((int64_t)grid->nx * grid->ny * grid->nz > ((int64_t)1 << 40))
+    return fail(GS_ERR_INVALID_ARG, "grid too large");
+  for (int k = 0; k < 3; ++k) {
+    if (!(grid->spacing[k] > 0.f) || !std::isfinite(grid->spacing[k]) || !std::isfinite(grid->origin[k]))
+      return fail(GS_ERR_INVALID_ARG, "grid spacing must be positive and finite, origin finite");
+  }
+  return GS_OK;
+}
+
+static int check_opts(const gs_opts_t *opts) {
+  if (!opts) return fail(GS_ERR_INVALID_ARG, "opts is NULL");
+  if (opts->bx <= 0 || opts->by <= 0 || opts->bz <= 0) return fail(GS_ERR_INVALID_ARG, "brick dims must be positive");
+  if (!brick_supported(opts->bx, opts->by, opts->bz))
+    return fail(GS_ERR_UNSUPPORTED, "brick %dx%dx%d not supported by this build", opts->bx, opts->by, opts->bz);
+  if (!(opts->cutoff > 0.f) || !std::isfinite(opts->cutoff)) return fail(GS_ERR_INVALID_ARG, "cutoff must be > 0");
+  if (!(opts->eps >= 0.f) || !std::isfinite(opts->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be >= 0");
+  if (opts->flags != 0) return fail(GS_ERR_INVALID_ARG, "flags must be 0");
+  return GS_OK;
+}
+
+static int check_gaussians(const gs_gaussians_t *g) {
+  if (!g) return fail(GS_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+  if (g->n >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "n must be < 2^31");
+  if (g->n > 0 && (!g->mu || !g->log_scale || !g->quat || !g->amp))
+    return fail(GS_ERR_INVALID_ARG, "mu, log_scale, quat and amp are required");
+  return GS_OK;
+}
+
+static int check_common(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                        BrickGrid *bg, WsLayout *L) {
+  int rc;
+  if ((rc = check_gaussians(g)) || (rc = check_grid(grid)) || (rc = check_opts(opts))) return rc;
+  if (!bins || !bins->ws) return fail(GS_ERR_INVALID_ARG, "bins or bins->ws is NULL");
+  if (bins->key_capacity < 0 || bins->key_capacity > (int64_t)0xFFFFFFF0)
+    return fail(GS_ERR_INVALID_ARG, "key_capacity must be in [0, 2^32 - 16]");
+  make_brick_grid(grid, opts, bg);
+  if (bg->nbricks >= ((int64_t)1 << 32)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
+  *L = make_layout(g->n, *bg, bins->key_capacity);
+  if ((int64_t)kRadix * L->sort_blocks > (int64_t)kScanTile * 8192 || g->n + 1 > (int64_t)kScanTile * 8192)
+    return fail(GS_ERR_INVALID_ARG, "key capacity or n beyond the scan limit");
+  if (bins->ws_bytes < L->total)
+    return fail(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes given, %zu needed", bins->ws_bytes, L->total);
+  return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char *gs_last_error(void) { return g_last_error.c_str(); }
+
+int gs_brick_supported(int32_t bx, int32_t by, int32_t bz) { return brick_supported(bx, by, bz) ? 1 : 0; }
+
+int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, int64_t key_capacity, size_t *bytes) {
+  int rc;
+  if (n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+  if ((rc = check_grid(grid)) || (rc = check_opts(opts))) return rc;
+  if (!bytes) return fail(GS_ERR_INVALID_ARG, "bytes is NULL");
+  if (key_capacity < 0) return fail(GS_ERR_INVALID_ARG, "key_capacity must be >= 0");
+  BrickGrid bg;
+  make_brick_grid(grid, opts, &bg);
+  *bytes = make_layout(n, bg, key_capacity).total;
+  return GS_OK;
+}
+
+size_t gs_loss_scratch_bytes(int64_t nvox) { return sizeof(float) * (size_t)std::max(1, loss_blocks(nvox)); }
+
+static int bin_front(const gs_gaussians_t *g, const BrickGrid &bg, const gs_opts_t *opts, const gs_bins_t *bins,
+                     const WsLayout &L, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_reset_status(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "reset_status");
+  if ((e = launch_prep(*g, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep");
+  if ((e = launch_keygen(bg, opts->cutoff, false, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "keygen_count");
+  if ((e = launch_scan_counts(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "scan_counts");
+  return GS_OK;
+}
+
+int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                 void *stream, int64_t *n_keys) {
+  BrickGrid bg;
+  WsLayout L;
+  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  if (rc) return rc;
+  if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = bin_front(g, bg, opts, bins, L, s))) return rc;
+  DevStatus st;
+  hipError_t e = hipMemcpyAsync(&st, (char *)bins->ws + L.status, sizeof st, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gs_bin_query");
+  *n_keys = st.n_keys;
+  if (st.nonfinite) return fail(GS_ERR_NONFINITE, "non-finite parameter, zero quaternion or r <= 0");
+  return GS_OK;
+}
+
+int gs_bin(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+           void *stream) {
+  BrickGrid bg;
+  WsLayout L;
+  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = bin_front(g, bg, opts, bins, L, s))) return rc;
+  hipError_t e;
+  if ((e = launch_keygen(bg, opts->cutoff, true, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "keygen_emit");
+  if ((e = launch_sort(bg, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
+  return GS_OK;
+}
+
+int gs_render_fwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                  float *I, float *W, void *stream) {
+  BrickGrid bg;
+  WsLayout L;
+  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  if (rc) return rc;
+  if (!I) return fail(GS_ERR_INVALID_ARG, "I is NULL");
+  hipError_t e = launch_fwd(bg, opts->cutoff, opts->eps, bins->ws, L, I, W, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "render_fwd");
+}
+
+int gs_count_pairs(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                   int64_t *d_count, void *stream) {
+  BrickGrid bg;
+  WsLayout L;
+  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  if (rc) return rc;
+  if (!d_count) return fail(GS_ERR_INVALID_ARG, "d_count is NULL");
+  hipError_t e = launch_count_pairs(bg, opts->cutoff, bins->ws, L, d_count, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "count_pairs");
+}
+
+int gs_render_bwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                  const float *I, const float *W, const float *dL_dI, const gs_grads_t *grads, void *stream) {
+  BrickGrid bg;
+  WsLayout L;
+  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  if (rc) return rc;
+  if (!I || !W || !dL_dI || !grads) return fail(GS_ERR_INVALID_ARG, "I, W, dL_dI and grads are required");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_bwd(bg, opts->cutoff, opts->eps, bins->ws, L, I, W, dL_dI, s);
+  if (e != hipSuccess) return hip_fail(e, "render_bwd");
+  e = launch_reduce_chain(*g, bins->ws, L, *grads, s);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_chain");
+}
+
+int gs_loss_mse(const float *I, const float *T, int64_t nvox, float *dL_dI, float *loss, void *scratch,
+                size_t scratch_bytes, void *stream) {
+  if (nvox <= 0 || !I || !T || !dL_dI || !loss || !scratch)
+    return fail(GS_ERR_INVALID_ARG, "gs_loss_mse: null pointer or nvox <= 0");
+  if (scratch_bytes < gs_loss_scratch_bytes(nvox)) return fail(GS_ERR_INVALID_ARG, "gs_loss_mse: scratch too small");
+  hipError_t e = launch_loss_mse(I, T, nvox, dL_dI, loss, scratch, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "loss_mse");
+}
+
+int gs_loss_l1_zmean(const float *I, const float *obs, const gs_grid_t *hr, int32_t zdown, float *dL_dI, float *loss,
+                     void *scratch, size_t scratch_bytes, void *stream) {
+  int rc = check_grid(hr);
+  if (rc) return rc;
+  if (zdown <= 0 || hr->nz % zdown != 0) return fail(GS_ERR_INVALID_ARG, "nz must be a positive multiple of zdown");
+  if (!I || !obs || !dL_dI || !loss || !scratch) return fail(GS_ERR_INVALID_ARG, "gs_loss_l1_zmean: null pointer");
+  int64_t nlr = (int64_t)hr->nx * hr->ny * (hr->nz / zdown);
+  if (scratch_bytes < gs_loss_scratch_bytes(nlr)) return fail(GS_ERR_INVALID_ARG, "gs_loss_l1_zmean: scratch too small");
+  hipError_t e = launch_loss_l1z(I, obs, hr->nx, hr->ny, hr->nz, zdown, dL_dI, loss, scratch, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "loss_l1z");
+}
+
+static int check_state(const gs_fit_state_t *st, const gs_grads_t *gr) {
+  if (!st || !gr) return fail(GS_ERR_INVALID_ARG, "state or grads is NULL");
+  if (st->n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+  if (st->n > 0 && (!st->mu || !st->log_scale || !st->quat || !st->amp || !st->m || !st->v || !st->step))
+    return fail(GS_ERR_INVALID_ARG, "state arrays mu, log_scale, quat, amp, m, v, step are required");
+  if (st->n > 0 && (!gr->d_mu || !gr->d_log_scale || !gr->d_quat || !gr->d_amp))
+    return fail(GS_ERR_INVALID_ARG, "gradients d_mu, d_log_scale, d_quat, d_amp are required");
+  if (st->n > 0 && st->relax && !gr->d_relax) return fail(GS_ERR_INVALID_ARG, "d_relax is required when relax is set");
+  return GS_OK;
+}
+
+int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_adam_t *hp, const gs_bins_t *bins,
+                 void *stream) {
+  int rc = check_state(st, grads);
+  if (rc) return rc;
+  if (!hp) return fail(GS_ERR_INVALID_ARG, "hp is NULL");
+  const void *status = bins && bins->ws ? bins->ws : nullptr;  // status block is at offset 0
+  hipError_t e = launch_adam(*st, *grads, *hp, status, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "adam");
+}
+
+int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
+                const gs_fit_buffers_t *buf, void *stream) {
+  if (!fo || !buf || !lr_obs) return fail(GS_ERR_INVALID_ARG, "fit opts, buffers and lr_obs are required");
+  int rc = check_state(st, &buf->grads);
+  if (rc) return rc;
+  if (fo->loss != 0) return fail(GS_ERR_UNSUPPORTED, "only loss 0 (L1 on the z-mean) is supported");
+  gs_gaussians_t g{st->n, st->mu, st->log_scale, st->quat, st->amp, st->relax};
+  hipStream_t s = (hipStream_t)stream;
+  if (!buf->I || !buf->W || !buf->dL_dI || !buf->loss) return fail(GS_ERR_INVALID_ARG, "fit buffers incomplete");
+  if ((rc = gs_bin(&g, &fo->hr, &fo->opts, bins, stream))) return rc;
+  if ((rc = gs_render_fwd(&g, &fo->hr, &fo->opts, bins, buf->I, buf->W, stream))) return rc;
+  if ((rc = gs_loss_l1_zmean(buf->I, lr_obs, &fo->hr, fo->zdown, buf->dL_dI, buf->loss, buf->scratch,
+                             buf->scratch_bytes, stream)))
+    return rc;
+  if ((rc = gs_render_bwd(&g, &fo->hr, &fo->opts, bins, buf->I, buf->W, buf->dL_dI, &buf->grads, stream))) return rc;
+  hipError_t e = launch_adam(*st, buf->grads, fo->adam, bins->ws, s);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "adam");
+}
+
+int gs_status(const gs_bins_t *bins, void *stream, gs_status_t *out) {
+  if (!bins || !bins->ws || !out) return fail(GS_ERR_INVALID_ARG, "bins, bins->ws and out are required");
+  DevStatus st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(&st, bins->ws, sizeof st, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gs_status");
+  out->n_keys = st.n_keys;
+  out->overflow = st.overflow;
+  out->nonfinite = st.nonfinite;
+  if (st.overflow)
+    return fail(GS_ERR_CAPACITY, "%lld keys exceed the key capacity %lld", (long long)st.n_keys,
+                (long long)bins->key_capacity);
+  if (st.nonfinite) return fail(GS_ERR_NONFINITE, "non-finite parameter, zero quaternion or r <= 0");
+  return GS_OK;
+}
+
+int gs_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return GS_OK;
+}
+
+int gs_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof_pending) {
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_pending.clear();
+  g_prof_acc.clear();
+  return GS_OK;
+}
+
+int gs_profile_read(void *stream, int cap, char (*names)[48], int64_t *launches, double *total_ms, int *n_out) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gs_profile_read");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      bool found = false;
+      for (auto &a : g_prof_acc)
+        if (a.first == r.name) {
+          a.second.first += 1;
+          a.second.second += ms;
+          found = true;
+        }
+      if (!found) g_prof_acc.push_back({r.name, {1, (double)ms}});
+    }
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_pending.clear();
+  int k = 0;
+  for (auto &a : g_prof_acc) {
+    if (k >= cap) break;
+    if (names) {
+      std::strncpy(names[k], a.first.c_str(), 47);
+      names[k][47] = 0;
+    }
+    if (launches) launches[k] = a.second.first;
+    if (total_ms) total_ms[k] = a.second.second;
+    ++k;
+  }
+  if (n_out) *n_out = k;
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal declarations of the gfx950 rasterizer library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs.h"
+
+namespace gs {
+
+// log2(e) and the exponent scale: w = r exp(-d^2/2) = exp2(q + log2 r) with q = -1/2 log2(e) d^2.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kHalfLog2e = 0.7213475204444817f;
+
+// Per-Gaussian evaluation record (48 B), written by the prep kernel and staged through LDS by the
+// forward and backward kernels:
+//   r0 = (mu_x, mu_y, mu_z, A)
+//   r1 = (Q_xx, Q_yy, Q_zz, log2 r)             Q = -1/2 log2(e) Sigma^{-1}
+//   r2 = (2 Q_xy, 2 Q_xz, 2 Q_yz, 1 / r)
+// so that q(p) = delta^T Q delta (delta = p - mu), the pair is kept iff q >= -1/2 log2(e) cutoff^2,
+// and w = exp2(q + log2 r).
+struct __align__(16) EvalRec {
+  float4 r0, r1, r2;
+};
+
+// Per-Gaussian culling record (32 B): covariance entries and a validity flag.
+//   c0 = (S_xx, S_yy, S_zz, S_xy), c1 = (S_xz, S_yz, valid ? 1 : 0, 0)
+struct __align__(16) CullRec {
+  float4 c0, c1;
+};
+
+// Device status block at offset 0 of every workspace (layout of gs_status_t + spare).
+struct DevStatus {
+  int64_t n_keys;
+  int32_t overflow;
+  int32_t nonfinite;
+  int32_t spare[12];
+};
+
+// Brick grid geometry.
+struct BrickGrid {
+  int nx, ny, nz;    // voxels
+  int bx, by, bz;    // brick shape
+  int nbx, nby, nbz; // bricks per axis
+  int64_t nbricks;
+  float ox, oy, oz;  // origin
+  float hx, hy, hz;  // spacing
+};
+
+// Radix sort tiling.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Scan tiling (exclusive scan of uint32 arrays).
+constexpr int kScanThreads = 512;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
+struct WsLayout {
+  int64_t n = 0, cap = 0, nbricks = 0;
+  int sort_blocks = 0;  // blocks per radix pass (covers cap keys)
+  int sort_passes = 0;  // ceil(bits(nbricks) / 8)
+  size_t status = 0, evalrec = 0, cullrec = 0, off = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
+         vals_b = 0, sorted_gid = 0, brick_off = 0, hist = 0, scan_tmp = 0, partials = 0, sorted_slot = 0, total = 0;
+};
+
+// Host-side helpers (api.cpp).
+bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg);
+WsLayout make_layout(int64_t n, const BrickGrid &bg, int64_t cap);
+
+// Launch bookkeeping for the optional kernel timing (api.cpp).
+void prof_begin(hipStream_t s);
+void prof_end(hipStream_t s, const char *name);
+
+// Kernel launchers (bin.hip, render.hip, fit.hip).  Return hipGetLastError() of the launches.
+hipError_t launch_reset_status(void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_prep(const gs_gaussians_t &g, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_keygen(const BrickGrid &bg, float cutoff, bool emit, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_sort(const BrickGrid &bg, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_fwd(const BrickGrid &bg, float cutoff, float eps, const void *ws, const WsLayout &L, float *I,
+                      float *W, hipStream_t s);
+hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws, const WsLayout &L, int64_t *d_count,
+                              hipStream_t s);
+hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
+                      const float *W, const float *dLdI, hipStream_t s);
+hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
+                               hipStream_t s);
+hipError_t launch_loss_mse(const float *I, const float *T, int64_t nvox, float *g, float *loss, void *scratch,
+                           hipStream_t s);
+hipError_t launch_loss_l1z(const float *I, const float *obs, int nx, int ny, int nz, int f, float *g, float *loss,
+                           void *scratch, hipStream_t s);
+hipError_t launch_adam(const gs_fit_state_t &st, const gs_grads_t &gr, const gs_adam_t &hp, const void *ws_status,
+                       hipStream_t s);
+
+// Loss reduction tiling.
+constexpr int kLossThreads = 256;
+constexpr int kLossItems = 16;
+int loss_blocks(int64_t nvox);
+
+}  // namespace gs

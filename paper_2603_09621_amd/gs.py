@@ -1,0 +1,450 @@
+"""Python binding of libgs.so (include/gs.h): ctypes marshalling of torch device tensors.
+
+Every computation runs in the library's HIP kernels; this module only builds the C structs, takes
+device pointers from torch tensors and passes torch's current HIP stream.  Importing it fails
+loudly if the library has not been built (there is no fallback path).
+
+The ``gs_*`` functions mirror the C entry points one to one.  ``Bins``, ``render``, ``backward``
+and ``FitState`` are conveniences that size and allocate the caller-owned buffers with torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_2603_09621_amd/build.py`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_NONFINITE, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+_ERR_NAMES = {-1: "INVALID_ARG", -2: "CAPACITY", -3: "NONFINITE", -4: "HIP", -5: "UNSUPPORTED"}
+
+
+class GSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"GS_ERR_{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CapacityError(GSError):
+    pass
+
+
+_vp = ctypes.c_void_p
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+class gs_gaussians_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mu", _vp), ("log_scale", _vp), ("quat", _vp), ("amp", _vp), ("relax", _vp)]
+
+
+class gs_grid_t(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3)]
+
+
+class gs_opts_t(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32), ("cutoff", ctypes.c_float),
+                ("eps", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class gs_bins_t(ctypes.Structure):
+    _fields_ = [("ws", _vp), ("ws_bytes", ctypes.c_size_t), ("key_capacity", ctypes.c_int64)]
+
+
+class gs_grads_t(ctypes.Structure):
+    _fields_ = [("d_mu", _vp), ("d_log_scale", _vp), ("d_quat", _vp), ("d_amp", _vp), ("d_relax", _vp)]
+
+
+class gs_adam_t(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 5), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class gs_fit_state_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mu", _vp), ("log_scale", _vp), ("quat", _vp), ("amp", _vp), ("relax", _vp),
+                ("m", _vp), ("v", _vp), ("step", _vp)]
+
+
+class gs_fit_opts_t(ctypes.Structure):
+    _fields_ = [("hr", gs_grid_t), ("opts", gs_opts_t), ("zdown", ctypes.c_int32), ("loss", ctypes.c_int32),
+                ("adam", gs_adam_t)]
+
+
+class gs_fit_buffers_t(ctypes.Structure):
+    _fields_ = [("I", _vp), ("W", _vp), ("dL_dI", _vp), ("grads", gs_grads_t), ("scratch", _vp),
+                ("scratch_bytes", ctypes.c_size_t), ("loss", _vp)]
+
+
+class gs_status_t(ctypes.Structure):
+    _fields_ = [("n_keys", ctypes.c_int64), ("overflow", ctypes.c_int32), ("nonfinite", ctypes.c_int32)]
+
+
+_P = ctypes.POINTER
+_sigs = {
+    "gs_workspace_size": [ctypes.c_int64, _P(gs_grid_t), _P(gs_opts_t), ctypes.c_int64, _P(ctypes.c_size_t)],
+    "gs_brick_supported": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "gs_bin_query": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _P(ctypes.c_int64)],
+    "gs_bin": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp],
+    "gs_render_fwd": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp, _vp],
+    "gs_count_pairs": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp],
+    "gs_render_bwd": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp, _vp,
+                      _P(gs_grads_t), _vp],
+    "gs_loss_mse": [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_size_t, _vp],
+    "gs_loss_l1_zmean": [_vp, _vp, _P(gs_grid_t), ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp],
+    "gs_adam_step": [_P(gs_fit_state_t), _P(gs_grads_t), _P(gs_adam_t), _P(gs_bins_t), _vp],
+    "gs_fit_step": [_P(gs_fit_state_t), _vp, _P(gs_fit_opts_t), _P(gs_bins_t), _P(gs_fit_buffers_t), _vp],
+    "gs_status": [_P(gs_bins_t), _vp, _P(gs_status_t)],
+    "gs_profile_enable": [ctypes.c_int],
+    "gs_profile_reset": [],
+    "gs_profile_read": [_vp, ctypes.c_int, _vp, _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_int)],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.gs_loss_scratch_bytes.argtypes = [ctypes.c_int64]
+_lib.gs_loss_scratch_bytes.restype = ctypes.c_size_t
+_lib.gs_last_error.argtypes = []
+_lib.gs_last_error.restype = ctypes.c_char_p
+
+EXPORTED = tuple(_sigs) + ("gs_loss_scratch_bytes", "gs_last_error")
+
+
+def gs_last_error() -> str:
+    return _lib.gs_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != GS_OK:
+        msg = gs_last_error()
+        if rc == GS_ERR_CAPACITY:
+            raise CapacityError(rc, msg)
+        raise GSError(rc, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(t: Optional[torch.Tensor]) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    if t.dtype != torch.float32:
+        raise ValueError(f"float32 tensor expected, got {t.dtype}")
+    return t
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------------------------------------
+# Plain-data descriptions
+
+
+@dataclass
+class Grid:
+    nx: int
+    ny: int
+    nz: int
+    origin: Sequence[float] = (0.5, 0.5, 0.5)
+    spacing: Sequence[float] = (1.0, 1.0, 1.0)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def size(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def c(self) -> gs_grid_t:
+        return gs_grid_t(self.nx, self.ny, self.nz, (ctypes.c_float * 3)(*self.origin),
+                         (ctypes.c_float * 3)(*self.spacing))
+
+    @staticmethod
+    def at_scale(lr_dims, scale: float) -> "Grid":
+        """Grid of round(scale * dims) voxels covering the same extent as an LR grid of unit spacing
+        and origin 0.5 (cell-centred; rendering at an arbitrary scale)."""
+        nx, ny, nz = (int(round(scale * d)) for d in lr_dims)
+        sp = tuple(d / n for d, n in zip(lr_dims, (nx, ny, nz)))
+        return Grid(nx, ny, nz, tuple(0.5 * s for s in sp), sp)
+
+
+@dataclass
+class Opts:
+    bx: int = 8
+    by: int = 8
+    bz: int = 4
+    cutoff: float = 3.0
+    eps: float = 1e-8
+
+    def c(self) -> gs_opts_t:
+        return gs_opts_t(self.bx, self.by, self.bz, self.cutoff, self.eps, 0)
+
+
+GROUPS = ("mu", "log_scale", "quat", "amp", "relax")
+
+
+@dataclass
+class Gaussians:
+    """Device tensors of one Gaussian set (float32, contiguous)."""
+
+    mu: torch.Tensor
+    log_scale: torch.Tensor
+    quat: torch.Tensor
+    amp: torch.Tensor
+    relax: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.amp.shape[0])
+
+    @staticmethod
+    def from_numpy(p: dict, device="cuda") -> "Gaussians":
+        def t(k):
+            v = p.get(k)
+            return None if v is None else torch.as_tensor(v, dtype=torch.float32).contiguous().to(device)
+
+        return Gaussians(t("mu"), t("log_scale"), t("quat"), t("amp"), t("relax"))
+
+    def c(self) -> gs_gaussians_t:
+        return gs_gaussians_t(self.n, _ptr(_f32(self.mu)), _ptr(_f32(self.log_scale)), _ptr(_f32(self.quat)),
+                              _ptr(_f32(self.amp)), _ptr(_f32(self.relax)))
+
+
+def brick_supported(bx: int, by: int, bz: int) -> bool:
+    return bool(_lib.gs_brick_supported(bx, by, bz))
+
+
+def gs_workspace_size(n: int, grid: Grid, opts: Opts, key_capacity: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.gs_workspace_size(n, ctypes.byref(grid.c()), ctypes.byref(opts.c()), key_capacity,
+                                  ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_loss_scratch_bytes(nvox: int) -> int:
+    return int(_lib.gs_loss_scratch_bytes(nvox))
+
+
+class Bins:
+    """Caller-owned binning workspace (a uint8 device tensor) for one Gaussian count and grid."""
+
+    def __init__(self, n: int, grid: Grid, opts: Opts, key_capacity: int, device="cuda"):
+        self.n, self.grid, self.opts, self.key_capacity = n, grid, opts, int(key_capacity)
+        self.ws_bytes = gs_workspace_size(n, grid, opts, self.key_capacity)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def c(self) -> gs_bins_t:
+        return gs_bins_t(ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.key_capacity)
+
+
+def gs_bin_query(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    _check(_lib.gs_bin_query(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
+                             ctypes.byref(bins.c()), _stream(stream), ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_bin(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, stream=None) -> None:
+    _check(_lib.gs_bin(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()), ctypes.byref(bins.c()),
+                       _stream(stream)))
+
+
+def gs_render_fwd(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, I: torch.Tensor, W: Optional[torch.Tensor] = None,
+                  stream=None) -> None:
+    _check(_lib.gs_render_fwd(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
+                              ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _stream(stream)))
+
+
+def gs_count_pairs(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, out: torch.Tensor, stream=None) -> None:
+    if out.dtype != torch.int64:
+        raise ValueError("int64 tensor expected")
+    _check(_lib.gs_count_pairs(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
+                               ctypes.byref(bins.c()), _ptr(out), _stream(stream)))
+
+
+@dataclass
+class Grads:
+    mu: torch.Tensor
+    log_scale: torch.Tensor
+    quat: torch.Tensor
+    amp: torch.Tensor
+    relax: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def empty(n: int, relax: bool = True, device="cuda") -> "Grads":
+        z = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)  # noqa: E731
+        return Grads(z(n, 3), z(n, 3), z(n, 4), z(n), z(n) if relax else None)
+
+    def c(self) -> gs_grads_t:
+        return gs_grads_t(_ptr(self.mu), _ptr(self.log_scale), _ptr(self.quat), _ptr(self.amp), _ptr(self.relax))
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k in GROUPS}
+
+
+def gs_render_bwd(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, I: torch.Tensor, W: torch.Tensor,
+                  dL_dI: torch.Tensor, grads: Grads, stream=None) -> None:
+    _check(_lib.gs_render_bwd(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
+                              ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _ptr(_f32(dL_dI)),
+                              ctypes.byref(grads.c()), _stream(stream)))
+
+
+def gs_loss_mse(I: torch.Tensor, T: torch.Tensor, dL_dI: torch.Tensor, loss: torch.Tensor, scratch: torch.Tensor,
+                stream=None) -> None:
+    _check(_lib.gs_loss_mse(_ptr(_f32(I)), _ptr(_f32(T)), I.numel(), _ptr(_f32(dL_dI)), _ptr(_f32(loss)),
+                            _ptr(scratch), scratch.numel() * scratch.element_size(), _stream(stream)))
+
+
+def gs_loss_l1_zmean(I: torch.Tensor, obs: torch.Tensor, grid: Grid, zdown: int, dL_dI: torch.Tensor,
+                     loss: torch.Tensor, scratch: torch.Tensor, stream=None) -> None:
+    _check(_lib.gs_loss_l1_zmean(_ptr(_f32(I)), _ptr(_f32(obs)), ctypes.byref(grid.c()), zdown, _ptr(_f32(dL_dI)),
+                                 _ptr(_f32(loss)), _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                 _stream(stream)))
+
+
+def gs_status(bins: Bins, stream=None, raise_on_error: bool = True):
+    st = gs_status_t()
+    rc = _lib.gs_status(ctypes.byref(bins.c()), _stream(stream), ctypes.byref(st))
+    if raise_on_error:
+        _check(rc)
+    return {"rc": rc, "n_keys": int(st.n_keys), "overflow": int(st.overflow), "nonfinite": int(st.nonfinite)}
+
+
+# ------------------------------------------------------------------------------------------------
+# Profiling
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.gs_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    _check(_lib.gs_profile_reset())
+
+
+def profile_read(stream=None) -> dict:
+    cap = 64
+    names = (ctypes.c_char * 48 * cap)()
+    launches = (ctypes.c_int64 * cap)()
+    total = (ctypes.c_double * cap)()
+    n = ctypes.c_int(0)
+    _check(_lib.gs_profile_read(_stream(stream), cap, ctypes.cast(names, _vp), launches, total, ctypes.byref(n)))
+    out = {}
+    for i in range(n.value):
+        out[bytes(names[i]).split(b"\0", 1)[0].decode()] = (int(launches[i]), float(total[i]))
+    return out
+
+
+# ------------------------------------------------------------------------------------------------
+# Conveniences
+
+
+def plan_bins(g: Gaussians, grid: Grid, opts: Opts, headroom: float = 1.25, min_capacity: int = 1024,
+              stream=None) -> Bins:
+    """Workspace with room for the exact key count of ``g`` times ``headroom`` (one synchronising
+    count pass)."""
+    probe = Bins(g.n, grid, opts, 0, device=g.amp.device if g.n else "cuda")
+    k = gs_bin_query(g, grid, opts, probe, stream)
+    return Bins(g.n, grid, opts, max(min_capacity, int(math.ceil(k * headroom))), device=probe.ws.device)
+
+
+def render(g: Gaussians, grid: Grid, opts: Optional[Opts] = None, bins: Optional[Bins] = None, want_w: bool = True,
+           stream=None):
+    """Bin + forward.  Returns (I, W, bins) with I, W float32 [nz, ny, nx] (W None if not wanted)."""
+    opts = opts or Opts()
+    if bins is None:
+        bins = plan_bins(g, grid, opts, stream=stream)
+    dev = bins.ws.device
+    I = torch.empty(grid.shape, dtype=torch.float32, device=dev)
+    W = torch.empty(grid.shape, dtype=torch.float32, device=dev) if want_w else None
+    gs_bin(g, grid, opts, bins, stream)
+    gs_render_fwd(g, grid, opts, bins, I, W, stream)
+    return I, W, bins
+
+
+def backward(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, I, W, dL_dI, stream=None) -> Grads:
+    grads = Grads.empty(g.n, relax=g.relax is not None, device=bins.ws.device)
+    gs_render_bwd(g, grid, opts, bins, I, W, dL_dI, grads, stream)
+    return grads
+
+
+@dataclass
+class Adam:
+    lr: Sequence[float] = (1e-2, 5e-3, 1e-3, 1e-2, 0.0)
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self) -> gs_adam_t:
+        return gs_adam_t((ctypes.c_float * 5)(*self.lr), self.beta1, self.beta2, self.eps)
+
+
+class FitState:
+    """Parameters (updated in place), Adam moments and the device step counter of one fit."""
+
+    def __init__(self, g: Gaussians):
+        self.g = g
+        n = g.n
+        dev = g.amp.device
+        self.m = torch.zeros(12 * n, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(12 * n, dtype=torch.float32, device=dev)
+        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def c(self) -> gs_fit_state_t:
+        g = self.g
+        return gs_fit_state_t(g.n, _ptr(g.mu), _ptr(g.log_scale), _ptr(g.quat), _ptr(g.amp), _ptr(g.relax),
+                              _ptr(self.m), _ptr(self.v), _ptr(self.step))
+
+
+def gs_adam_step(st: FitState, grads: Grads, hp: Adam, bins: Optional[Bins] = None, stream=None) -> None:
+    _check(_lib.gs_adam_step(ctypes.byref(st.c()), ctypes.byref(grads.c()), ctypes.byref(hp.c()),
+                             ctypes.byref(bins.c()) if bins is not None else None, _stream(stream)))
+
+
+class FitBuffers:
+    def __init__(self, n: int, grid: Grid, relax: bool, device="cuda"):
+        f = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)  # noqa: E731
+        self.I, self.W, self.dL_dI = f(grid.shape), f(grid.shape), f(grid.shape)
+        self.grads = Grads.empty(n, relax, device)
+        self.scratch = torch.empty(gs_loss_scratch_bytes(grid.size), dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def c(self) -> gs_fit_buffers_t:
+        return gs_fit_buffers_t(_ptr(self.I), _ptr(self.W), _ptr(self.dL_dI), self.grads.c(), _ptr(self.scratch),
+                                self.scratch.numel(), _ptr(self.loss))
+
+
+@dataclass
+class FitOpts:
+    grid: Grid
+    opts: Opts = field(default_factory=Opts)
+    zdown: int = 4
+    adam: Adam = field(default_factory=Adam)
+
+    def c(self) -> gs_fit_opts_t:
+        return gs_fit_opts_t(self.grid.c(), self.opts.c(), self.zdown, 0, self.adam.c())
+
+
+def gs_fit_step(st: FitState, lr_obs: torch.Tensor, fo: FitOpts, bins: Bins, buf: FitBuffers, stream=None) -> None:
+    _check(_lib.gs_fit_step(ctypes.byref(st.c()), _ptr(_f32(lr_obs)), ctypes.byref(fo.c()), ctypes.byref(bins.c()),
+                            ctypes.byref(buf.c()), _stream(stream)))

@@ -15,10 +15,10 @@ import oracle
 from paper_2603_09621_amd import synth
 
 # |d^2 - 9| band treated as ambiguous between FP32 and FP64 (d^2 units).
-BAND = 2e-3
+BAND = 1e-3
 
 
-def condition(p: dict, grid: oracle.Grid, seed: int = 12345, band: float = BAND, jitter=None, max_rounds: int = 60):
+def condition(p: dict, grid: oracle.Grid, seed: int = 12345, band: float = BAND, jitter=None, max_rounds: int = 400):
     """Redraw the positions of Gaussians with ambiguous pairs until none is left."""
     dims = (grid.nx, grid.ny, grid.nz)
     amb = oracle.ambiguous(p, grid, band)

@@ -1,0 +1,285 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, element by element.
+
+Inputs are seeded and conditioned boundary-clean (no pair within the FP32/FP64 ambiguity band of
+the 3-sigma cutoff).  Forward: |x - y| <= 1e-5 |y| + 1e-7.  Gradients: |x - y| <= 1e-4 |y| +
+1e-4 rms(y) per array.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_09621_amd import synth
+from tests import cases
+from tests.gpu_util import (assert_fwd_close, assert_grad_close, gpu_grads, gpu_render, gs_mod, np64, rel_l2, say,
+                            to_grid)
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (seed, dims, n, ls_std, max_ratio)
+    "tiny_ragged": (101, (20, 18, 12), 60, 0.3, None),
+    "aniso": (102, (40, 36, 20), 400, 0.8, 8.0),
+    "dense": (103, (24, 24, 16), 1500, 0.3, None),
+    "big_sigma": (104, (48, 40, 24), 40, 0.5, None),
+}
+
+
+def _case(name):
+    seed, dims, n, std, ratio = CASES[name]
+    kw = {"ls_mean": math.log(4.0)} if name == "big_sigma" else {}
+    p, grid = cases.small_case(seed, dims=dims, n=n, ls_std=std, max_ratio=ratio, **kw)
+    p["relax"] = np.random.default_rng(seed).uniform(0.3, 1.0, n).astype(np.float32)
+    return p, grid
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_matches_oracle(name):
+    p, grid = _case(name)
+    say("forward", name, grid.shape, p["amp"].shape[0])
+    _, _, _, _, I, W = gpu_render(p, grid)
+    Io, Wo, _ = oracle.render(p, grid)
+    assert_fwd_close(np64(W), Wo, f"{name} W")
+    assert_fwd_close(np64(I), Io, f"{name} I")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_matches_oracle(name):
+    p, grid = _case(name)
+    say("backward", name)
+    g, ggrid, opts, bins, I, W = gpu_render(p, grid)
+    T = synth.uniform_volume(7, (grid.nx, grid.ny, grid.nz))
+    # stage-wise: both sides take the oracle's forward and the MSE adjoint (rounded to FP32)
+    Io, Wo, _ = oracle.render(p, grid)
+    _, go = oracle.mse_loss(Io, T)
+    I32, W32, g32 = (x.astype(np.float32) for x in (Io, Wo, go))
+    d = torch.device("cuda")
+    gg = gpu_grads(g, ggrid, opts, bins, torch.from_numpy(I32).to(d), torch.from_numpy(W32).to(d),
+                   torch.from_numpy(g32).to(d))
+    ref = oracle.grad(p, grid, I32.astype(np.float64), W32.astype(np.float64), g32.astype(np.float64))
+    for k in oracle.GROUPS:
+        assert_grad_close(gg[k], ref[k], f"{name} d_{k}")
+        say(f"  d_{k} rel_l2 {rel_l2(gg[k], ref[k]):.2e}")
+
+
+def test_end_to_end_mse_gradient():
+    """GPU forward -> GPU MSE loss -> GPU backward against the oracle's FP64 pipeline."""
+    gs = gs_mod()
+    p, grid = _case("dense")
+    say("end-to-end mse")
+    g, ggrid, opts, bins, I, W = gpu_render(p, grid)
+    T = synth.uniform_volume(8, (grid.nx, grid.ny, grid.nz))
+    Tt = torch.from_numpy(T).cuda()
+    gI = torch.empty_like(I)
+    loss = torch.zeros(1, device="cuda")
+    scratch = torch.empty(gs.gs_loss_scratch_bytes(grid.size), dtype=torch.uint8, device="cuda")
+    gs.gs_loss_mse(I, Tt, gI, loss, scratch)
+    gg = gpu_grads(g, ggrid, opts, bins, I, W, gI)
+    Io, Wo, _ = oracle.render(p, grid)
+    Lo, go = oracle.mse_loss(Io, T)
+    assert float(loss.item()) == pytest.approx(Lo, rel=1e-5)
+    ref = oracle.grad(p, grid, Io, Wo, go)
+    for k in oracle.GROUPS:
+        assert_grad_close(gg[k], ref[k], f"e2e d_{k}")
+
+
+def test_plain_workload_forward_and_backward():
+    """The plain render + gradient workload: 64x64x32, 20k Gaussians, MSE vs U(0,1) target."""
+    gs = gs_mod()
+    p, T, grid = cases.plain_case()
+    say("plain workload", grid.shape, p["amp"].shape[0])
+    g, ggrid, opts, bins, I, W = gpu_render(p, grid)
+    Io, Wo, _ = oracle.render(p, grid)
+    assert_fwd_close(np64(W), Wo, "plain W")
+    assert_fwd_close(np64(I), Io, "plain I")
+    gI = torch.empty_like(I)
+    loss = torch.zeros(1, device="cuda")
+    scratch = torch.empty(gs.gs_loss_scratch_bytes(grid.size), dtype=torch.uint8, device="cuda")
+    gs.gs_loss_mse(I, torch.from_numpy(T).cuda(), gI, loss, scratch)
+    gg = gpu_grads(g, ggrid, opts, bins, I, W, gI)
+    Lo, go = oracle.mse_loss(Io, T)
+    ref = oracle.grad(p, grid, Io, Wo, go)
+    for k in ("mu", "log_scale", "quat", "amp"):
+        assert_grad_close(gg[k], ref[k], f"plain d_{k}")
+        say(f"  d_{k} rel_l2 {rel_l2(gg[k], ref[k]):.2e}")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gs.gs_count_pairs(g, ggrid, opts, bins, cnt)
+    assert int(cnt.item()) == oracle.count_pairs(p, grid)
+
+
+def test_arbitrary_scale_grid():
+    """Render the same Gaussians on a finer grid with non-unit spacing and origin (§4.2)."""
+    gs = gs_mod()
+    p, grid = _case("tiny_ragged")
+    fine = gs.Grid.at_scale((grid.nx, grid.ny, grid.nz), 2.5)
+    og = oracle.Grid(fine.nx, fine.ny, fine.nz, fine.origin, fine.spacing)
+    p = cases.condition(p, og, seed=5)
+    say("arbitrary scale", og.shape)
+    _, _, _, _, I, W = gpu_render(p, og)
+    Io, Wo, _ = oracle.render(p, og)
+    assert_fwd_close(np64(W), Wo, "scaled W")
+    assert_fwd_close(np64(I), Io, "scaled I")
+
+
+def test_deterministic_and_order_independent():
+    p, grid = _case("dense")
+    say("determinism")
+    outs = [np64(gpu_render(p, grid)[4]) for _ in range(2)]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    perm = np.random.default_rng(0).permutation(p["amp"].shape[0])
+    pp = {k: v[perm] for k, v in p.items()}
+    Ip = np64(gpu_render(pp, grid)[4])
+    assert_fwd_close(Ip, outs[0], "permuted")
+
+
+def test_empty_and_degenerate_inputs():
+    gs = gs_mod()
+    grid = oracle.Grid(9, 10, 7)
+    say("empty set")
+    empty = {k: v[:0] for k, v in synth.gaussians_uniform(1, 1, (9, 10, 7)).items()}
+    _, _, _, bins, I, W = gpu_render(empty, grid)
+    assert np.all(np64(I) == 0) and np.all(np64(W) == 0)
+    say("gaussians outside the grid")
+    far = synth.gaussians_uniform(2, 30, (9, 10, 7))
+    far["mu"] = far["mu"] + np.float32(100.0)
+    _, _, _, bins, I, W = gpu_render(far, grid)
+    assert np.all(np64(W) == 0)
+    say("single gaussian")
+    one = {k: v[:1] for k, v in cases.small_case(3, dims=(9, 10, 7), n=5)[0].items()}
+    _, _, _, _, I, W = gpu_render(one, grid)
+    Io, Wo, _ = oracle.render(one, grid)
+    assert_fwd_close(np64(W), Wo, "single W")
+
+
+def test_nonfinite_input_is_reported():
+    gs = gs_mod()
+    p, grid = _case("tiny_ragged")
+    p["quat"][5] = 0.0
+    p["log_scale"][7, 1] = np.nan
+    say("nonfinite")
+    g = gs.Gaussians.from_numpy(p)
+    ggrid, opts = to_grid(grid), gs.Opts()
+    with pytest.raises(gs.GSError) as e:
+        gs.plan_bins(g, ggrid, opts)
+    assert e.value.code == gs.GS_ERR_NONFINITE
+    # the remaining Gaussians still render exactly as the oracle does without the bad ones
+    bins = gs.Bins(g.n, ggrid, opts, 100000)
+    I = torch.empty(grid.shape, device="cuda")
+    W = torch.empty(grid.shape, device="cuda")
+    gs.gs_bin(g, ggrid, opts, bins)
+    gs.gs_render_fwd(g, ggrid, opts, bins, I, W)
+    st = gs.gs_status(bins, raise_on_error=False)
+    assert st["rc"] == gs.GS_ERR_NONFINITE and st["nonfinite"] == 1
+    keep = np.setdiff1d(np.arange(p["amp"].shape[0]), [5, 7])
+    Io, Wo, _ = oracle.render({k: v[keep] for k, v in p.items()}, grid)
+    assert_fwd_close(np64(W), Wo, "W without bad")
+
+
+def test_capacity_overflow_is_reported_and_outputs_untouched():
+    gs = gs_mod()
+    p, grid = _case("dense")
+    say("overflow")
+    g = gs.Gaussians.from_numpy(p)
+    ggrid, opts = to_grid(grid), gs.Opts()
+    bins = gs.Bins(g.n, ggrid, opts, 100)
+    I = torch.full(grid.shape, -7.0, device="cuda")
+    gs.gs_bin(g, ggrid, opts, bins)
+    gs.gs_render_fwd(g, ggrid, opts, bins, I, None)
+    with pytest.raises(gs.CapacityError):
+        gs.gs_status(bins)
+    st = gs.gs_status(bins, raise_on_error=False)
+    assert st["overflow"] == 1 and st["n_keys"] > 100
+    assert torch.all(I == -7.0)
+    # retry with the reported count succeeds
+    bins2 = gs.Bins(g.n, ggrid, opts, st["n_keys"])
+    gs.gs_bin(g, ggrid, opts, bins2)
+    gs.gs_render_fwd(g, ggrid, opts, bins2, I, None)
+    assert gs.gs_status(bins2)["n_keys"] == st["n_keys"]
+    Io, _, _ = oracle.render(p, grid)
+    assert_fwd_close(np64(I), Io, "after retry")
+
+
+def test_losses_match_oracle():
+    gs = gs_mod()
+    rng = np.random.default_rng(4)
+    grid = gs.Grid(24, 20, 16)
+    I = rng.random(grid.shape, dtype=np.float32)
+    T = rng.random(grid.shape, dtype=np.float32)
+    O = rng.random((4, 20, 24), dtype=np.float32)
+    O[0, 0, :3] = I.reshape(4, 4, 20, 24)[0, :, 0, :3].astype(np.float32).sum(0) * np.float32(0.25)  # exact ties
+    say("losses")
+    d = torch.device("cuda")
+    It, Tt, Ot = (torch.from_numpy(x).to(d) for x in (I, T, O))
+    g = torch.empty_like(It)
+    loss = torch.zeros(1, device=d)
+    scratch = torch.empty(gs.gs_loss_scratch_bytes(grid.size), dtype=torch.uint8, device=d)
+    gs.gs_loss_mse(It, Tt, g, loss, scratch)
+    L, go = oracle.mse_loss(I, T)
+    assert float(loss.item()) == pytest.approx(L, rel=1e-5)
+    assert_fwd_close(np64(g), go, "mse grad")
+    gs.gs_loss_l1_zmean(It, Ot, grid, 4, g, loss, scratch)
+    L1, g1 = oracle.fit_l1_loss(I, O)
+    assert float(loss.item()) == pytest.approx(L1, rel=1e-5)
+    np.testing.assert_allclose(np64(g), g1, rtol=1e-6, atol=0)
+
+
+def test_adam_matches_oracle():
+    gs = gs_mod()
+    p, grid = _case("tiny_ragged")
+    n = p["amp"].shape[0]
+    say("adam")
+    g = gs.Gaussians.from_numpy(p)
+    st = gs.FitState(g)
+    hp = gs.Adam(lr=(1e-2, 5e-3, 1e-3, 1e-2, 2e-3))
+    rng = np.random.default_rng(9)
+    cur = {k: p[k].astype(np.float64) for k in oracle.GROUPS}
+    m = {k: np.zeros_like(v) for k, v in cur.items()}
+    v = {k: np.zeros_like(vv) for k, vv in cur.items()}
+    lr = dict(zip(oracle.GROUPS, [float(np.float32(x)) for x in hp.lr]))
+    for step in range(1, 4):
+        grads_np = {k: rng.standard_normal(p[k].shape).astype(np.float32) for k in oracle.GROUPS}
+        gr = gs.Grads(*[torch.from_numpy(grads_np[k]).cuda() for k in oracle.GROUPS])
+        gs.gs_adam_step(st, gr, hp)
+        cur, m, v = oracle.adam_step(cur, grads_np, m, v, step, lr, float(np.float32(0.9)), float(np.float32(0.999)),
+                                     float(np.float32(1e-8)))
+        for k in oracle.GROUPS:
+            np.testing.assert_allclose(np64(getattr(g, k)), cur[k], rtol=2e-6, atol=2e-6 * lr[k], err_msg=k)
+    assert int(st.step.item()) == 3
+    assert n == 60
+
+
+def test_fit_step_matches_oracle():
+    """One full fit step (bin, render, z-mean L1, backward, Adam) against the oracle's FP64 step."""
+    gs = gs_mod()
+    dims = (32, 32, 16)
+    hr = synth.phantom(21, dims)
+    lr_obs = synth.zmean_observation(hr)
+    p = synth.lattice_init(22, lr_obs, 900)
+    grid = oracle.Grid(*dims)
+    p = cases.condition(p, grid, seed=23, jitter=(0.5, 0.5, 1.0))
+    say("fit step", grid.shape, p["amp"].shape[0])
+    g = gs.Gaussians.from_numpy(p)
+    ggrid = to_grid(grid)
+    fo = gs.FitOpts(ggrid)
+    bins = gs.plan_bins(g, ggrid, fo.opts, headroom=1.5)
+    st = gs.FitState(g)
+    buf = gs.FitBuffers(g.n, ggrid, relax=True)
+    obs_t = torch.from_numpy(lr_obs).cuda()
+    gs.gs_fit_step(st, obs_t, fo, bins, buf)
+    gs.gs_status(bins)
+    lr = dict(zip(oracle.GROUPS, [float(np.float32(x)) for x in fo.adam.lr]))
+    m0 = {k: np.zeros(np.shape(p[k])) for k in oracle.GROUPS}
+    L, newp, _, _, gr = oracle.fit_step(p, lr_obs, grid, m0, m0, 1, lr, beta1=float(np.float32(0.9)),
+                                        beta2=float(np.float32(0.999)), adam_eps=float(np.float32(1e-8)))
+    assert float(buf.loss.item()) == pytest.approx(L, rel=1e-5)
+    gg = {k: np64(v) for k, v in buf.grads.as_dict().items() if v is not None}
+    for k in ("mu", "log_scale", "quat", "amp"):
+        assert_grad_close(gg[k], gr[k], f"fit d_{k}")
+    # Adam's first step moves each entry by ~lr * sign(g): compare where |g| is not tiny
+    for k in ("mu", "log_scale", "quat", "amp"):
+        got = np64(getattr(g, k))
+        big = np.abs(gr[k]) > 1e-2 * np.sqrt(np.mean(gr[k] ** 2))
+        np.testing.assert_allclose(got[big], newp[k][big], rtol=1e-6, atol=1e-3 * lr[k], err_msg=k)
+    assert int(st.step.item()) == 1
