@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, run one plain device-to-device copy of this many MiB (a known-size "
+                         "kernel against which profiler byte counters are calibrated)")
     return ap.parse_args()
 
 
@@ -156,6 +159,15 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic_from_profiles(dom)}
+
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- CPU baseline: the oracle on the host cores, one full fit step of the same workload -------
     cpu = None

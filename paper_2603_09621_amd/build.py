@@ -1,8 +1,9 @@
 """Build libgs.so (HIP for gfx950) in-tree: one object per source, then a shared library.
 
 Every HIP source is compiled with packed-FP32 instruction selection switched off.  The binning
-source is also compiled without floating-point contraction, so that its count pass and its emit
-pass (two instantiations of one enumeration) round identically.
+and rendering sources are also compiled without floating-point contraction (fused multiply-adds
+are written explicitly), so that the count and emit passes of the binning round identically and
+the forward, backward and pair-count kernels take the same inclusion decision for every pair.
 """
 import os
 import shutil
@@ -20,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
           "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 SOURCES = {
     "bin.hip": ["-ffp-contract=off"],
-    "render.hip": [],
+    "render.hip": ["-ffp-contract=off"],
     "fit.hip": [],
     "api.cpp": ["-x", "hip"],
 }

@@ -94,6 +94,9 @@ bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg
   bg->hx = grid->spacing[0];
   bg->hy = grid->spacing[1];
   bg->hz = grid->spacing[2];
+  bg->ihx = 1.f / grid->spacing[0];
+  bg->ihy = 1.f / grid->spacing[1];
+  bg->ihz = 1.f / grid->spacing[2];
   return true;
 }
 
@@ -123,15 +126,16 @@ WsLayout make_layout(int64_t n, const BrickGrid &bg, int64_t cap) {
   L.keys_alt = take(sizeof(uint32_t) * (size_t)cap);
   L.vals_a = take(sizeof(uint32_t) * (size_t)cap);
   L.vals_b = take(sizeof(uint32_t) * (size_t)cap);
-  L.sorted_gid = take(sizeof(uint32_t) * (size_t)cap);
+  L.list_gid = take(sizeof(uint32_t) * (size_t)cap);
+  L.list_slot = take(sizeof(uint32_t) * (size_t)cap);
   L.brick_off = take(sizeof(uint32_t) * (size_t)(bg.nbricks + 1));
   L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
-  int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
+  const int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
   L.scan_tmp = take(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
   L.partials = take(sizeof(float) * 12 * (size_t)cap);
   L.total = o;
-  // the sorted slot list ends in vals_a after an odd number of passes, vals_b after an even number
-  L.sorted_slot = (L.sort_passes & 1) ? L.vals_a : L.vals_b;
+  // pass p writes keys to keys_alt when p is even, key_brick when odd
+  L.sorted_keys = ((L.sort_passes - 1) & 1) ? L.key_brick : L.keys_alt;
   return L;
 }
 
@@ -175,10 +179,10 @@ static int check_common(const gs_gaussians_t *g, const gs_grid_t *grid, const gs
   int rc;
   if ((rc = check_gaussians(g)) || (rc = check_grid(grid)) || (rc = check_opts(opts))) return rc;
   if (!bins || !bins->ws) return fail(GS_ERR_INVALID_ARG, "bins or bins->ws is NULL");
-  if (bins->key_capacity < 0 || bins->key_capacity > (int64_t)0xFFFFFFF0)
-    return fail(GS_ERR_INVALID_ARG, "key_capacity must be in [0, 2^32 - 16]");
+  if (bins->key_capacity < 0 || bins->key_capacity > (int64_t)0x7FFFFF00)
+    return fail(GS_ERR_INVALID_ARG, "key_capacity must be in [0, 2^31 - 256]");
   make_brick_grid(grid, opts, bg);
-  if (bg->nbricks >= ((int64_t)1 << 32)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
+  if (bg->nbricks >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
   *L = make_layout(g->n, *bg, bins->key_capacity);
   if ((int64_t)kRadix * L->sort_blocks > (int64_t)kScanTile * 8192 || g->n + 1 > (int64_t)kScanTile * 8192)
     return fail(GS_ERR_INVALID_ARG, "key capacity or n beyond the scan limit");
@@ -214,9 +218,8 @@ size_t gs_loss_scratch_bytes(int64_t nvox) { return sizeof(float) * (size_t)std:
 static int bin_front(const gs_gaussians_t *g, const BrickGrid &bg, const gs_opts_t *opts, const gs_bins_t *bins,
                      const WsLayout &L, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_reset_status(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "reset_status");
-  if ((e = launch_prep(*g, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep");
-  if ((e = launch_keygen(bg, opts->cutoff, false, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "keygen_count");
+  if ((e = launch_reset(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "reset");
+  if ((e = launch_prep_count(*g, bg, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
   if ((e = launch_scan_counts(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "scan_counts");
   return GS_OK;
 }
@@ -248,7 +251,7 @@ int gs_bin(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts
   hipStream_t s = (hipStream_t)stream;
   if ((rc = bin_front(g, bg, opts, bins, L, s))) return rc;
   hipError_t e;
-  if ((e = launch_keygen(bg, opts->cutoff, true, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "keygen_emit");
+  if ((e = launch_emit(bg, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
   if ((e = launch_sort(bg, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
   return GS_OK;
 }

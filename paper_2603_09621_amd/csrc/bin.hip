@@ -1,21 +1,22 @@
 // Binning: per-Gaussian records, (brick, Gaussian) key generation with a conservative ellipsoid
-// cull, exclusive scans, LSD radix sort on brick id, brick offsets.
+// cull, and an LSD radix sort of the keys on brick id.
 //
 // The paper's rasterizer partitions the volume into bricks and, for each brick, identifies the
-// Gaussians whose 3-sigma Mahalanobis ellipsoid meets it (§3.3).  Here every Gaussian emits one key
-// per brick its ellipsoid may meet; a stable radix sort on brick id then yields, per brick, a
-// contiguous list of Gaussian indices in ascending order.
+// Gaussians whose 3-sigma Mahalanobis ellipsoid meets it (§3.3).  Here every Gaussian enumerates the
+// bricks its ellipsoid may meet: a count pass (fused with the record computation), an exclusive scan
+// that numbers the keys Gaussian-major, and an emit pass that writes (brick id, Gaussian) at each key's
+// slot.  A stable LSD radix sort on brick id (8-bit digits) then yields per-brick lists in ascending
+// Gaussian order together with each key's slot, which the backward uses to store its partial sums.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "geom.h"
 #include "gs_internal.h"
 
 namespace gs {
 
-// ------------------------------------------------------------------------------------------------
-// Status
-
-__global__ void k_reset_status(DevStatus *st) {
+__global__ void k_reset(DevStatus *st) {
   if (threadIdx.x == 0) {
     st->n_keys = 0;
     st->overflow = 0;
@@ -23,21 +24,21 @@ __global__ void k_reset_status(DevStatus *st) {
   }
 }
 
-hipError_t launch_reset_status(void *ws, const WsLayout &L, hipStream_t s) {
+hipError_t launch_reset(void *ws, const WsLayout &L, hipStream_t s) {
   prof_begin(s);
-  k_reset_status<<<1, 64, 0, s>>>((DevStatus *)((char *)ws + L.status));
-  prof_end(s, "reset_status");
+  k_reset<<<1, 64, 0, s>>>((DevStatus *)((char *)ws + L.status));
+  prof_end(s, "reset");
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
-// Prep: (mu, s, q, A, r) -> evaluation and culling records (§3.1 parameters; §3.2 weight).
+// Prep: (mu, s, q, A, r) -> evaluation and culling records (§3.1 parameters; §3.2 weight).  The
+// records are built by a device function shared by the fused prep + count kernel.
 
-__global__ void k_prep(int64_t n, const float *__restrict__ mu, const float *__restrict__ ls,
-                       const float *__restrict__ quat, const float *__restrict__ amp, const float *__restrict__ relax,
-                       EvalRec *__restrict__ er, CullRec *__restrict__ cr, DevStatus *st) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void make_records(int64_t i, const float *__restrict__ mu, const float *__restrict__ ls,
+                                             const float *__restrict__ quat, const float *__restrict__ amp,
+                                             const float *__restrict__ relax, float cutoff, EvalRec &e, CullRec &cr,
+                                             DevStatus *st) {
   float mx = mu[3 * i], my = mu[3 * i + 1], mz = mu[3 * i + 2];
   float s0 = ls[3 * i], s1 = ls[3 * i + 1], s2 = ls[3 * i + 2];
   float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
@@ -48,8 +49,8 @@ __global__ void k_prep(int64_t n, const float *__restrict__ mu, const float *__r
             isfinite(qn2) && qn2 > 0.f && isfinite(A) && isfinite(r) && r > 0.f;
   if (!ok) {
     atomicOr(&st->nonfinite, 1);
-    er[i] = EvalRec{make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
-    cr[i] = CullRec{make_float4(1, 1, 1, 0), make_float4(0, 0, 0, 0)};
+    e = EvalRec{make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
+    cr = CullRec{make_float4(1, 1, 1, 0), make_float4(0, 0, 0, 0)};
     return;
   }
   float qn = sqrtf(qn2);
@@ -68,132 +69,102 @@ __global__ void k_prep(int64_t n, const float *__restrict__ mu, const float *__r
       P[a][b] = R[a][0] * iv[0] * R[b][0] + R[a][1] * iv[1] * R[b][1] + R[a][2] * iv[2] * R[b][2];
     }
   const float k = -kHalfLog2e;
-  EvalRec e;
+  const float l2r = log2f(r);
   e.r0 = make_float4(mx, my, mz, A);
-  e.r1 = make_float4(k * P[0][0], k * P[1][1], k * P[2][2], log2f(r));
-  e.r2 = make_float4(2.f * k * P[0][1], 2.f * k * P[0][2], 2.f * k * P[1][2], 1.f / r);
-  er[i] = e;
-  cr[i] = CullRec{make_float4(S[0][0], S[1][1], S[2][2], S[0][1]), make_float4(S[0][2], S[1][2], 1.f, 0.f)};
-}
-
-hipError_t launch_prep(const gs_gaussians_t &g, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
-  (void)cutoff;
-  if (g.n == 0) return hipSuccess;
-  char *b = (char *)ws;
-  int blocks = (int)((g.n + 255) / 256);
-  prof_begin(s);
-  k_prep<<<blocks, 256, 0, s>>>(g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, (EvalRec *)(b + L.evalrec),
-                                (CullRec *)(b + L.cullrec), (DevStatus *)(b + L.status));
-  prof_end(s, "prep");
-  return hipGetLastError();
+  e.r1 = make_float4(k * P[0][0], 2.f * k * P[0][1], 2.f * k * P[0][2], k * cutoff * cutoff + l2r);
+  e.r2 = make_float4(k * P[1][1], 2.f * k * P[1][2], k * P[2][2], l2r);
+  cr = CullRec{make_float4(S[0][0], S[1][1], S[2][2], S[0][1]), make_float4(S[0][2], S[1][2], 1.f, 0.f)};
 }
 
 // ------------------------------------------------------------------------------------------------
 // Key generation.  For one Gaussian: its axis-aligned 3-sigma voxel box; for each brick z-slab the
 // y-extent of the ellipsoid inside that slab; for each brick row the x-extent inside the row's y-slab
 // intersected with the x-extent inside the z-slab.  Every brick whose voxel centres fall in these
-// conservative ranges receives a key.  The count pass and the emit pass run the same enumeration.
+// conservative ranges receives a key.  The count pass and the emit pass run the same enumeration
+// (visit(brick, j) is called for the j-th key of the Gaussian).
 
-template <bool EMIT>
+template <class Visit>
 __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
-                                     uint32_t gid, uint32_t base, int64_t cap, uint32_t *__restrict__ key_brick,
-                                     uint32_t *__restrict__ key_gid) {
+                                     Visit visit) {
   if (c.c1.z == 0.f) return 0;  // invalid Gaussian: no keys
   const float mx = e.r0.x, my = e.r0.y, mz = e.r0.z;
   const float sxx = c.c0.x, syy = c.c0.y, szz = c.c0.z, sxy = c.c0.w, sxz = c.c1.x, syz = c.c1.y;
-  const float ex = cutoff * sqrtf(sxx), ey = cutoff * sqrtf(syy), ez = cutoff * sqrtf(szz);
+  const float ex = cutoff * __builtin_amdgcn_sqrtf(sxx), ey = cutoff * __builtin_amdgcn_sqrtf(syy),
+              ez = cutoff * __builtin_amdgcn_sqrtf(szz);
   const float tx = extent_tol(mx, ex, bg.hx), ty = extent_tol(my, ey, bg.hy), tz = extent_tol(mz, ez, bg.hz);
   int xl, xh, yl, yh, zl, zh;
-  world_to_index(mx - ex - tx, mx + ex + tx, bg.ox, bg.hx, bg.nx, xl, xh);
-  world_to_index(my - ey - ty, my + ey + ty, bg.oy, bg.hy, bg.ny, yl, yh);
-  world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.hz, bg.nz, zl, zh);
+  world_to_index(mx - ex - tx, mx + ex + tx, bg.ox, bg.ihx, bg.nx, xl, xh);
+  world_to_index(my - ey - ty, my + ey + ty, bg.oy, bg.ihy, bg.ny, yl, yh);
+  world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.ihz, bg.nz, zl, zh);
   if (xl > xh || yl > yh || zl > zh) return 0;
   uint32_t count = 0;
   for (int kz = zl / bg.bz; kz <= zh / bg.bz; ++kz) {
     int za = max(zl, kz * bg.bz), zb = min(zh, kz * bg.bz + bg.bz - 1);
-    float Z0 = bg.oz + bg.hz * za, Z1 = bg.oz + bg.hz * zb;
+    const float Z0 = centre(bg.oz, bg.hz, za), Z1 = centre(bg.oz, bg.hz, zb);
     float ylo, yhi, xzlo, xzhi;
     if (!extent_in_slab(my, mz, syy, szz, syz, cutoff, Z0, Z1, ty, ylo, yhi)) continue;
     if (!extent_in_slab(mx, mz, sxx, szz, sxz, cutoff, Z0, Z1, tx, xzlo, xzhi)) continue;
     int yl2, yh2;
-    world_to_index(ylo, yhi, bg.oy, bg.hy, bg.ny, yl2, yh2);
+    world_to_index(ylo, yhi, bg.oy, bg.ihy, bg.ny, yl2, yh2);
     yl2 = max(yl2, yl);
     yh2 = min(yh2, yh);
     if (yl2 > yh2) continue;
     for (int ky = yl2 / bg.by; ky <= yh2 / bg.by; ++ky) {
       int ya = max(yl2, ky * bg.by), yb = min(yh2, ky * bg.by + bg.by - 1);
-      float Y0 = bg.oy + bg.hy * ya, Y1 = bg.oy + bg.hy * yb;
+      const float Y0 = centre(bg.oy, bg.hy, ya), Y1 = centre(bg.oy, bg.hy, yb);
       float xylo, xyhi;
       if (!extent_in_slab(mx, my, sxx, syy, sxy, cutoff, Y0, Y1, tx, xylo, xyhi)) continue;
       int xl2, xh2;
-      world_to_index(fmaxf(xzlo, xylo), fminf(xzhi, xyhi), bg.ox, bg.hx, bg.nx, xl2, xh2);
+      world_to_index(fmaxf(xzlo, xylo), fminf(xzhi, xyhi), bg.ox, bg.ihx, bg.nx, xl2, xh2);
       xl2 = max(xl2, xl);
       xh2 = min(xh2, xh);
       if (xl2 > xh2) continue;
-      int kx0 = xl2 / bg.bx, kx1 = xh2 / bg.bx;
-      if (EMIT) {
-        uint32_t row = (uint32_t)((kz * bg.nby + ky) * bg.nbx);
-        for (int kx = kx0; kx <= kx1; ++kx) {
-          int64_t slot = (int64_t)base + count + (kx - kx0);
-          if (slot < cap) {
-            key_brick[slot] = row + (uint32_t)kx;
-            key_gid[slot] = gid;
-          }
-        }
-      }
+      const int kx0 = xl2 / bg.bx, kx1 = xh2 / bg.bx;
+      const uint32_t row = (uint32_t)((kz * bg.nby + ky) * bg.nbx);
+      for (int kx = kx0; kx <= kx1; ++kx) visit(row + (uint32_t)kx, count + (uint32_t)(kx - kx0));
       count += (uint32_t)(kx1 - kx0 + 1);
     }
   }
   return count;
 }
 
-__global__ void k_keygen_count(int64_t n, BrickGrid bg, float cutoff, const EvalRec *__restrict__ er,
-                               const CullRec *__restrict__ cr, uint32_t *__restrict__ cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Fused prep + count: records of Gaussian i and its key count cnt[i].  Thread n writes cnt[n] = 0
+// (the scan's total slot).
+__global__ void k_prep_count(int64_t n, const float *__restrict__ mu, const float *__restrict__ ls,
+                             const float *__restrict__ quat, const float *__restrict__ amp,
+                             const float *__restrict__ relax, BrickGrid bg, float cutoff, EvalRec *__restrict__ er,
+                             CullRec *__restrict__ cr, uint32_t *__restrict__ cnt, DevStatus *st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
   if (i == n) {
-    cnt[n] = 0;
+    cnt[n] = 0u;
     return;
   }
-  cnt[i] = enumerate_bricks<false>(bg, er[i], cr[i], cutoff, (uint32_t)i, 0, 0, nullptr, nullptr);
+  EvalRec e;
+  CullRec c;
+  make_records(i, mu, ls, quat, amp, relax, cutoff, e, c, st);
+  er[i] = e;
+  cr[i] = c;
+  cnt[i] = enumerate_bricks(bg, e, c, cutoff, [](uint32_t, uint32_t) {});
 }
 
-__global__ void k_keygen_emit(int64_t n, BrickGrid bg, float cutoff, const EvalRec *__restrict__ er,
-                              const CullRec *__restrict__ cr, const uint32_t *__restrict__ off, int64_t cap,
-                              const DevStatus *st, uint32_t *__restrict__ key_brick, uint32_t *__restrict__ key_gid) {
-  if (st->overflow) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  enumerate_bricks<true>(bg, er[i], cr[i], cutoff, (uint32_t)i, off[i], cap, key_brick, key_gid);
-}
-
-hipError_t launch_keygen(const BrickGrid &bg, float cutoff, bool emit, void *ws, const WsLayout &L, hipStream_t s) {
+hipError_t launch_prep_count(const gs_gaussians_t &g, const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L,
+                             hipStream_t s) {
   char *b = (char *)ws;
-  const EvalRec *er = (const EvalRec *)(b + L.evalrec);
-  const CullRec *cr = (const CullRec *)(b + L.cullrec);
-  uint32_t *off = (uint32_t *)(b + L.off);
+  int blocks = (int)((g.n + 1 + 255) / 256);
   prof_begin(s);
-  if (!emit) {
-    int blocks = (int)((L.n + 1 + 255) / 256);
-    k_keygen_count<<<blocks, 256, 0, s>>>(L.n, bg, cutoff, er, cr, off);
-    prof_end(s, "keygen_count");
-  } else {
-    if (L.n == 0) {
-      prof_end(s, "keygen_emit");
-      return hipGetLastError();
-    }
-    int blocks = (int)((L.n + 255) / 256);
-    k_keygen_emit<<<blocks, 256, 0, s>>>(L.n, bg, cutoff, er, cr, off, L.cap, (const DevStatus *)(b + L.status),
-                                         (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid));
-    prof_end(s, "keygen_emit");
-  }
+  k_prep_count<<<blocks, 256, 0, s>>>(g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, bg, cutoff,
+                                      (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
+                                      (uint32_t *)(b + L.off), (DevStatus *)(b + L.status));
+  prof_end(s, "prep_count");
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
 // Exclusive scan of a uint32 array (length on the host).  Three launches: per-tile totals, a
-// one-block scan of the tile totals (64-bit, so the grand total is exact), and the per-tile scan.
-// Each wave scans 16 consecutive chunks of 64 elements with a running carry.
+// one-block scan of the tile totals (64-bit), and the per-tile scan.  Each wave scans 16 consecutive
+// chunks of 64 elements with a running carry.  If key_idx >= 0, entry key_idx of the result is the
+// key count: it is stored (64-bit) in the status block with the overflow flag.
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 #pragma unroll
@@ -234,9 +205,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__
   }
 }
 
-// One block of 1024 threads scans nb <= 8192 tile totals in place (exclusive).  If st != NULL the
-// grand total is the key count: it is stored and checked against the capacity.
-__global__ __launch_bounds__(1024) void k_scan_bsums(uint64_t *__restrict__ bsum, int nb, DevStatus *st, int64_t cap) {
+// One block of 1024 threads scans nb <= 8192 tile totals in place (exclusive).
+__global__ __launch_bounds__(1024) void k_scan_bsums(uint64_t *__restrict__ bsum, int nb) {
   __shared__ uint64_t wsum[16];
   constexpr int PER = 8;
   int t = threadIdx.x;
@@ -251,11 +221,8 @@ __global__ __launch_bounds__(1024) void k_scan_bsums(uint64_t *__restrict__ bsum
   uint64_t incl = wave_incl_scan64(local);
   if (lane_id() == 63) wsum[t >> 6] = incl;
   __syncthreads();
-  uint64_t woff = 0, total = 0;
-  for (int w = 0; w < 16; ++w) {
-    if (w < (t >> 6)) woff += wsum[w];
-    total += wsum[w];
-  }
+  uint64_t woff = 0;
+  for (int w = 0; w < (t >> 6); ++w) woff += wsum[w];
   uint64_t run = woff + incl - local;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
@@ -263,15 +230,12 @@ __global__ __launch_bounds__(1024) void k_scan_bsums(uint64_t *__restrict__ bsum
     if (idx < nb) bsum[idx] = run;
     run += v[j];
   }
-  if (st && t == 0) {
-    st->n_keys = (int64_t)total;
-    st->overflow = (int64_t)total > cap ? 1 : 0;
-  }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t *__restrict__ in,
                                                               uint32_t *__restrict__ out, int64_t len,
-                                                              const uint64_t *__restrict__ bsum_ex) {
+                                                              const uint64_t *__restrict__ bsum_ex, int64_t key_idx,
+                                                              int64_t cap, DevStatus *st) {
   __shared__ uint32_t ws[kScanThreads / 64];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * (64 * kScanItems);
@@ -287,38 +251,80 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t *__r
   }
   if (l == 0) ws[w] = carry;
   __syncthreads();
-  uint32_t off = (uint32_t)bsum_ex[blockIdx.x];
+  uint32_t off = 0;
   for (int v = 0; v < w; ++v) off += ws[v];
+  const uint64_t bex = bsum_ex[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     int64_t idx = base + j * 64 + l;
-    if (idx < len) out[idx] = pref[j] + off;
+    if (idx < len) {
+      const uint64_t e64 = bex + (uint64_t)(pref[j] + off);
+      out[idx] = (uint32_t)e64;
+      if (idx == key_idx) {
+        st->n_keys = (int64_t)e64;
+        st->overflow = (int64_t)e64 > cap ? 1 : 0;
+      }
+    }
   }
 }
 
-static hipError_t scan_u32(uint32_t *data, int64_t len, uint64_t *tmp, DevStatus *st, int64_t cap, hipStream_t s,
-                           const char *name) {
-  int nb = (int)((len + kScanTile - 1) / kScanTile);
+static hipError_t scan_u32(uint32_t *data, int64_t len, uint64_t *tmp, int64_t key_idx, int64_t cap, DevStatus *st,
+                           hipStream_t s, const char *name) {
+  const int nb = (int)((len + kScanTile - 1) / kScanTile);
   if (nb == 0) return hipSuccess;
   prof_begin(s);
   k_scan_reduce<<<nb, kScanThreads, 0, s>>>(data, len, tmp);
-  k_scan_bsums<<<1, 1024, 0, s>>>(tmp, nb, st, cap);
-  k_scan_apply<<<nb, kScanThreads, 0, s>>>(data, data, len, tmp);
+  k_scan_bsums<<<1, 1024, 0, s>>>(tmp, nb);
+  k_scan_apply<<<nb, kScanThreads, 0, s>>>(data, data, len, tmp, key_idx, cap, st);
   prof_end(s, name);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
-  return scan_u32((uint32_t *)(b + L.off), L.n + 1, (uint64_t *)(b + L.scan_tmp), (DevStatus *)(b + L.status), L.cap,
-                  s, "scan_counts");
+  return scan_u32((uint32_t *)(b + L.off), L.n + 1, (uint64_t *)(b + L.scan_tmp), L.n, L.cap,
+                  (DevStatus *)(b + L.status), s, "scan_counts");
 }
 
 // ------------------------------------------------------------------------------------------------
-// LSD radix sort of (brick id, slot) pairs, 8 bits per pass, stable.  Tile = 2048 keys per block,
-// processed in 8 rounds of 256 keys in key order; within a round a key's rank among equal digits
-// comes from wave ballots (lanes with the same digit and a lower lane id) plus the counts of the
-// lower waves and of the earlier rounds.
+// Emit: the j-th key of Gaussian i is written at slot off[i] + j.
+
+__global__ void k_emit(int64_t n, BrickGrid bg, float cutoff, const EvalRec *__restrict__ er,
+                       const CullRec *__restrict__ cr, const uint32_t *__restrict__ off, int64_t cap,
+                       const DevStatus *st, uint32_t *__restrict__ key_brick, uint32_t *__restrict__ key_gid) {
+  if (st->overflow) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t base = off[i];
+  enumerate_bricks(bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
+    const int64_t slot = (int64_t)base + j;
+    if (slot < cap) {
+      key_brick[slot] = brick;
+      key_gid[slot] = (uint32_t)i;
+    }
+  });
+}
+
+hipError_t launch_emit(const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
+  if (L.n == 0) return hipSuccess;
+  char *b = (char *)ws;
+  int blocks = (int)((L.n + 255) / 256);
+  prof_begin(s);
+  k_emit<<<blocks, 256, 0, s>>>(L.n, bg, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+                                (const uint32_t *)(b + L.off), L.cap, (const DevStatus *)(b + L.status),
+                                (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid));
+  prof_end(s, "emit");
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// LSD radix sort of (brick id, slot) pairs, 8 bits per pass, stable.  Tiles of 4096 keys.
+//   hist:    per-tile digit counts, digit-major [256][tiles] (scanned into global offsets).
+//   scatter: each wave ranks its 1024 consecutive keys in 16 rounds of 64 (rank among equal digits =
+//            wave ballots + a per-wave running count), the four waves' counts are combined into
+//            per-digit tile offsets, the tile is reordered by digit in LDS and written out in
+//            order, so consecutive threads store consecutive positions of a digit's run.  The last
+//            pass writes the Gaussian index of each key (looked up by slot) and the slot.
 
 __device__ __forceinline__ int64_t live_keys(const DevStatus *st, int64_t cap) {
   return st->overflow ? 0 : (st->n_keys < cap ? st->n_keys : cap);
@@ -326,75 +332,112 @@ __device__ __forceinline__ int64_t live_keys(const DevStatus *st, int64_t cap) {
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, const DevStatus *st,
                                                               int64_t cap, int shift, uint32_t *__restrict__ hist,
-                                                              int nblocks) {
+                                                              int ntiles) {
   __shared__ uint32_t cnt[kRadix];
   const int t = threadIdx.x;
   cnt[t] = 0;
   __syncthreads();
   const int64_t K = live_keys(st, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll
+#pragma unroll 4
   for (int j = 0; j < kSortItems; ++j) {
-    int64_t idx = base + j * kSortThreads + t;
+    const int64_t idx = base + j * kSortThreads + t;
     if (idx < K) atomicAdd(&cnt[(keys[idx] >> shift) & (kRadix - 1)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)t * nblocks + blockIdx.x] = cnt[t];
+  hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
 }
 
+template <bool LAST>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, const DevStatus *st, int64_t cap, int shift, const uint32_t *__restrict__ offsets,
-    int nblocks) {
-  __shared__ uint32_t run[kRadix];
-  __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
-  const int t = threadIdx.x, w = t >> 6;
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ key_gid, uint32_t *__restrict__ gout,
+    const DevStatus *st, int64_t cap, int shift, const uint32_t *__restrict__ offsets, int ntiles) {
+  __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];  // per-wave running counts, then per-wave offsets
+  __shared__ uint32_t tdo[kRadix];                      // digit offsets within the tile
+  __shared__ uint32_t goff[kRadix];                     // global offset of the tile's first key of each digit
+  __shared__ uint32_t skey[kSortTile], sval[kSortTile];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int64_t K = live_keys(st, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= K) return;  // uniform per block
-  run[t] = offsets[(int64_t)t * nblocks + blockIdx.x];
+  const int n_tile = (int)min((int64_t)kSortTile, K - base);
 #pragma unroll
   for (int v = 0; v < kSortThreads / 64; ++v) wcnt[v][t] = 0;
+  goff[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
   __syncthreads();
   const uint64_t lt = lanemask_lt();
-  for (int j = 0; j < kSortItems; ++j) {
-    int64_t idx = base + j * kSortThreads + t;
-    bool valid = idx < K;
-    uint32_t key = valid ? kin[idx] : 0u;
-    uint32_t val = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
-    uint32_t d = (key >> shift) & (kRadix - 1);
+  uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int li = w * (64 * kSortItems) + r * 64 + l;  // position in the tile, wave-contiguous
+    const bool valid = li < n_tile;
+    const uint32_t key = valid ? kin[base + li] : 0u;
+    const uint32_t val = valid ? (vin ? vin[base + li] : (uint32_t)(base + li)) : 0u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
     uint64_t m = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < kRadixBits; ++bit) {
-      uint64_t bb = __ballot((d >> bit) & 1u);
+      const uint64_t bb = __ballot((d >> bit) & 1u);
       m &= ((d >> bit) & 1u) ? bb : ~bb;
     }
-    uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int v = 0; v < w; ++v) pos += wcnt[v][d];
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int v = 0; v < kSortThreads / 64; ++v) {
-      add += wcnt[v][t];
-      wcnt[v][t] = 0;
-    }
-    run[t] += add;
-    __syncthreads();
+    const uint32_t before = (uint32_t)__popcll(m & lt);
+    // the running count is shared by the lanes of this wave only; a wave's LDS accesses complete in
+    // program order, so every lane reads the count before the group's first lane updates it
+    volatile uint32_t *wc = &wcnt[w][0];
+    const uint32_t prev = valid ? wc[d] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) wc[d] = prev + (uint32_t)__popcll(m);
+    __builtin_amdgcn_wave_barrier();
+    keys[r] = key;
+    vals[r] = val;
+    rank[r] = valid ? prev + before : 0xFFFFFFFFu;
   }
-}
-
-// Sorted slot -> Gaussian index; brick offsets by binary search of the sorted brick ids.
-__global__ void k_gather_gid(const uint32_t *__restrict__ sorted_slot, const uint32_t *__restrict__ key_gid,
-                             uint32_t *__restrict__ sorted_gid, const DevStatus *st, int64_t cap) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < live_keys(st, cap)) sorted_gid[k] = key_gid[sorted_slot[k]];
+  __syncthreads();
+  // per digit: totals over the waves -> exclusive offsets of the waves, and the tile's digit count
+  {
+    const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+    wcnt[0][t] = 0;
+    wcnt[1][t] = c0;
+    wcnt[2][t] = c0 + c1;
+    wcnt[3][t] = c0 + c1 + c2;
+    tdo[t] = c0 + c1 + c2 + c3;  // count; scanned below
+  }
+  __syncthreads();
+  if (t < 64) {  // exclusive scan of the 256 digit counts by one wave (4 per lane)
+    uint32_t a0 = tdo[4 * t], a1 = tdo[4 * t + 1], a2 = tdo[4 * t + 2], a3 = tdo[4 * t + 3];
+    const uint32_t s4 = a0 + a1 + a2 + a3;
+    uint32_t incl = s4;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const uint32_t o = __shfl_up(incl, dd, 64);
+      if (l >= dd) incl += o;
+    }
+    const uint32_t ex = incl - s4;
+    tdo[4 * t] = ex;
+    tdo[4 * t + 1] = ex + a0;
+    tdo[4 * t + 2] = ex + a0 + a1;
+    tdo[4 * t + 3] = ex + a0 + a1 + a2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (rank[r] != 0xFFFFFFFFu) {
+      const uint32_t d = (keys[r] >> shift) & (kRadix - 1);
+      const uint32_t pos = tdo[d] + wcnt[w][d] + rank[r];
+      skey[pos] = keys[r];
+      sval[pos] = vals[r];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n_tile; i += kSortThreads) {
+    const uint32_t key = skey[i], val = sval[i];
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t pos = goff[d] + ((uint32_t)i - tdo[d]);
+    kout[pos] = key;
+    vout[pos] = val;
+    if (LAST) gout[pos] = key_gid[val];
+  }
 }
 
 __global__ void k_brick_offsets(const uint32_t *__restrict__ sorted_brick, const DevStatus *st, int64_t cap,
@@ -415,39 +458,41 @@ __global__ void k_brick_offsets(const uint32_t *__restrict__ sorted_brick, const
 
 hipError_t launch_sort(const BrickGrid &bg, void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
-  const DevStatus *st = (const DevStatus *)(b + L.status);
+  DevStatus *st = (DevStatus *)(b + L.status);
   uint32_t *ka = (uint32_t *)(b + L.key_brick), *kb = (uint32_t *)(b + L.keys_alt);
   uint32_t *va = (uint32_t *)(b + L.vals_a), *vb = (uint32_t *)(b + L.vals_b);
   uint32_t *hist = (uint32_t *)(b + L.hist);
   uint64_t *tmp = (uint64_t *)(b + L.scan_tmp);
-  const int nbk = L.sort_blocks;
+  const int nt = L.sort_blocks;
   hipError_t err = hipSuccess;
-  if (nbk > 0) {
+  if (nt > 0) {
     const uint32_t *kin = ka, *vin = nullptr;
     for (int p = 0; p < L.sort_passes; ++p) {
+      const bool last = p == L.sort_passes - 1;
       uint32_t *kout = (p & 1) ? ka : kb;
-      uint32_t *vout = (p & 1) ? vb : va;
+      uint32_t *vout = last ? (uint32_t *)(b + L.list_slot) : ((p & 1) ? vb : va);
       prof_begin(s);
-      k_radix_hist<<<nbk, kSortThreads, 0, s>>>(kin, st, L.cap, p * kRadixBits, hist, nbk);
+      k_radix_hist<<<nt, kSortThreads, 0, s>>>(kin, st, L.cap, p * kRadixBits, hist, nt);
       prof_end(s, "radix_hist");
-      err = scan_u32(hist, (int64_t)kRadix * nbk, tmp, nullptr, 0, s, "radix_scan");
+      err = scan_u32(hist, (int64_t)kRadix * nt, tmp, -1, 0, st, s, "radix_scan");
       if (err != hipSuccess) return err;
       prof_begin(s);
-      k_radix_scatter<<<nbk, kSortThreads, 0, s>>>(kin, vin, kout, vout, st, L.cap, p * kRadixBits, hist, nbk);
+      if (last)
+        k_radix_scatter<true><<<nt, kSortThreads, 0, s>>>(kin, vin, kout, vout, (const uint32_t *)(b + L.key_gid),
+                                                          (uint32_t *)(b + L.list_gid), st, L.cap, p * kRadixBits,
+                                                          hist, nt);
+      else
+        k_radix_scatter<false><<<nt, kSortThreads, 0, s>>>(kin, vin, kout, vout, nullptr, nullptr, st, L.cap,
+                                                           p * kRadixBits, hist, nt);
       prof_end(s, "radix_scatter");
       kin = kout;
       vin = vout;
     }
-    int gb = (int)((L.cap + 255) / 256);
-    prof_begin(s);
-    k_gather_gid<<<gb, 256, 0, s>>>(vin, (const uint32_t *)(b + L.key_gid), (uint32_t *)(b + L.sorted_gid), st,
-                                    L.cap);
-    prof_end(s, "gather_gid");
   }
-  int ob = (int)((bg.nbricks + 1 + 255) / 256);
+  const int ob = (int)((bg.nbricks + 1 + 255) / 256);
   prof_begin(s);
-  k_brick_offsets<<<ob, 256, 0, s>>>((const uint32_t *)(b + (L.sort_passes & 1 ? L.keys_alt : L.key_brick)), st,
-                                     L.cap, (uint32_t *)(b + L.brick_off), bg.nbricks);
+  k_brick_offsets<<<ob, 256, 0, s>>>((const uint32_t *)(b + L.sorted_keys), st, L.cap, (uint32_t *)(b + L.brick_off),
+                                     bg.nbricks);
   prof_end(s, "brick_offsets");
   return hipGetLastError();
 }

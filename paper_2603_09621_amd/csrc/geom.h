@@ -16,56 +16,63 @@ __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) -
 // For fixed offset d_b the a-offsets span (sab / sbb) d_b +- sqrt((c^2 - d_b^2 / sbb) (saa - sab^2 / sbb));
 // the upper end is concave in d_b with its maximum at d_b* = c sab / sqrt(saa), so over an interval
 // it peaks at d_b* clamped to the interval (likewise for the lower end at -d_b*).  Returns false if
-// the slab misses the ellipsoid.  Bounds are widened by `tol` (world units).
+// the slab misses the ellipsoid.  Bounds are widened by `tol` (world units), which covers the
+// hardware reciprocal and square-root approximations used here (these ranges only cull).
 __device__ __forceinline__ bool extent_in_slab(float ma, float mb, float saa, float sbb, float sab, float c, float lo_b,
                                                float hi_b, float tol, float &amin, float &amax) {
-  float eb = c * sqrtf(sbb);
-  float d0 = fmaxf(lo_b - mb, -eb - tol);
-  float d1 = fminf(hi_b - mb, eb + tol);
+  const float isbb = __builtin_amdgcn_rcpf(sbb);
+  const float eb = c * __builtin_amdgcn_sqrtf(sbb);
+  const float d0 = fmaxf(lo_b - mb, -eb - tol);
+  const float d1 = fminf(hi_b - mb, eb + tol);
   if (d0 > d1) return false;
-  float slope = sab / sbb;
-  float schur = fmaxf(saa - sab * slope, 0.f);
-  float dstar = c * sab / sqrtf(saa);
-  float dm = fminf(fmaxf(dstar, d0), d1);
-  float dn = fminf(fmaxf(-dstar, d0), d1);
-  float c2 = c * c;
-  float hm = sqrtf(fmaxf(c2 - dm * dm / sbb, 0.f) * schur);
-  float hn = sqrtf(fmaxf(c2 - dn * dn / sbb, 0.f) * schur);
+  const float slope = sab * isbb;
+  const float schur = fmaxf(saa - sab * slope, 0.f);
+  const float dstar = c * sab * __builtin_amdgcn_rsqf(saa);
+  const float dm = fminf(fmaxf(dstar, d0), d1);
+  const float dn = fminf(fmaxf(-dstar, d0), d1);
+  const float c2 = c * c;
+  const float hm = __builtin_amdgcn_sqrtf(fmaxf(c2 - dm * dm * isbb, 0.f) * schur);
+  const float hn = __builtin_amdgcn_sqrtf(fmaxf(c2 - dn * dn * isbb, 0.f) * schur);
   amax = ma + slope * dm + hm + tol;
   amin = ma + slope * dn - hn - tol;
   return true;
 }
 
-// World range [lo, hi] -> inclusive voxel index range on an axis of n voxels (origin o, spacing h).
-__device__ __forceinline__ void world_to_index(float lo, float hi, float o, float h, int n, int &il, int &ih) {
-  float a = ceilf((lo - o) / h);
-  float b = floorf((hi - o) / h);
+// World range [lo, hi] -> inclusive voxel index range on an axis of n voxels (origin o, inverse
+// spacing ih); empty (il > ih) if the range misses the axis.
+__device__ __forceinline__ void world_to_index(float lo, float hi, float o, float ih, int n, int &il, int &ihx) {
+  float a = ceilf((lo - o) * ih);
+  float b = floorf((hi - o) * ih);
   a = fmaxf(a, 0.f);
   b = fminf(b, (float)(n - 1));
   if (!(a <= b)) {
     il = 1;
-    ih = 0;
+    ihx = 0;
     return;
   }
   il = (int)a;
-  ih = (int)b;
+  ihx = (int)b;
 }
 
 // Rounding guard for the conservative extents, world units.
-__device__ __forceinline__ float extent_tol(float m, float e, float h) { return 2e-3f * h + 4e-6f * (fabsf(m) + e); }
+__device__ __forceinline__ float extent_tol(float m, float e, float h) { return 4e-3f * h + 8e-6f * (fabsf(m) + e); }
 
-// q(p) = delta^T Q delta with Q = -1/2 log2(e) Sigma^{-1}; one fixed evaluation order shared by
-// every kernel, so that the forward and the backward take the same inclusion decision per pair.
-__device__ __forceinline__ float qform(const EvalRec &R, float px, float py, float pz, float &dx, float &dy,
-                                       float &dz) {
-  dx = px - R.r0.x;
+// Voxel centre coordinate along one axis; one fixed formula for every kernel.
+__device__ __forceinline__ float centre(float o, float h, int i) { return fmaf(h, (float)i, o); }
+
+// Row coefficients of the exponent (see EvalRec): for the row through (py, pz),
+// q(dx) = Q_xx dx^2 + b dx + c.  Every kernel evaluates a pair through row_coeffs + row_q with the
+// same operation order, so the forward, the backward and the pair count take the same inclusion
+// decision for every pair.
+__device__ __forceinline__ void row_coeffs(const EvalRec &R, float py, float pz, float &dy, float &dz, float &b,
+                                           float &c) {
   dy = py - R.r0.y;
   dz = pz - R.r0.z;
-  float tx = fmaf(R.r1.x, dx, fmaf(R.r2.x, dy, R.r2.y * dz));
-  float ty = fmaf(R.r1.y, dy, R.r2.z * dz);
-  float tz = R.r1.z * dz;
-  return fmaf(dx, tx, fmaf(dy, ty, tz * dz));
+  b = fmaf(R.r1.y, dy, R.r1.z * dz);
+  c = fmaf(fmaf(R.r2.x, dy, R.r2.y * dz), dy, fmaf(R.r2.z * dz, dz, R.r2.w));
 }
+
+__device__ __forceinline__ float row_q(float a, float b, float c, float dx) { return fmaf(fmaf(a, dx, b), dx, c); }
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 

@@ -14,10 +14,11 @@ constexpr float kHalfLog2e = 0.7213475204444817f;
 // Per-Gaussian evaluation record (48 B), written by the prep kernel and staged through LDS by the
 // forward and backward kernels:
 //   r0 = (mu_x, mu_y, mu_z, A)
-//   r1 = (Q_xx, Q_yy, Q_zz, log2 r)             Q = -1/2 log2(e) Sigma^{-1}
-//   r2 = (2 Q_xy, 2 Q_xz, 2 Q_yz, 1 / r)
-// so that q(p) = delta^T Q delta (delta = p - mu), the pair is kept iff q >= -1/2 log2(e) cutoff^2,
-// and w = exp2(q + log2 r).
+//   r1 = (Q_xx, 2 Q_xy, 2 Q_xz, thr + log2 r)     Q = -1/2 log2(e) Sigma^{-1}, thr = -1/2 log2(e) cutoff^2
+//   r2 = (Q_yy, 2 Q_yz, Q_zz, log2 r)
+// On a voxel row (fixed y, z) the exponent is q(dx) = Q_xx dx^2 + b dx + c with
+// b = 2 Q_xy dy + 2 Q_xz dz and c = Q_yy dy^2 + 2 Q_yz dy dz + Q_zz dz^2 + log2 r (delta = p - mu);
+// the pair is kept iff q >= thr + log2 r (i.e. d^2 <= cutoff^2) and w = r exp(-d^2/2) = exp2(q).
 struct __align__(16) EvalRec {
   float4 r0, r1, r2;
 };
@@ -44,11 +45,12 @@ struct BrickGrid {
   int64_t nbricks;
   float ox, oy, oz;  // origin
   float hx, hy, hz;  // spacing
+  float ihx, ihy, ihz;  // 1 / spacing
 };
 
 // Radix sort tiling.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
+constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
@@ -59,12 +61,18 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 // Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
+//   off: uint32 [n + 1]: key counts per Gaussian, after the scan the first key slot of each Gaussian
+//        (keys are numbered Gaussian-major) and off[n] = the key count.
+//   key_brick, key_gid: uint32 [cap] keys in slot order; keys_alt, vals_a, vals_b: radix ping-pong.
+//   list_gid, list_slot: uint32 [cap] the keys sorted by brick: Gaussian index and key slot.
+//   brick_off: uint32 [B + 1] brick list offsets.  partials: 48 B per key slot (backward).
 struct WsLayout {
   int64_t n = 0, cap = 0, nbricks = 0;
-  int sort_blocks = 0;  // blocks per radix pass (covers cap keys)
-  int sort_passes = 0;  // ceil(bits(nbricks) / 8)
+  int sort_blocks = 0;  // tiles per radix pass (covers cap keys)
+  int sort_passes = 0;  // ceil(bits(nbricks) / 8), at least 1
   size_t status = 0, evalrec = 0, cullrec = 0, off = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
-         vals_b = 0, sorted_gid = 0, brick_off = 0, hist = 0, scan_tmp = 0, partials = 0, sorted_slot = 0, total = 0;
+         vals_b = 0, list_gid = 0, list_slot = 0, brick_off = 0, hist = 0, scan_tmp = 0, partials = 0, total = 0;
+  size_t sorted_keys = 0;  // where the brick ids end up after the last pass
 };
 
 // Host-side helpers (api.cpp).
@@ -76,10 +84,11 @@ void prof_begin(hipStream_t s);
 void prof_end(hipStream_t s, const char *name);
 
 // Kernel launchers (bin.hip, render.hip, fit.hip).  Return hipGetLastError() of the launches.
-hipError_t launch_reset_status(void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_prep(const gs_gaussians_t &g, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_keygen(const BrickGrid &bg, float cutoff, bool emit, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_reset(void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_prep_count(const gs_gaussians_t &g, const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L,
+                             hipStream_t s);
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_emit(const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_sort(const BrickGrid &bg, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_fwd(const BrickGrid &bg, float cutoff, float eps, const void *ws, const WsLayout &L, float *I,
                       float *W, hipStream_t s);

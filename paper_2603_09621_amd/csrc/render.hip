@@ -1,18 +1,24 @@
 // Forward and backward rasterizer kernels (§3.2 Eq. (rendering), §3.3).
 //
-// Forward: one workgroup of 256 threads per 8x8x4 brick, one voxel per lane; each wave owns a 4x4x4
-// quarter of the brick.  The brick's Gaussian list is staged through LDS in chunks of 256 records;
-// while staging, each Gaussian is tested against the four quarters and every wave compacts the
-// indices of the Gaussians that may touch its quarter, so a wave only iterates over those.  Per
-// pair: d^2 as a quadratic form, the inclusive cutoff test, one exp2, and the two accumulations
-// (numerator S and denominator W).  Voxels sum their Gaussians in ascending index order.
+// Forward: one workgroup of 256 threads per 8x8x4 brick; each wave owns a 4x4x4 quarter of the
+// brick.  The brick's Gaussian list is staged through LDS in chunks of 256 records; while staging,
+// each Gaussian is tested against the four quarters and every wave compacts the indices of the
+// Gaussians that may touch its quarter.  A wave then keeps four Gaussians in flight: lanes 16g..16g+15
+// (group g) take list entries g, g+4, g+8, ...; each lane owns one voxel row of 4 voxels along x, sets
+// up the row's quadratic once per Gaussian and evaluates the 4 voxels by Horner's rule, the inclusive
+// cutoff test, one exp2 and the two accumulations (numerator S, denominator W).  The four groups'
+// partial sums of a voxel are added in a fixed order at the end, so the result is bitwise
+// deterministic.
 //
-// Backward: one wave per brick, one Gaussian per lane.  The brick's per-voxel factors
-// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; each lane walks the rows of its
-// Gaussian's box inside the brick, restricted per row to the x-interval of the ellipsoid, and
-// accumulates the brick-local sums of dL/dw * (1, delta, delta delta^T) and dL/dA.  The 11 sums of
-// each (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel reduces each
-// Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
+// Backward: one workgroup of two waves per brick, one Gaussian per lane.  The brick's per-voxel
+// factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by
+// their estimated work (heaviest first) so that the lanes of a wave carry similar loads; each lane
+// walks the rows of its Gaussian's box inside the brick, restricted per row to the x-interval of the
+// ellipsoid, and
+// accumulates per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
+// folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.
+// The sums of each (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel
+// reduces each Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
 
 #include "geom.h"
@@ -31,18 +37,19 @@ __device__ __forceinline__ uint32_t quarter_mask(const BrickGrid &bg, const Eval
   if (c.c1.z == 0.f) return 0u;
   const float mx = e.r0.x, my = e.r0.y, mz = e.r0.z;
   const float sxx = c.c0.x, syy = c.c0.y, szz = c.c0.z, sxy = c.c0.w, sxz = c.c1.x, syz = c.c1.y;
-  const float tx = extent_tol(mx, cutoff * sqrtf(sxx), bg.hx), ty = extent_tol(my, cutoff * sqrtf(syy), bg.hy);
-  const float Z0 = bg.oz + bg.hz * z0, Z1 = bg.oz + bg.hz * (z0 + 3);
+  const float tx = extent_tol(mx, cutoff * __builtin_amdgcn_sqrtf(sxx), bg.hx),
+              ty = extent_tol(my, cutoff * __builtin_amdgcn_sqrtf(syy), bg.hy);
+  const float Z0 = centre(bg.oz, bg.hz, z0), Z1 = centre(bg.oz, bg.hz, z0 + 3);
   float xzl, xzh, yzl, yzh;
   if (!extent_in_slab(mx, mz, sxx, szz, sxz, cutoff, Z0, Z1, tx, xzl, xzh)) return 0u;
   if (!extent_in_slab(my, mz, syy, szz, syz, cutoff, Z0, Z1, ty, yzl, yzh)) return 0u;
   float X0[2], X1[2], Y0[2], Y1[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    X0[h] = bg.ox + bg.hx * (x0 + 4 * h);
-    X1[h] = bg.ox + bg.hx * (x0 + 4 * h + 3);
-    Y0[h] = bg.oy + bg.hy * (y0 + 4 * h);
-    Y1[h] = bg.oy + bg.hy * (y0 + 4 * h + 3);
+    X0[h] = centre(bg.ox, bg.hx, x0 + 4 * h);
+    X1[h] = centre(bg.ox, bg.hx, x0 + 4 * h + 3);
+    Y0[h] = centre(bg.oy, bg.hy, y0 + 4 * h);
+    Y1[h] = centre(bg.oy, bg.hy, y0 + 4 * h + 3);
   }
   float xyl[2], xyh[2], yxl[2], yxh[2];
   bool okxy[2], okyx[2];
@@ -65,9 +72,9 @@ __device__ __forceinline__ uint32_t quarter_mask(const BrickGrid &bg, const Eval
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, float thr, float cutoff, float eps,
+__global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, int64_t n, float cutoff, float eps,
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
-                                                     const uint32_t *__restrict__ sorted_gid,
+                                                     const uint32_t *__restrict__ list_gid,
                                                      const uint32_t *__restrict__ brick_off, const DevStatus *st,
                                                      float *__restrict__ I, float *__restrict__ W,
                                                      unsigned long long *__restrict__ pair_count) {
@@ -75,29 +82,39 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, float thr, fl
   __shared__ EvalRec srec[kFwdChunk];
   __shared__ uint8_t smask[kFwdChunk];
   __shared__ uint16_t wlist[kFwdThreads / 64][kFwdChunk];
+  __shared__ float4 sred[kFwdThreads / 64][4][16][2];
   __shared__ unsigned long long scount[kFwdThreads / 64];
 
   const int64_t b = blockIdx.x;
   const int kx = (int)(b % bg.nbx), ky = (int)((b / bg.nbx) % bg.nby), kz = (int)(b / ((int64_t)bg.nbx * bg.nby));
   const int x0 = kx * 8, y0 = ky * 8, z0 = kz * 4;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int ix = x0 + (w & 1) * 4 + (l & 3);
-  const int iy = y0 + (w >> 1) * 4 + ((l >> 2) & 3);
-  const int iz = z0 + (l >> 4);
-  const float px = bg.ox + bg.hx * ix, py = bg.oy + bg.hy * iy, pz = bg.oz + bg.hz * iz;
+  const int grp = l >> 4, row = l & 15;
+  const int qx0 = x0 + (w & 1) * 4;
+  const int iy = y0 + (w >> 1) * 4 + (row & 3);
+  const int iz = z0 + (row >> 2);
+  const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
+  float px[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) px[k] = centre(bg.ox, bg.hx, qx0 + k);
+  const bool rowin = iy < bg.ny && iz < bg.nz;
   const uint32_t start = brick_off[b], end = brick_off[b + 1];
   const uint64_t lt = lanemask_lt();
 
-  float Wacc = 0.f, Sacc = 0.f;
+  float Wa[4] = {0.f, 0.f, 0.f, 0.f}, Sa[4] = {0.f, 0.f, 0.f, 0.f};
   uint32_t npairs = 0;
   for (uint32_t c0 = start; c0 < end; c0 += kFwdChunk) {
     const int cnt = (int)min((uint32_t)kFwdChunk, end - c0);
     if (t < cnt) {
-      uint32_t gid = sorted_gid[c0 + t];
-      EvalRec e = er[gid];
-      CullRec c = cr[gid];
-      srec[t] = e;
-      smask[t] = (uint8_t)quarter_mask(bg, e, c, cutoff, x0, y0, z0);
+      const uint32_t gid = list_gid[c0 + t];
+      if (gid < n) {
+        const EvalRec e = er[gid];
+        const CullRec c = cr[gid];
+        srec[t] = e;
+        smask[t] = (uint8_t)quarter_mask(bg, e, c, cutoff, x0, y0, z0);
+      } else {
+        smask[t] = 0;
+      }
     }
     __syncthreads();
     int nw = 0;
@@ -108,34 +125,63 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, float thr, fl
       nw += __popcll(bal);
     }
     __syncthreads();
-    for (int j = 0; j < nw; ++j) {
-      const EvalRec R = srec[wlist[w][j]];
-      float dx, dy, dz;
-      float q = qform(R, px, py, pz, dx, dy, dz);
-      bool in = q >= thr;
-      if (COUNT) {
-        npairs += in ? 1u : 0u;
-      } else {
-        float wt = fast_exp2(q + R.r1.w);
-        wt = in ? wt : 0.f;
-        Wacc += wt;
-        Sacc = fmaf(R.r0.w, wt, Sacc);
+    for (int j0 = 0; j0 < nw; j0 += 4) {
+      const int j = j0 + grp;
+      const bool valid = j < nw;
+      const EvalRec R = srec[wlist[w][valid ? j : j0]];
+      const float thr = valid ? R.r1.w : INFINITY;
+      float dy, dz, bq, cq;
+      row_coeffs(R, py, pz, dy, dz, bq, cq);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float q = row_q(R.r1.x, bq, cq, px[k] - R.r0.x);
+        const bool in = q >= thr;
+        if (COUNT) {
+          npairs += (in && rowin && qx0 + k < bg.nx) ? 1u : 0u;
+        } else {
+          float wt = fast_exp2(q);
+          wt = in ? wt : 0.f;
+          Wa[k] += wt;
+          Sa[k] = fmaf(R.r0.w, wt, Sa[k]);
+        }
       }
     }
     __syncthreads();
   }
-  const bool inside = ix < bg.nx && iy < bg.ny && iz < bg.nz;
   if (COUNT) {
-    unsigned long long v = inside ? npairs : 0u;
+    unsigned long long v = npairs;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
     if (l == 0) scount[w] = v;
     __syncthreads();
     if (t == 0) atomicAdd(pair_count, scount[0] + scount[1] + scount[2] + scount[3]);
-  } else if (inside) {
-    int64_t v = ((int64_t)iz * bg.ny + iy) * bg.nx + ix;
-    I[v] = Sacc / (Wacc + eps);
-    if (W) W[v] = Wacc;
+    return;
+  }
+  sred[w][grp][row][0] = make_float4(Wa[0], Wa[1], Wa[2], Wa[3]);
+  sred[w][grp][row][1] = make_float4(Sa[0], Sa[1], Sa[2], Sa[3]);
+  __syncthreads();
+  if (grp == 0 && rowin) {
+    float4 Wt = sred[w][0][row][0], St = sred[w][0][row][1];
+#pragma unroll
+    for (int g2 = 1; g2 < 4; ++g2) {
+      const float4 a = sred[w][g2][row][0], s2 = sred[w][g2][row][1];
+      Wt.x += a.x; Wt.y += a.y; Wt.z += a.z; Wt.w += a.w;
+      St.x += s2.x; St.y += s2.y; St.z += s2.z; St.w += s2.w;
+    }
+    const float4 It = make_float4(St.x / (Wt.x + eps), St.y / (Wt.y + eps), St.z / (Wt.z + eps), St.w / (Wt.w + eps));
+    const int64_t v0 = ((int64_t)iz * bg.ny + iy) * bg.nx + qx0;
+    if ((bg.nx & 3) == 0 && qx0 + 3 < bg.nx) {
+      *reinterpret_cast<float4 *>(I + v0) = It;
+      if (W) *reinterpret_cast<float4 *>(W + v0) = Wt;
+    } else {
+      const float iv[4] = {It.x, It.y, It.z, It.w}, wv[4] = {Wt.x, Wt.y, Wt.z, Wt.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (qx0 + k < bg.nx) {
+          I[v0 + k] = iv[k];
+          if (W) W[v0 + k] = wv[k];
+        }
+    }
   }
 }
 
@@ -146,12 +192,11 @@ __global__ void k_zero_u64(unsigned long long *p) {
 hipError_t launch_fwd(const BrickGrid &bg, float cutoff, float eps, const void *ws, const WsLayout &L, float *I,
                       float *W, hipStream_t s) {
   const char *b = (const char *)ws;
-  const float thr = -kHalfLog2e * cutoff * cutoff;
   prof_begin(s);
   k_fwd<false><<<(unsigned)bg.nbricks, kFwdThreads, 0, s>>>(
-      bg, thr, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.sorted_gid), (const uint32_t *)(b + L.brick_off), (const DevStatus *)(b + L.status), I,
-      W, nullptr);
+      bg, L.n, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.brick_off),
+      (const DevStatus *)(b + L.status), I, W, nullptr);
   prof_end(s, "render_fwd");
   return hipGetLastError();
 }
@@ -159,13 +204,12 @@ hipError_t launch_fwd(const BrickGrid &bg, float cutoff, float eps, const void *
 hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws, const WsLayout &L, int64_t *d_count,
                               hipStream_t s) {
   const char *b = (const char *)ws;
-  const float thr = -kHalfLog2e * cutoff * cutoff;
   prof_begin(s);
   k_zero_u64<<<1, 64, 0, s>>>((unsigned long long *)d_count);
   k_fwd<true><<<(unsigned)bg.nbricks, kFwdThreads, 0, s>>>(
-      bg, thr, cutoff, 0.f, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.sorted_gid), (const uint32_t *)(b + L.brick_off), (const DevStatus *)(b + L.status),
-      nullptr, nullptr, (unsigned long long *)d_count);
+      bg, L.n, cutoff, 0.f, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.brick_off),
+      (const DevStatus *)(b + L.status), nullptr, nullptr, (unsigned long long *)d_count);
   prof_end(s, "count_pairs");
   return hipGetLastError();
 }
@@ -176,21 +220,53 @@ hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws,
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
-constexpr int kBwdThreads = 64;
+constexpr int kBwdThreads = 128;
+constexpr int kBwdWindow = 2048;  // keys ordered by work per pass over the brick list
+constexpr int kBwdBuckets = 16;
 
-__global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, float thr, float cutoff, float eps,
+// Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
+__device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
+                                        int y0, int z0, int xe, int ye, int ze, int &xl, int &xh, int &yl, int &yh,
+                                        int &zl, int &zh) {
+  const float mx = R.r0.x, my = R.r0.y, mz = R.r0.z;
+  const float ex = cutoff * __builtin_amdgcn_sqrtf(C.c0.x), ey = cutoff * __builtin_amdgcn_sqrtf(C.c0.y),
+              ez = cutoff * __builtin_amdgcn_sqrtf(C.c0.z);
+  const float tx = extent_tol(mx, ex, bg.hx), ty = extent_tol(my, ey, bg.hy), tz = extent_tol(mz, ez, bg.hz);
+  world_to_index(mx - ex - tx, mx + ex + tx, bg.ox, bg.ihx, bg.nx, xl, xh);
+  world_to_index(my - ey - ty, my + ey + ty, bg.oy, bg.ihy, bg.ny, yl, yh);
+  world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.ihz, bg.nz, zl, zh);
+  xl = max(xl, x0);
+  xh = min(xh, xe);
+  yl = max(yl, y0);
+  yh = min(yh, ye);
+  zl = max(zl, z0);
+  zh = min(zh, ze);
+}
+
+// Work bucket of a key (0 = heaviest): rows x (2 + row length) of its clipped box, on a half-log2 scale.
+__device__ __forceinline__ int work_bucket(int xl, int xh, int yl, int yh, int zl, int zh) {
+  if (xl > xh || yl > yh || zl > zh) return kBwdBuckets - 1;
+  const float est = (float)((yh - yl + 1) * (zh - zl + 1) * (xh - xl + 3));
+  const int lv = (int)(2.f * log2f(est + 1.f));  // 0 .. ~17 for a 8x8x4 brick
+  return kBwdBuckets - 1 - min(lv, kBwdBuckets - 1);
+}
+
+__global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, int64_t cap, float cutoff, float eps,
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
-                                                     const uint32_t *__restrict__ sorted_gid,
-                                                     const uint32_t *__restrict__ sorted_slot,
+                                                     const uint32_t *__restrict__ list_gid,
+                                                     const uint32_t *__restrict__ list_slot,
                                                      const uint32_t *__restrict__ brick_off, const DevStatus *st,
                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
                                                      const float *__restrict__ gI, float4 *__restrict__ part) {
   if (st->overflow) return;
-  __shared__ float sc[256], sI[256];
+  __shared__ float2 sCI[256];
+  __shared__ uint16_t sorder[kBwdWindow];
+  __shared__ uint8_t sbucket[kBwdWindow];
+  __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   const int64_t b = blockIdx.x;
   const int kx = (int)(b % bg.nbx), ky = (int)((b / bg.nbx) % bg.nby), kz = (int)(b / ((int64_t)bg.nbx * bg.nby));
   const int x0 = kx * 8, y0 = ky * 8, z0 = kz * 4;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const uint32_t start = brick_off[b], end = brick_off[b + 1];
   if (start == end) return;
   for (int v = t; v < 256; v += kBwdThreads) {
@@ -201,94 +277,117 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, float thr, fl
       c = gI[g] / (Wv[g] + eps);
       iv = Iv[g];
     }
-    sc[v] = c;
-    sI[v] = iv;
+    sCI[v] = make_float2(c, iv);
   }
-  __syncthreads();
   const int xe = min(x0 + 7, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
-  for (uint32_t c0 = start; c0 < end; c0 += kBwdThreads) {
-    const uint32_t k = c0 + t;
-    if (k >= end) continue;
-    const uint32_t gid = sorted_gid[k];
-    const uint32_t slot = sorted_slot[k];
-    const EvalRec R = er[gid];
-    const CullRec C = cr[gid];
-    const float mx = R.r0.x, my = R.r0.y, mz = R.r0.z, A = R.r0.w;
-    float ex = cutoff * sqrtf(C.c0.x), ey = cutoff * sqrtf(C.c0.y), ez = cutoff * sqrtf(C.c0.z);
-    int xl, xh, yl, yh, zl, zh;
-    world_to_index(mx - ex - extent_tol(mx, ex, bg.hx), mx + ex + extent_tol(mx, ex, bg.hx), bg.ox, bg.hx, bg.nx, xl,
-                   xh);
-    world_to_index(my - ey - extent_tol(my, ey, bg.hy), my + ey + extent_tol(my, ey, bg.hy), bg.oy, bg.hy, bg.ny, yl,
-                   yh);
-    world_to_index(mz - ez - extent_tol(mz, ez, bg.hz), mz + ez + extent_tol(mz, ez, bg.hz), bg.oz, bg.hz, bg.nz, zl,
-                   zh);
-    xl = max(xl, x0);
-    xh = min(xh, xe);
-    yl = max(yl, y0);
-    yh = min(yh, ye);
-    zl = max(zl, z0);
-    zh = min(zh, ze);
-    float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
-    float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-    const float a = R.r1.x;  // Q_xx < 0
-    for (int iz = zl; iz <= zh; ++iz) {
-      const float pz = bg.oz + bg.hz * iz;
-      for (int iy = yl; iy <= yh; ++iy) {
-        const float py = bg.oy + bg.hy * iy;
-        // x-interval of q >= thr on this row: a dx^2 + bb dx + cc >= thr
-        const float dy = py - my, dz = pz - mz;
-        const float bb = fmaf(R.r2.x, dy, R.r2.y * dz);
-        const float cc = fmaf(dy, fmaf(R.r1.y, dy, R.r2.z * dz), R.r1.z * dz * dz);
-        const float disc = fmaf(bb, bb, -4.f * a * (cc - thr));
-        if (disc < 0.f) continue;
-        const float sq = sqrtf(disc);
-        const float lo = (-bb + sq) / (2.f * a), hi = (-bb - sq) / (2.f * a);
-        int xa, xb;
-        world_to_index(mx + lo - 0.02f * bg.hx, mx + hi + 0.02f * bg.hx, bg.ox, bg.hx, bg.nx, xa, xb);
-        xa = max(xa, xl);
-        xb = min(xb, xh);
-        for (int ix = xa; ix <= xb; ++ix) {
-          const float px = bg.ox + bg.hx * ix;
-          float ddx, ddy, ddz;
-          const float q = qform(R, px, py, pz, ddx, ddy, ddz);
-          if (q >= thr) {
-            const int lv = ((iz - z0) * 8 + (iy - y0)) * 8 + (ix - x0);
-            const float wt = fast_exp2(q + R.r1.w);
-            const float cp = sc[lv];
-            const float tt = cp * wt;
-            const float kap = cp * (A - sI[lv]) * wt;
-            sA += tt;
-            sk += kap;
-            const float ux = kap * ddx, uy = kap * ddy, uz = kap * ddz;
-            skx += ux;
-            sky += uy;
-            skz += uz;
-            mxx = fmaf(ux, ddx, mxx);
-            myy = fmaf(uy, ddy, myy);
-            mzz = fmaf(uz, ddz, mzz);
-            mxy = fmaf(ux, ddy, mxy);
-            mxz = fmaf(ux, ddz, mxz);
-            myz = fmaf(uy, ddz, myz);
-          }
-        }
+  for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
+    const int L = (int)min((uint32_t)kBwdWindow, end - w0);
+    // order the window's keys by estimated work, heaviest first, so that the lanes of a wave get
+    // similar loads (each key's result is independent of where it runs)
+    if (t < kBwdBuckets) bcount[t] = 0u;
+    __syncthreads();
+    for (int j = t; j < L; j += kBwdThreads) {
+      const uint32_t gid = list_gid[w0 + j];
+      int bk = kBwdBuckets - 1;
+      if (gid < n) {
+        int xl, xh, yl, yh, zl, zh;
+        key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+        bk = work_bucket(xl, xh, yl, yh, zl, zh);
+      }
+      sbucket[j] = (uint8_t)bk;
+      atomicAdd(&bcount[bk], 1u);
+    }
+    __syncthreads();
+    if (t == 0) {
+      uint32_t run = 0;
+      for (int k = 0; k < kBwdBuckets; ++k) {
+        bcursor[k] = run;
+        run += bcount[k];
       }
     }
-    float4 *o = part + (int64_t)slot * 3;
-    o[0] = make_float4(sA, sk, skx, sky);
-    o[1] = make_float4(skz, mxx, myy, mzz);
-    o[2] = make_float4(mxy, mxz, myz, 0.f);
+    __syncthreads();
+    for (int j = t; j < L; j += kBwdThreads) sorder[atomicAdd(&bcursor[sbucket[j]], 1u)] = (uint16_t)j;
+    __syncthreads();
+    for (int c0 = w * 64; c0 < L; c0 += kBwdThreads) {
+      const int p = c0 + l;
+      if (p >= L) continue;
+      const uint32_t k = w0 + sorder[p];
+      const uint32_t gid = list_gid[k];
+      const uint32_t slot = list_slot[k];
+      if (gid >= n || (int64_t)slot >= cap) continue;
+      const EvalRec R = er[gid];
+      const CullRec C = cr[gid];
+      const float mx = R.r0.x, A = R.r0.w;
+      const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
+      int xl, xh, yl, yh, zl, zh;
+      key_box(bg, R, C, cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+      float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
+      float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+      const float ninva = -__builtin_amdgcn_rcpf(a);
+      const float inv2a = -0.5f * ninva;
+      for (int iz = zl; iz <= zh; ++iz) {
+        const float pz = centre(bg.oz, bg.hz, iz);
+        for (int iy = yl; iy <= yh; ++iy) {
+          const float py = centre(bg.oy, bg.hy, iy);
+          float dy, dz, bq, cq;
+          row_coeffs(R, py, pz, dy, dz, bq, cq);
+          // the row's maximum of q is at dx* = -b / (2a); skip rows whose maximum is clearly below thr
+          const float xs = -bq * inv2a;
+          const float qmax = fmaf(0.5f * bq, xs, cq);
+          if (qmax < thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) continue;
+          const float hw = __builtin_amdgcn_sqrtf(fmaxf(qmax - thr, 0.f) * ninva) + 0.02f * bg.hx;
+          int xa, xb;
+          world_to_index(mx + xs - hw, mx + xs + hw, bg.ox, bg.ihx, bg.nx, xa, xb);
+          xa = max(xa, xl);
+          xb = min(xb, xh);
+          float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+          const int rowbase = ((iz - z0) * 8 + (iy - y0)) * 8 - x0;
+          for (int ix = xa; ix <= xb; ++ix) {
+            const float dx = centre(bg.ox, bg.hx, ix) - mx;
+            const float q = row_q(a, bq, cq, dx);
+            float wt = fast_exp2(q);
+            wt = q >= thr ? wt : 0.f;
+            const float2 ci = sCI[rowbase + ix];
+            const float tt = ci.x * wt;
+            const float kap = (A - ci.y) * tt;
+            tA += tt;
+            m0 += kap;
+            const float u = kap * dx;
+            m1 += u;
+            m2 = fmaf(u, dx, m2);
+          }
+          sA += tA;
+          sk += m0;
+          skx += m1;
+          sky = fmaf(m0, dy, sky);
+          skz = fmaf(m0, dz, skz);
+          mxx += m2;
+          mxy = fmaf(m1, dy, mxy);
+          mxz = fmaf(m1, dz, mxz);
+          const float m0dy = m0 * dy;
+          myy = fmaf(m0dy, dy, myy);
+          myz = fmaf(m0dy, dz, myz);
+          mzz = fmaf(m0 * dz, dz, mzz);
+        }
+      }
+      float4 *o = part + (int64_t)slot * 3;
+      o[0] = make_float4(sA, sk, skx, sky);
+      o[1] = make_float4(skz, mxx, myy, mzz);
+      o[2] = make_float4(mxy, mxz, myz, 0.f);
+    }
+    __syncthreads();
   }
 }
 
 hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
                       const float *W, const float *dLdI, hipStream_t s) {
   char *b = (char *)ws;
-  const float thr = -kHalfLog2e * cutoff * cutoff;
   prof_begin(s);
   k_bwd<<<(unsigned)bg.nbricks, kBwdThreads, 0, s>>>(
-      bg, thr, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.sorted_gid), (const uint32_t *)(b + L.sorted_slot), (const uint32_t *)(b + L.brick_off),
-      (const DevStatus *)(b + L.status), I, W, dLdI, (float4 *)(b + L.partials));
+      bg, L.n, L.cap, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.list_slot),
+      (const uint32_t *)(b + L.brick_off), (const DevStatus *)(b + L.status), I, W, dLdI,
+      (float4 *)(b + L.partials));
   prof_end(s, "render_bwd");
   return hipGetLastError();
 }

@@ -52,7 +52,7 @@ def test_workspace_grows_with_n_and_capacity():
     b = gs.gs_workspace_size(2000, g, o, 0)
     c = gs.gs_workspace_size(2000, g, o, 100000)
     assert 0 < a < b < c
-    # per key: 6 uint32 arrays + 48 B of partials, plus histogram share
-    assert c - b >= 100000 * (6 * 4 + 48)
+    # per key: the two uint32 brick lists + 48 B of partial sums
+    assert c - b >= 100000 * (2 * 4 + 48)
     assert gs.gs_loss_scratch_bytes(1) >= 4
     assert gs.gs_loss_scratch_bytes(10 ** 7) >= 4 * (10 ** 7 // 4096)

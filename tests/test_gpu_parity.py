@@ -283,3 +283,24 @@ def test_fit_step_matches_oracle():
         big = np.abs(gr[k]) > 1e-2 * np.sqrt(np.mean(gr[k] ** 2))
         np.testing.assert_allclose(got[big], newp[k][big], rtol=1e-6, atol=1e-3 * lr[k], err_msg=k)
     assert int(st.step.item()) == 1
+
+
+def test_crowded_bricks_long_lists():
+    """Thousands of Gaussians over a few bricks: brick lists longer than the in-LDS sort holds."""
+    rng = np.random.default_rng(31)
+    n, dims = 6000, (16, 16, 8)
+    p = synth.gaussians_uniform(31, n, dims, ls_mean=math.log(2.5), ls_std=0.2)
+    p["mu"] = (np.array([8.0, 8.0, 4.0]) + rng.normal(0, 1.5, (n, 3))).astype(np.float32)
+    grid = oracle.Grid(*dims)
+    p = cases.condition(p, grid, seed=32, jitter=(0.3, 0.3, 0.3))
+    say("crowded", grid.shape, n)
+    g, ggrid, opts, bins, I, W = gpu_render(p, grid)
+    Io, Wo, _ = oracle.render(p, grid)
+    assert_fwd_close(np64(W), Wo, "crowded W")
+    assert_fwd_close(np64(I), Io, "crowded I")
+    T = synth.uniform_volume(9, dims)
+    _, go = oracle.mse_loss(Io, T)
+    gg = gpu_grads(g, ggrid, opts, bins, I, W, torch.from_numpy(go.astype(np.float32)).cuda())
+    ref = oracle.grad(p, grid, np64(I), np64(W), go.astype(np.float32).astype(np.float64))
+    for k in ("mu", "amp"):
+        assert_grad_close(gg[k], ref[k], f"crowded d_{k}")
