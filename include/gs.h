@@ -123,9 +123,10 @@ typedef struct {
 /* Caller-owned per-step buffers of the fit (device). */
 typedef struct {
   float *I, *W;        /* [nz][ny][nx] forward outputs (kept for the backward) */
-  float *dL_dI;        /* [nz][ny][nx] */
-  gs_grads_t grads;    /* [n]-sized gradient arrays; all of d_mu, d_log_scale, d_quat, d_amp required */
-  void *scratch;       /* >= gs_loss_scratch_bytes(nx*ny*nz) bytes */
+  float *dL_dI;        /* [nz][ny][nx]; used only when zdown differs from the brick depth bz (else
+                          the loss is fused into the backward and this may be NULL) */
+  gs_grads_t grads;    /* [n]-sized gradient arrays (written); d_mu, d_log_scale, d_quat, d_amp required */
+  void *scratch;       /* >= gs_fit_scratch_bytes(&hr) bytes */
   size_t scratch_bytes;
   float *loss;         /* device scalar: the step's loss */
 } gs_fit_buffers_t;
@@ -146,6 +147,9 @@ int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, i
 
 /* Bytes of scratch for the loss reductions over nvox voxels. */
 size_t gs_loss_scratch_bytes(int64_t nvox);
+
+/* Bytes of scratch for gs_fit_step on the HR grid hr (0 for an invalid grid). */
+size_t gs_fit_scratch_bytes(const gs_grid_t *hr);
 
 /* 1 if the brick shape is supported by the kernels of this build, else 0. */
 int gs_brick_supported(int32_t bx, int32_t by, int32_t bz);
@@ -207,9 +211,11 @@ int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_ada
                  void *stream);
 
 /* One step of the per-scan zero-shot fit (§3.3 "end-to-end", Fig. 1): bin -> render -> z-mean ->
- * L1 vs lr_obs -> backward -> Adam.  lr_obs: device [hr.nz/zdown][hr.ny][hr.nx].  No host
- * synchronisation; check gs_status() for capacity overflow (the step then leaves the parameters
- * unchanged). */
+ * L1 vs lr_obs -> backward -> Adam.  lr_obs: device [hr.nz/zdown][hr.ny][hr.nx].  Writes I, W, the
+ * gradients and the loss; updates the parameters, the moments and *step.  When zdown equals the
+ * brick depth the loss is computed inside the backward kernel and the gradient reduction is fused
+ * with Adam.  No host synchronisation; check gs_status() for capacity overflow (the step then leaves
+ * the parameters and *step unchanged). */
 int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
                 const gs_fit_buffers_t *buf, void *stream);
 

@@ -1,9 +1,10 @@
 """Build libgs.so (HIP for gfx950) in-tree: one object per source, then a shared library.
 
-Every HIP source is compiled with packed-FP32 instruction selection switched off.  The binning
-and rendering sources are also compiled without floating-point contraction (fused multiply-adds
-are written explicitly), so that the count and emit passes of the binning round identically and
-the forward, backward and pair-count kernels take the same inclusion decision for every pair.
+Every HIP source is compiled with packed-FP32 instruction selection switched off and without
+floating-point contraction (fused multiply-adds are written explicitly), so that the count and emit
+passes of the binning round identically, the forward, backward and pair-count kernels take the same
+inclusion decision for every pair, and the standalone and fused fit losses take the same sign
+decisions.
 """
 import os
 import shutil
@@ -22,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
 SOURCES = {
     "bin.hip": ["-ffp-contract=off"],
     "render.hip": ["-ffp-contract=off"],
-    "fit.hip": [],
+    "fit.hip": ["-ffp-contract=off"],
     "api.cpp": ["-x", "hip"],
 }
 

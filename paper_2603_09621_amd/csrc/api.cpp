@@ -334,22 +334,51 @@ int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_ada
   return e == hipSuccess ? GS_OK : hip_fail(e, "adam");
 }
 
+size_t gs_fit_scratch_bytes(const gs_grid_t *hr) {
+  if (!hr || hr->nx <= 0 || hr->ny <= 0 || hr->nz <= 0) return 0;
+  const int64_t nvox = (int64_t)hr->nx * hr->ny * hr->nz;
+  const int64_t nbricks = (int64_t)((hr->nx + 7) / 8) * ((hr->ny + 7) / 8) * ((hr->nz + 3) / 4);
+  return sizeof(float) * (size_t)std::max<int64_t>(std::max(1, loss_blocks(nvox)), nbricks);
+}
+
 int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
                 const gs_fit_buffers_t *buf, void *stream) {
   if (!fo || !buf || !lr_obs) return fail(GS_ERR_INVALID_ARG, "fit opts, buffers and lr_obs are required");
   int rc = check_state(st, &buf->grads);
   if (rc) return rc;
   if (fo->loss != 0) return fail(GS_ERR_UNSUPPORTED, "only loss 0 (L1 on the z-mean) is supported");
+  if ((rc = check_grid(&fo->hr))) return rc;
+  if (fo->zdown <= 0 || fo->hr.nz % fo->zdown != 0)
+    return fail(GS_ERR_INVALID_ARG, "hr.nz must be a positive multiple of zdown");
   gs_gaussians_t g{st->n, st->mu, st->log_scale, st->quat, st->amp, st->relax};
   hipStream_t s = (hipStream_t)stream;
-  if (!buf->I || !buf->W || !buf->dL_dI || !buf->loss) return fail(GS_ERR_INVALID_ARG, "fit buffers incomplete");
+  if (!buf->I || !buf->W || !buf->loss || !buf->scratch) return fail(GS_ERR_INVALID_ARG, "fit buffers incomplete");
+  if (buf->scratch_bytes < gs_fit_scratch_bytes(&fo->hr))
+    return fail(GS_ERR_INVALID_ARG, "fit scratch too small: %zu bytes given, %zu needed", buf->scratch_bytes,
+                gs_fit_scratch_bytes(&fo->hr));
   if ((rc = gs_bin(&g, &fo->hr, &fo->opts, bins, stream))) return rc;
   if ((rc = gs_render_fwd(&g, &fo->hr, &fo->opts, bins, buf->I, buf->W, stream))) return rc;
+  BrickGrid bg;
+  make_brick_grid(&fo->hr, &fo->opts, &bg);
+  const WsLayout L = make_layout(st->n, bg, bins->key_capacity);
+  hipError_t e;
+  if (fo->zdown == fo->opts.bz) {
+    // the z-mean groups coincide with the brick's z extent: loss fused into the backward's staging,
+    // gradient reduction fused with Adam
+    float *loss_part = (float *)buf->scratch;
+    const int64_t nlr = (int64_t)fo->hr.nx * fo->hr.ny * (fo->hr.nz / fo->zdown);
+    e = launch_bwd_fit(bg, fo->opts.cutoff, fo->opts.eps, bins->ws, L, buf->I, buf->W, lr_obs, loss_part, s);
+    if (e != hipSuccess) return hip_fail(e, "render_bwd");
+    e = launch_reduce_adam(*st, bins->ws, L, buf->grads, fo->adam, loss_part, bg.nbricks, (float)(1.0 / (double)nlr),
+                           buf->loss, s);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_adam");
+  }
+  if (!buf->dL_dI) return fail(GS_ERR_INVALID_ARG, "dL_dI is required when zdown differs from the brick depth");
   if ((rc = gs_loss_l1_zmean(buf->I, lr_obs, &fo->hr, fo->zdown, buf->dL_dI, buf->loss, buf->scratch,
                              buf->scratch_bytes, stream)))
     return rc;
   if ((rc = gs_render_bwd(&g, &fo->hr, &fo->opts, bins, buf->I, buf->W, buf->dL_dI, &buf->grads, stream))) return rc;
-  hipError_t e = launch_adam(*st, buf->grads, fo->adam, bins->ws, s);
+  e = launch_adam(*st, buf->grads, fo->adam, bins->ws, s);
   return e == hipSuccess ? GS_OK : hip_fail(e, "adam");
 }
 

@@ -4,6 +4,8 @@
 // block sums the partials in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "geom.h"
 #include "gs_internal.h"
 
@@ -116,7 +118,8 @@ struct AdamGroups {
 };
 
 __global__ void k_adam(AdamGroups G, int ngroups, int64_t total, float *__restrict__ m, float *__restrict__ v, float b1,
-                       float b2, float eps, const int32_t *__restrict__ step, const DevStatus *st) {
+                       float b2, float eps, float lnb1, float lnb2, const int32_t *__restrict__ step,
+                       const DevStatus *st) {
   if (st && st->overflow) return;
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -124,7 +127,7 @@ __global__ void k_adam(AdamGroups G, int ngroups, int64_t total, float *__restri
   while (gi < ngroups - 1 && e >= G.end[gi]) ++gi;
   const int64_t j = e - (gi ? G.end[gi - 1] : 0);
   const float t = (float)(*step + 1);
-  const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+  const float bc1 = -expm1f(t * lnb1), bc2 = -expm1f(t * lnb2);
   const float g = G.g[gi][j];
   const float mm = fmaf(b1, m[e], (1.f - b1) * g);
   const float vv = fmaf(b2, v[e], (1.f - b2) * g * g);
@@ -158,8 +161,9 @@ hipError_t launch_adam(const gs_fit_state_t &st, const gs_grads_t &gr, const gs_
   // the moment arrays keep the fixed 12n layout: relax moments (if any) start at 11n
   const DevStatus *dst = (const DevStatus *)ws_status;
   prof_begin(s);
-  k_adam<<<(unsigned)((acc + 255) / 256), 256, 0, s>>>(G, ng, acc, st.m, st.v, hp.beta1, hp.beta2, hp.eps, st.step,
-                                                       dst);
+  k_adam<<<(unsigned)((acc + 255) / 256), 256, 0, s>>>(G, ng, acc, st.m, st.v, hp.beta1, hp.beta2, hp.eps,
+                                                       (float)std::log((double)hp.beta1),
+                                                       (float)std::log((double)hp.beta2), st.step, dst);
   k_step_inc<<<1, 64, 0, s>>>(st.step, dst);
   prof_end(s, "adam");
   return hipGetLastError();

@@ -98,6 +98,11 @@ hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, co
                       const float *W, const float *dLdI, hipStream_t s);
 hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
                                hipStream_t s);
+hipError_t launch_bwd_fit(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
+                          const float *W, const float *obs, float *loss_part, hipStream_t s);
+hipError_t launch_reduce_adam(const gs_fit_state_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
+                              const gs_adam_t &hp, const float *loss_part, int64_t nb, float loss_scale, float *loss,
+                              hipStream_t s);
 hipError_t launch_loss_mse(const float *I, const float *T, int64_t nvox, float *g, float *loss, void *scratch,
                            hipStream_t s);
 hipError_t launch_loss_l1z(const float *I, const float *obs, int nx, int ny, int nz, int f, float *g, float *loss,

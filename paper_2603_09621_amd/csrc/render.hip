@@ -12,14 +12,16 @@
 //
 // Backward: one workgroup of two waves per brick, one Gaussian per lane.  The brick's per-voxel
 // factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by
-// their estimated work (heaviest first) so that the lanes of a wave carry similar loads; each lane
-// walks the rows of its Gaussian's box inside the brick, restricted per row to the x-interval of the
-// ellipsoid, and
-// accumulates per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
+// their number of rows in the brick so that the lanes of a wave run the same number of iterations;
+// each lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
+// maximum exponent is below the cutoff, evaluates the 8 voxels of a row unrolled, and accumulates
+// per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
 // folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.
 // The sums of each (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel
 // reduces each Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 #include "geom.h"
 #include "gs_internal.h"
@@ -222,7 +224,8 @@ hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws,
 
 constexpr int kBwdThreads = 128;
 constexpr int kBwdWindow = 2048;  // keys ordered by work per pass over the brick list
-constexpr int kBwdBuckets = 16;
+constexpr int kBwdBuckets = 34;   // rows per key in a brick: 0 .. 32 (bucket 0 = 32 rows)
+constexpr int kRowPad = 9;        // LDS row stride in voxels (8 + 1 pad: rows of a wave hit different banks)
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
 __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
@@ -243,23 +246,22 @@ __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, c
   zh = min(zh, ze);
 }
 
-// Work bucket of a key (0 = heaviest): rows x (2 + row length) of its clipped box, on a half-log2 scale.
-__device__ __forceinline__ int work_bucket(int xl, int xh, int yl, int yh, int zl, int zh) {
-  if (xl > xh || yl > yh || zl > zh) return kBwdBuckets - 1;
-  const float est = (float)((yh - yl + 1) * (zh - zl + 1) * (xh - xl + 3));
-  const int lv = (int)(2.f * log2f(est + 1.f));  // 0 .. ~17 for a 8x8x4 brick
-  return kBwdBuckets - 1 - min(lv, kBwdBuckets - 1);
-}
-
+// FIT: the fit's loss is fused into the staging.  The brick's 4 z slices are one group of the
+// z-mean (LR slice z0 / 4): per (x, y) column, LR = (((I0 + I1) + I2) + I3) * 1/4 (the loss kernel's
+// order), dL/dI = sign(LR - obs) * gscale on the column's 4 voxels, and the brick's sum of |LR - obs|
+// goes to loss_part[brick] (also for bricks without Gaussians).  Otherwise dL/dI is read from gI.
+template <bool FIT>
 __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, int64_t cap, float cutoff, float eps,
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                      const uint32_t *__restrict__ list_gid,
                                                      const uint32_t *__restrict__ list_slot,
                                                      const uint32_t *__restrict__ brick_off, const DevStatus *st,
                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
-                                                     const float *__restrict__ gI, float4 *__restrict__ part) {
+                                                     const float *__restrict__ gI, const float *__restrict__ obs,
+                                                     float gscale, float *__restrict__ loss_part,
+                                                     float4 *__restrict__ part) {
   if (st->overflow) return;
-  __shared__ float2 sCI[256];
+  __shared__ float2 sCI[32 * kRowPad];
   __shared__ uint16_t sorder[kBwdWindow];
   __shared__ uint8_t sbucket[kBwdWindow];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
@@ -268,22 +270,57 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
   const int x0 = kx * 8, y0 = ky * 8, z0 = kz * 4;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const uint32_t start = brick_off[b], end = brick_off[b + 1];
-  if (start == end) return;
-  for (int v = t; v < 256; v += kBwdThreads) {
-    int gx = x0 + (v & 7), gy = y0 + ((v >> 3) & 7), gz = z0 + (v >> 6);
-    float c = 0.f, iv = 0.f;
-    if (gx < bg.nx && gy < bg.ny && gz < bg.nz) {
-      int64_t g = ((int64_t)gz * bg.ny + gy) * bg.nx + gx;
-      c = gI[g] / (Wv[g] + eps);
-      iv = Iv[g];
+  if (FIT) {
+    // 64 columns of 4 voxels; threads 0..63 (wave 0) own one column each
+    float absd = 0.f;
+    if (t < 64) {
+      const int lx = t & 7, ly = t >> 3;
+      const int gx = x0 + lx, gy = y0 + ly;
+      float c4[4] = {0.f, 0.f, 0.f, 0.f}, i4[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gx < bg.nx && gy < bg.ny) {
+        const int64_t plane = (int64_t)bg.nx * bg.ny;
+        const int64_t g0 = ((int64_t)z0 * bg.ny + gy) * bg.nx + gx;
+#pragma unroll
+        for (int z = 0; z < 4; ++z) i4[z] = Iv[g0 + z * plane];
+        const float lr = (((i4[0] + i4[1]) + i4[2]) + i4[3]) * 0.25f;
+        const float d = lr - obs[((int64_t)(z0 >> 2) * bg.ny + gy) * bg.nx + gx];
+        const float sg = d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
+        absd = fabsf(d);
+#pragma unroll
+        for (int z = 0; z < 4; ++z) c4[z] = sg / (Wv[g0 + z * plane] + eps);
+      }
+#pragma unroll
+      for (int z = 0; z < 4; ++z) sCI[(z * 8 + ly) * kRowPad + lx] = make_float2(c4[z], i4[z]);
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) absd += __shfl_down(absd, d, 64);
+      if (t == 0) loss_part[b] = absd;
     }
-    sCI[v] = make_float2(c, iv);
+  } else {
+    if (start == end) return;
+    // per voxel of the brick: c = dL/dI / (W + eps) and I; zero outside the grid, so that voxels
+    // beyond the grid's edge contribute nothing
+    for (int v = t; v < 256; v += kBwdThreads) {
+      const int lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+      const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+      float c = 0.f, iv = 0.f;
+      if (gx < bg.nx && gy < bg.ny && gz < bg.nz) {
+        const int64_t g = ((int64_t)gz * bg.ny + gy) * bg.nx + gx;
+        c = gI[g] / (Wv[g] + eps);
+        iv = Iv[g];
+      }
+      sCI[(lz * 8 + ly) * kRowPad + lx] = make_float2(c, iv);
+    }
   }
+  if (start == end) return;
+  float px[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) px[k] = centre(bg.ox, bg.hx, x0 + k);
   const int xe = min(x0 + 7, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
   for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
     const int L = (int)min((uint32_t)kBwdWindow, end - w0);
-    // order the window's keys by estimated work, heaviest first, so that the lanes of a wave get
-    // similar loads (each key's result is independent of where it runs)
+    // order the window's keys by their number of rows in the brick, most first, so that the lanes of
+    // a wave run the same number of row iterations (each key's result is independent of where it
+    // runs, so the order does not change any result)
     if (t < kBwdBuckets) bcount[t] = 0u;
     __syncthreads();
     for (int j = t; j < L; j += kBwdThreads) {
@@ -292,7 +329,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
       if (gid < n) {
         int xl, xh, yl, yh, zl, zh;
         key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
-        bk = work_bucket(xl, xh, yl, yh, zl, zh);
+        if (xl <= xh && yl <= yh && zl <= zh) bk = 32 - (yh - yl + 1) * (zh - zl + 1);
       }
       sbucket[j] = (uint8_t)bk;
       atomicAdd(&bcount[bk], 1u);
@@ -323,31 +360,28 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
       key_box(bg, R, C, cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-      const float ninva = -__builtin_amdgcn_rcpf(a);
-      const float inv2a = -0.5f * ninva;
-      for (int iz = zl; iz <= zh; ++iz) {
-        const float pz = centre(bg.oz, bg.hz, iz);
-        for (int iy = yl; iy <= yh; ++iy) {
-          const float py = centre(bg.oy, bg.hy, iy);
-          float dy, dz, bq, cq;
-          row_coeffs(R, py, pz, dy, dz, bq, cq);
-          // the row's maximum of q is at dx* = -b / (2a); skip rows whose maximum is clearly below thr
-          const float xs = -bq * inv2a;
-          const float qmax = fmaf(0.5f * bq, xs, cq);
-          if (qmax < thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) continue;
-          const float hw = __builtin_amdgcn_sqrtf(fmaxf(qmax - thr, 0.f) * ninva) + 0.02f * bg.hx;
-          int xa, xb;
-          world_to_index(mx + xs - hw, mx + xs + hw, bg.ox, bg.ihx, bg.nx, xa, xb);
-          xa = max(xa, xl);
-          xb = min(xb, xh);
+      const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
+      const int ny_k = yh - yl + 1;
+      const int nrows = (xl <= xh && yl <= yh && zl <= zh) ? ny_k * (zh - zl + 1) : 0;
+      int iy = yl, iz = zl;
+      for (int r = 0; r < nrows; ++r) {
+        const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
+        float dy, dz, bq, cq;
+        row_coeffs(R, py, pz, dy, dz, bq, cq);
+        // the row's maximum of q is at dx* = -b / (2a); rows whose maximum is clearly below the
+        // cutoff hold no pair
+        const float xs = -bq * inv2a;
+        const float qmax = fmaf(0.5f * bq, xs, cq);
+        if (qmax >= thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) {
+          const int rb = ((iz - z0) * 8 + (iy - y0)) * kRowPad;
           float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
-          const int rowbase = ((iz - z0) * 8 + (iy - y0)) * 8 - x0;
-          for (int ix = xa; ix <= xb; ++ix) {
-            const float dx = centre(bg.ox, bg.hx, ix) - mx;
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const float dx = px[kk] - mx;
             const float q = row_q(a, bq, cq, dx);
             float wt = fast_exp2(q);
             wt = q >= thr ? wt : 0.f;
-            const float2 ci = sCI[rowbase + ix];
+            const float2 ci = sCI[rb + kk];
             const float tt = ci.x * wt;
             const float kap = (A - ci.y) * tt;
             tA += tt;
@@ -369,6 +403,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
           myz = fmaf(m0dy, dz, myz);
           mzz = fmaf(m0 * dz, dz, mzz);
         }
+        if (++iy > yh) {
+          iy = yl;
+          ++iz;
+        }
       }
       float4 *o = part + (int64_t)slot * 3;
       o[0] = make_float4(sA, sk, skx, sky);
@@ -383,11 +421,24 @@ hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, co
                       const float *W, const float *dLdI, hipStream_t s) {
   char *b = (char *)ws;
   prof_begin(s);
-  k_bwd<<<(unsigned)bg.nbricks, kBwdThreads, 0, s>>>(
+  k_bwd<false><<<(unsigned)bg.nbricks, kBwdThreads, 0, s>>>(
       bg, L.n, L.cap, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.list_slot),
-      (const uint32_t *)(b + L.brick_off), (const DevStatus *)(b + L.status), I, W, dLdI,
-      (float4 *)(b + L.partials));
+      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.list_slot), (const uint32_t *)(b + L.brick_off),
+      (const DevStatus *)(b + L.status), I, W, dLdI, nullptr, 0.f, nullptr, (float4 *)(b + L.partials));
+  prof_end(s, "render_bwd");
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_fit(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
+                          const float *W, const float *obs, float *loss_part, hipStream_t s) {
+  char *b = (char *)ws;
+  const int64_t nlr = (int64_t)bg.nx * bg.ny * (bg.nz / 4);
+  const float gscale = (float)(1.0 / (4.0 * (double)nlr));
+  prof_begin(s);
+  k_bwd<true><<<(unsigned)bg.nbricks, kBwdThreads, 0, s>>>(
+      bg, L.n, L.cap, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.list_slot), (const uint32_t *)(b + L.brick_off),
+      (const DevStatus *)(b + L.status), I, W, nullptr, obs, gscale, loss_part, (float4 *)(b + L.partials));
   prof_end(s, "render_bwd");
   return hipGetLastError();
 }
@@ -398,29 +449,51 @@ hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, co
 //   P = R D R^T, D = diag(exp(-2 s)):  ds_k = -2 D_k (R^T G R)_kk,  dR = 2 G R D,
 //   dqhat from dR through the rotation of a unit quaternion, dq = (dqhat - (qhat.dqhat) qhat) / |q|.
 
-__global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const float *__restrict__ ls,
-                               const float *__restrict__ relax, const uint32_t *__restrict__ off,
-                               const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
-                               float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
-                               float *__restrict__ d_relax) {
-  if (st->overflow) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t s0 = off[i], s1 = off[i + 1];
-  float4 a0 = make_float4(0, 0, 0, 0), a1 = a0, a2 = a0;
-  for (uint32_t s = s0; s < s1; ++s) {
-    const float4 p0 = part[(int64_t)s * 3], p1 = part[(int64_t)s * 3 + 1], p2 = part[(int64_t)s * 3 + 2];
-    a0.x += p0.x; a0.y += p0.y; a0.z += p0.z; a0.w += p0.w;
-    a1.x += p1.x; a1.y += p1.y; a1.z += p1.z; a1.w += p1.w;
-    a2.x += p2.x; a2.y += p2.y; a2.z += p2.z;
+// Per-Gaussian sums of the brick partials, for the 256 consecutive Gaussians of a block: the
+// block's partials (contiguous, since keys are numbered Gaussian-major) are loaded cooperatively
+// through LDS in chunks, and each thread adds its own Gaussian's partials in slot order.
+constexpr int kRedThreads = 256;
+constexpr int kRedChunk = 768;  // partials per LDS chunk (36 KB)
+
+__device__ __forceinline__ void block_partial_sums(int64_t i0, int64_t n, const uint32_t *__restrict__ off,
+                                                   const float4 *__restrict__ part, float4 *sp, float4 &a0,
+                                                   float4 &a1, float4 &a2) {
+  const int t = threadIdx.x;
+  const int64_t i = i0 + t;
+  const int64_t iend = min(i0 + (int64_t)kRedThreads, n);
+  const uint32_t sb = off[i0], se = off[iend];
+  const uint32_t my0 = i < n ? off[i] : se, my1 = i < n ? off[i + 1] : se;
+  a0 = make_float4(0, 0, 0, 0);
+  a1 = a0;
+  a2 = a0;
+  for (uint32_t c0 = sb; c0 < se; c0 += kRedChunk) {
+    const int m = (int)min((uint32_t)kRedChunk, se - c0);
+    __syncthreads();
+    for (int k = t; k < 3 * m; k += kRedThreads) sp[k] = part[(int64_t)c0 * 3 + k];
+    __syncthreads();
+    const uint32_t lo = max(my0, c0), hi = min(my1, c0 + (uint32_t)m);
+    for (uint32_t s = lo; s < hi; ++s) {
+      const int q = (int)(s - c0) * 3;
+      const float4 p0 = sp[q], p1 = sp[q + 1], p2 = sp[q + 2];
+      a0.x += p0.x; a0.y += p0.y; a0.z += p0.z; a0.w += p0.w;
+      a1.x += p1.x; a1.y += p1.y; a1.z += p1.z; a1.w += p1.w;
+      a2.x += p2.x; a2.y += p2.y; a2.z += p2.z;
+    }
   }
+}
+
+// Gradient of Gaussian i from its summed partials (a0, a1, a2) and its raw parameters.
+// g[0..2] = dmu, g[3..5] = dlog_scale, g[6..9] = dquat, g[10] = dA, g[11] = dr (r = 1 if relax NULL).
+__device__ __forceinline__ void gauss_grad(int64_t i, const float *__restrict__ quat, const float *__restrict__ ls,
+                                           const float *__restrict__ relax, float4 a0, float4 a1, float4 a2,
+                                           float g[12]) {
   const float sA = a0.x, sk = a0.y;
   const float kd[3] = {a0.z, a0.w, a1.x};
   // G = dL/dP = -1/2 M (symmetric)
   const float G[3][3] = {{-0.5f * a1.y, -0.5f * a2.x, -0.5f * a2.y},
                          {-0.5f * a2.x, -0.5f * a1.z, -0.5f * a2.z},
                          {-0.5f * a2.y, -0.5f * a2.z, -0.5f * a1.w}};
-  float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
+  const float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
   float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   if (!(qn > 0.f) || !isfinite(qn)) qn = 1.f;
   const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
@@ -433,43 +506,165 @@ __global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const 
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) P[r][c] = R[r][0] * D[0] * R[c][0] + R[r][1] * D[1] * R[c][1] + R[r][2] * D[2] * R[c][2];
-  if (d_mu) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) d_mu[3 * i + r] = P[r][0] * kd[0] + P[r][1] * kd[1] + P[r][2] * kd[2];
-  }
+  for (int r = 0; r < 3; ++r) g[r] = P[r][0] * kd[0] + P[r][1] * kd[1] + P[r][2] * kd[2];
   float GR[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) GR[r][c] = G[r][0] * R[0][c] + G[r][1] * R[1][c] + G[r][2] * R[2][c];
-  if (d_ls) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float rtgr = R[0][k] * GR[0][k] + R[1][k] * GR[1][k] + R[2][k] * GR[2][k];
-      d_ls[3 * i + k] = -2.f * D[k] * rtgr;
-    }
+  for (int k = 0; k < 3; ++k) {
+    const float rtgr = R[0][k] * GR[0][k] + R[1][k] * GR[1][k] + R[2][k] * GR[2][k];
+    g[3 + k] = -2.f * D[k] * rtgr;
+  }
+  float dR[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dR[r][c] = 2.f * GR[r][c] * D[c];
+  const float gw = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+  const float gx = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] +
+                          z * dR[2][0] + w * dR[2][1] - 2.f * x * dR[2][2]);
+  const float gy = 2.f * (-2.f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
+                          w * dR[2][0] + z * dR[2][1] - 2.f * y * dR[2][2]);
+  const float gz = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
+                          y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+  const float dot = w * gw + x * gx + y * gy + z * gz;
+  g[6] = (gw - dot * w) / qn;
+  g[7] = (gx - dot * x) / qn;
+  g[8] = (gy - dot * y) / qn;
+  g[9] = (gz - dot * z) / qn;
+  g[10] = sA;
+  g[11] = relax ? sk / relax[i] : sk;
+}
+
+__global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const float *__restrict__ ls,
+                               const float *__restrict__ relax, const uint32_t *__restrict__ off,
+                               const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
+                               float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
+                               float *__restrict__ d_relax) {
+  if (st->overflow) return;
+  __shared__ float4 sp[3 * kRedChunk];
+  const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
+  float4 a0, a1, a2;
+  block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
+  if (i >= n) return;
+  float g[12];
+  gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
+  if (d_mu) {
+    d_mu[3 * i] = g[0];
+    d_mu[3 * i + 1] = g[1];
+    d_mu[3 * i + 2] = g[2];
+  }
+  if (d_ls) {
+    d_ls[3 * i] = g[3];
+    d_ls[3 * i + 1] = g[4];
+    d_ls[3 * i + 2] = g[5];
   }
   if (d_quat) {
-    float dR[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) dR[r][c] = 2.f * GR[r][c] * D[c];
-    float gw = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
-    float gx = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
-                      w * dR[2][1] - 2.f * x * dR[2][2]);
-    float gy = 2.f * (-2.f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
-                      w * dR[2][0] + z * dR[2][1] - 2.f * y * dR[2][2]);
-    float gz = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
-                      y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
-    float dot = w * gw + x * gx + y * gy + z * gz;
-    d_quat[4 * i] = (gw - dot * w) / qn;
-    d_quat[4 * i + 1] = (gx - dot * x) / qn;
-    d_quat[4 * i + 2] = (gy - dot * y) / qn;
-    d_quat[4 * i + 3] = (gz - dot * z) / qn;
+    d_quat[4 * i] = g[6];
+    d_quat[4 * i + 1] = g[7];
+    d_quat[4 * i + 2] = g[8];
+    d_quat[4 * i + 3] = g[9];
   }
-  if (d_amp) d_amp[i] = sA;
-  if (d_relax) d_relax[i] = relax ? sk / relax[i] : sk;
+  if (d_amp) d_amp[i] = g[10];
+  if (d_relax) d_relax[i] = g[11];
+}
+
+// Fused gradient + Adam for the fit step: the gradient of Gaussian i (as k_reduce_chain, also
+// written to the gradient outputs) and the bias-corrected Adam update of its 12 parameters, moments
+// in the group layout mu (3n), log_scale (3n), quat (4n), amp (n), relax (n).  Step t = *step + 1.
+struct AdamArgs {
+  float lr[5];
+  float b1, b2, eps;
+  float lnb1, lnb2;  // ln of the betas: the bias corrections are 1 - beta^t = -expm1(t ln beta)
+};
+
+__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, float lr, float b1, float b2, float eps,
+                                         float bc1, float bc2) {
+  const float mm = fmaf(b1, m, (1.f - b1) * g);
+  const float vv = fmaf(b2, v, (1.f - b2) * g * g);
+  m = mm;
+  v = vv;
+  if (lr != 0.f) p -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+__global__ void k_reduce_adam(int64_t n, float *__restrict__ mu, float *__restrict__ ls, float *__restrict__ quat,
+                              float *__restrict__ amp, float *__restrict__ relax, const uint32_t *__restrict__ off,
+                              const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
+                              float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
+                              float *__restrict__ d_relax, float *__restrict__ m, float *__restrict__ v,
+                              const int32_t *__restrict__ step, AdamArgs h) {
+  if (st->overflow) return;
+  __shared__ float4 sp[3 * kRedChunk];
+  const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
+  float4 a0, a1, a2;
+  block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
+  if (i >= n) return;
+  float g[12];
+  gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
+  const float t = (float)(*step + 1);
+  const float bc1 = -expm1f(t * h.lnb1), bc2 = -expm1f(t * h.lnb2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d_mu[3 * i + a] = g[a];
+    d_ls[3 * i + a] = g[3 + a];
+    adam_one(mu[3 * i + a], g[a], m[3 * i + a], v[3 * i + a], h.lr[0], h.b1, h.b2, h.eps, bc1, bc2);
+    adam_one(ls[3 * i + a], g[3 + a], m[3 * n + 3 * i + a], v[3 * n + 3 * i + a], h.lr[1], h.b1, h.b2, h.eps, bc1,
+             bc2);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    d_quat[4 * i + a] = g[6 + a];
+    adam_one(quat[4 * i + a], g[6 + a], m[6 * n + 4 * i + a], v[6 * n + 4 * i + a], h.lr[2], h.b1, h.b2, h.eps, bc1,
+             bc2);
+  }
+  d_amp[i] = g[10];
+  adam_one(amp[i], g[10], m[10 * n + i], v[10 * n + i], h.lr[3], h.b1, h.b2, h.eps, bc1, bc2);
+  if (relax) {
+    if (d_relax) d_relax[i] = g[11];
+    adam_one(relax[i], g[11], m[11 * n + i], v[11 * n + i], h.lr[4], h.b1, h.b2, h.eps, bc1, bc2);
+  }
+}
+
+// Fit-step epilogue: loss = (sum of the per-brick partial sums, fixed order) * scale; step += 1.
+__global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ loss_part, int64_t nb, float scale,
+                                                      float *__restrict__ loss, int32_t *__restrict__ step,
+                                                      const DevStatus *st) {
+  __shared__ float sh[4];
+  float acc = 0.f;
+  for (int64_t i = threadIdx.x; i < nb; i += 256) acc += loss_part[i];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && !st->overflow) {
+    *loss = (((sh[0] + sh[1]) + sh[2]) + sh[3]) * scale;
+    *step += 1;
+  }
+}
+
+hipError_t launch_reduce_adam(const gs_fit_state_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
+                              const gs_adam_t &hp, const float *loss_part, int64_t nb, float loss_scale, float *loss,
+                              hipStream_t s) {
+  const char *b = (const char *)ws;
+  AdamArgs h;
+  for (int k = 0; k < 5; ++k) h.lr[k] = hp.lr[k];
+  h.b1 = hp.beta1;
+  h.b2 = hp.beta2;
+  h.eps = hp.eps;
+  h.lnb1 = (float)std::log((double)hp.beta1);
+  h.lnb2 = (float)std::log((double)hp.beta2);
+  prof_begin(s);
+  if (g.n > 0)
+    k_reduce_adam<<<(unsigned)((g.n + kRedThreads - 1) / kRedThreads), kRedThreads, 0, s>>>(
+        g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, (const uint32_t *)(b + L.off),
+        (const float4 *)(b + L.partials), (const DevStatus *)(b + L.status), gr.d_mu, gr.d_log_scale, gr.d_quat,
+        gr.d_amp, gr.d_relax, g.m, g.v, g.step, h);
+  k_fit_finalize<<<1, 256, 0, s>>>(loss_part, nb, loss_scale, loss, g.step, (const DevStatus *)(b + L.status));
+  prof_end(s, "reduce_adam");
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
@@ -477,7 +672,7 @@ hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const Ws
   if (g.n == 0) return hipSuccess;
   const char *b = (const char *)ws;
   prof_begin(s);
-  k_reduce_chain<<<(unsigned)((g.n + 255) / 256), 256, 0, s>>>(
+  k_reduce_chain<<<(unsigned)((g.n + kRedThreads - 1) / kRedThreads), kRedThreads, 0, s>>>(
       g.n, g.quat, g.log_scale, g.relax, (const uint32_t *)(b + L.off), (const float4 *)(b + L.partials),
       (const DevStatus *)(b + L.status), gr.d_mu, gr.d_log_scale, gr.d_quat, gr.d_amp,
       g.relax ? gr.d_relax : nullptr);

@@ -114,10 +114,12 @@ for _name, _args in _sigs.items():
     _f.restype = ctypes.c_int
 _lib.gs_loss_scratch_bytes.argtypes = [ctypes.c_int64]
 _lib.gs_loss_scratch_bytes.restype = ctypes.c_size_t
+_lib.gs_fit_scratch_bytes.argtypes = [_P(gs_grid_t)]
+_lib.gs_fit_scratch_bytes.restype = ctypes.c_size_t
 _lib.gs_last_error.argtypes = []
 _lib.gs_last_error.restype = ctypes.c_char_p
 
-EXPORTED = tuple(_sigs) + ("gs_loss_scratch_bytes", "gs_last_error")
+EXPORTED = tuple(_sigs) + ("gs_loss_scratch_bytes", "gs_fit_scratch_bytes", "gs_last_error")
 
 
 def gs_last_error() -> str:
@@ -243,6 +245,10 @@ def gs_workspace_size(n: int, grid: Grid, opts: Opts, key_capacity: int) -> int:
 
 def gs_loss_scratch_bytes(nvox: int) -> int:
     return int(_lib.gs_loss_scratch_bytes(nvox))
+
+
+def gs_fit_scratch_bytes(grid: "Grid") -> int:
+    return int(_lib.gs_fit_scratch_bytes(ctypes.byref(grid.c())))
 
 
 class Bins:
@@ -426,7 +432,8 @@ class FitBuffers:
         f = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)  # noqa: E731
         self.I, self.W, self.dL_dI = f(grid.shape), f(grid.shape), f(grid.shape)
         self.grads = Grads.empty(n, relax, device)
-        self.scratch = torch.empty(gs_loss_scratch_bytes(grid.size), dtype=torch.uint8, device=device)
+        self.scratch = torch.empty(max(gs_loss_scratch_bytes(grid.size), gs_fit_scratch_bytes(grid)),
+                                   dtype=torch.uint8, device=device)
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
 
     def c(self) -> gs_fit_buffers_t:

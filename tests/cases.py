@@ -34,6 +34,19 @@ def condition(p: dict, grid: oracle.Grid, seed: int = 12345, band: float = BAND,
     return p
 
 
+def condition_obs(p: dict, grid: oracle.Grid, obs, f: int = 4, band: float = 1e-5):
+    """Observation without near-ties: the fit loss's gradient is sign(zmean(I) - obs), and where
+    |zmean(I) - obs| is at rounding level an FP32 and an FP64 render may take different signs (both
+    correct).  Such observation values are moved 2 * band away from the oracle's z-mean."""
+    I, _, _ = oracle.render(p, grid)
+    lr = oracle.zmean(I, f)
+    obs = np.array(obs, dtype=np.float32, copy=True)
+    d = lr - obs.astype(np.float64)
+    near = np.abs(d) < band
+    obs[near] = (obs[near].astype(np.float64) - np.where(d[near] >= 0, 2 * band, -2 * band)).astype(np.float32)
+    return obs
+
+
 def small_case(seed: int, dims=(20, 18, 12), n: int = 60, ls_mean=None, ls_std=0.3, max_ratio=None,
                cond: bool = True):
     kw = {} if ls_mean is None else {"ls_mean": ls_mean}
