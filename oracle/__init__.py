@@ -69,6 +69,11 @@ def _lib(long_double: bool = False):
     lib.og_ambiguous.restype = _int
     lib.og_index_boxes.argtypes = [_i64, _f32p, _f32p, _f32p, *grid_args, _dbl, _i32p]
     lib.og_index_boxes.restype = _int
+    lib.og_render_frozen.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _vp, _f32p, _f32p, _f32p, *grid_args, _dbl,
+                                     _dbl, _f64p, _vp, _int]
+    lib.og_render_frozen.restype = _int
+    lib.og_ambiguous_voxels.argtypes = [_i64, _f32p, _f32p, _f32p, *grid_args, _dbl, _dbl, _i32p, _int]
+    lib.og_ambiguous_voxels.restype = _int
     _LIBS[name] = lib
     return lib
 
@@ -143,6 +148,21 @@ def render(p: dict, grid: Grid, cutoff: float = 3.0, eps: float = 1e-8, threads:
     return I.reshape(grid.shape), W.reshape(grid.shape), S.reshape(grid.shape)
 
 
+def render_frozen(p: dict, support: dict, grid: Grid, cutoff: float = 3.0, eps: float = 1e-8,
+                  threads: Optional[int] = None):
+    """Forward whose pair predicate uses the positions, scales and rotations of ``support`` and whose
+    weights use those of ``p`` (the support held fixed, for finite differences).  Returns (I, W)."""
+    n, mu, ls, q, amp, relax = _params(p)
+    _, mu0, ls0, q0, _, _ = _params(support)
+    I = np.zeros(grid.size)
+    W = np.zeros(grid.size)
+    rc = _lib().og_render_frozen(n, mu, ls, q, amp, _ptr(relax), mu0, ls0, q0, *grid._args(), float(cutoff),
+                                 float(eps), I, _ptr(W), threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle render_frozen failed ({rc})")
+    return I.reshape(grid.shape), W.reshape(grid.shape)
+
+
 def render_points(p: dict, grid: Grid, vox, cutoff: float = 3.0, eps: float = 1e-8, threads: Optional[int] = None):
     """Forward at the given flat voxel indices.  Returns (I, W, S) float64 [len(vox)]."""
     n, mu, ls, q, amp, relax = _params(p)
@@ -200,6 +220,16 @@ def ambiguous(p: dict, grid: Grid, band: float, cutoff: float = 3.0, sel=None, t
     if rc != 0:
         raise ValueError("oracle ambiguous failed")
     return cnt
+
+
+def ambiguous_voxels(p: dict, grid: Grid, band: float, cutoff: float = 3.0, threads: Optional[int] = None):
+    """Per voxel [nz, ny, nx]: number of Gaussians with |d^2 - cutoff^2| <= band there."""
+    n, mu, ls, q, _, _ = _params(p)
+    cnt = np.zeros(grid.size, dtype=np.int32)
+    if _lib().og_ambiguous_voxels(n, mu, ls, q, *grid._args(), float(cutoff), float(band), cnt,
+                                  threads or default_threads()) != 0:
+        raise ValueError("oracle ambiguous_voxels failed")
+    return cnt.reshape(grid.shape)
 
 
 def index_boxes(p: dict, grid: Grid, cutoff: float = 3.0):

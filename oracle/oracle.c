@@ -477,3 +477,109 @@ int og_index_boxes(int64_t n, const float *mu, const float *log_scale, const flo
   }
   return 0;
 }
+
+/* ---------------------------------------------------------------------------------------------
+ * Forward with the support held fixed: the pair (p, i) is kept iff its d^2 under a second
+ * parameter set (mu0, log_scale0, quat0) is <= cutoff^2, and weighted with the first set.  The
+ * analytic gradient of §3.3 is the derivative of this function at (mu0, ...) = (mu, ...), which is
+ * what central differences of it measure.
+ */
+int og_render_frozen(int64_t n, const float *mu, const float *log_scale, const float *quat, const float *amp,
+                     const float *relax, const float *mu0, const float *log_scale0, const float *quat0, int nx,
+                     int ny, int nz, const double *origin, const double *spacing, double cutoff, double eps,
+                     double *I, double *W, int nthreads) {
+  og_grid_t g;
+  make_grid(&g, nx, ny, nz, origin, spacing);
+  int64_t V = (int64_t)nx * ny * nz;
+  og_gauss_t *G = (og_gauss_t *)malloc(sizeof(og_gauss_t) * (size_t)(n > 0 ? n : 1));
+  og_gauss_t *G0 = (og_gauss_t *)malloc(sizeof(og_gauss_t) * (size_t)(n > 0 ? n : 1));
+  real_t *Wacc = (real_t *)calloc((size_t)V, sizeof(real_t));
+  real_t *Sacc = (real_t *)calloc((size_t)V, sizeof(real_t));
+  if (!G || !G0 || !Wacc || !Sacc) {
+    free(G);
+    free(G0);
+    free(Wacc);
+    free(Sacc);
+    return -2;
+  }
+  int rc = setup_all(G, n, mu, log_scale, quat, amp, relax, &g, (real_t)cutoff, nthreads);
+  if (rc == 0) rc = setup_all(G0, n, mu0, log_scale0, quat0, amp, relax, &g, (real_t)cutoff, nthreads);
+  real_t c2 = (real_t)cutoff * (real_t)cutoff;
+  if (rc == 0) {
+#pragma omp parallel num_threads(nthreads)
+    {
+      int T = omp_get_num_threads(), t = omp_get_thread_num();
+      int z0 = (int)((int64_t)nz * t / T), z1 = (int)((int64_t)nz * (t + 1) / T);
+      for (int64_t i = 0; i < n; ++i) {
+        const og_gauss_t *Gs = &G0[i], *Gw = &G[i];
+        if (Gs->lo[0] > Gs->hi[0] || Gs->lo[1] > Gs->hi[1] || Gs->lo[2] > Gs->hi[2]) continue;
+        int za = Gs->lo[2] > z0 ? Gs->lo[2] : z0;
+        int zb = Gs->hi[2] < z1 - 1 ? Gs->hi[2] : z1 - 1;
+        for (int iz = za; iz <= zb; ++iz)
+          for (int iy = Gs->lo[1]; iy <= Gs->hi[1]; ++iy)
+            for (int ix = Gs->lo[0]; ix <= Gs->hi[0]; ++ix) {
+              real_t d[3];
+              if (maha2(Gs, &g, ix, iy, iz, d) <= c2) {
+                real_t w = Gw->r * R_EXP(-maha2(Gw, &g, ix, iy, iz, d) / 2);
+                int64_t v = vidx(&g, ix, iy, iz);
+                Wacc[v] += w;
+                Sacc[v] += Gw->A * w;
+              }
+            }
+      }
+    }
+    for (int64_t v = 0; v < V; ++v) {
+      I[v] = (double)(Sacc[v] / (Wacc[v] + (real_t)eps));
+      if (W) W[v] = (double)Wacc[v];
+    }
+  }
+  free(G);
+  free(G0);
+  free(Wacc);
+  free(Sacc);
+  return rc;
+}
+
+/* Per voxel, the number of Gaussians whose d^2 at that voxel lies within `band` of cutoff^2 (the
+ * voxels whose value depends on an inclusion decision that FP32 and FP64 may take differently). */
+int og_ambiguous_voxels(int64_t n, const float *mu, const float *log_scale, const float *quat, int nx, int ny, int nz,
+                        const double *origin, const double *spacing, double cutoff, double band, int32_t *count,
+                        int nthreads) {
+  og_grid_t g;
+  make_grid(&g, nx, ny, nz, origin, spacing);
+  og_gauss_t *G = (og_gauss_t *)malloc(sizeof(og_gauss_t) * (size_t)(n > 0 ? n : 1));
+  if (!G) return -2;
+  real_t c2 = (real_t)cutoff * (real_t)cutoff;
+  real_t cw = R_SQRT(c2 + (real_t)band);
+  float one = 1;
+  int bad = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(| : bad)
+  for (int64_t i = 0; i < n; ++i) {
+    float a1 = one;
+    bad |= setup_gauss(&G[i], 0, mu + 3 * i, log_scale + 3 * i, quat + 4 * i, &a1, NULL, &g, cw) != 0;
+  }
+  if (bad) {
+    free(G);
+    return -1;
+  }
+  memset(count, 0, sizeof(int32_t) * (size_t)nx * ny * nz);
+#pragma omp parallel num_threads(nthreads)
+  {
+    int T = omp_get_num_threads(), t = omp_get_thread_num();
+    int z0 = (int)((int64_t)nz * t / T), z1 = (int)((int64_t)nz * (t + 1) / T);
+    for (int64_t i = 0; i < n; ++i) {
+      const og_gauss_t *Gi = &G[i];
+      if (Gi->lo[0] > Gi->hi[0] || Gi->lo[1] > Gi->hi[1] || Gi->lo[2] > Gi->hi[2]) continue;
+      int za = Gi->lo[2] > z0 ? Gi->lo[2] : z0;
+      int zb = Gi->hi[2] < z1 - 1 ? Gi->hi[2] : z1 - 1;
+      for (int iz = za; iz <= zb; ++iz)
+        for (int iy = Gi->lo[1]; iy <= Gi->hi[1]; ++iy)
+          for (int ix = Gi->lo[0]; ix <= Gi->hi[0]; ++ix) {
+            real_t d[3];
+            if (R_FABS(maha2(Gi, &g, ix, iy, iz, d) - c2) <= (real_t)band) count[vidx(&g, ix, iy, iz)] += 1;
+          }
+    }
+  }
+  free(G);
+  return 0;
+}

@@ -245,6 +245,15 @@ def test_conditioning_leaves_no_ambiguous_pair():
     assert before > 0  # the band is wide enough to matter at this size
 
 
+def test_ambiguity_counts_agree():
+    """Per-voxel and per-Gaussian ambiguity counts are two views of the same pair set."""
+    p, grid = cases.small_case(18, dims=(20, 18, 14), n=200, ls_std=0.5, cond=False)
+    band = 0.05
+    per_g = oracle.ambiguous(p, grid, band)
+    per_v = oracle.ambiguous_voxels(p, grid, band)
+    assert int(per_g.sum()) == int(per_v.sum()) > 0
+
+
 def test_long_double_agrees():
     """FP64 oracle error: rebuilt in long double, the forward agrees to ~1e-15 relative and the
     gradients to ~1e-12 relative of their scale."""
@@ -324,6 +333,32 @@ def test_grad_matches_central_differences():
             fd = (L(pp) - L(pm)) / step
             a = an[k].reshape(-1)[j]
             assert abs(fd - a) <= 2e-5 * max(abs(a), 1e-2 * np.abs(an[k]).max()) + 1e-9, (k, j, fd, a)
+
+
+def test_frozen_support_render():
+    """With the support parameters equal to the weight parameters the frozen-support render is the
+    plain render; moving the weight parameters keeps the truncation mask of the support set, and its
+    central differences match the analytic (truncated) gradient."""
+    p, grid = cases.small_case(26, dims=(14, 12, 10), n=25, ls_std=0.4)
+    I, W, _ = oracle.render(p, grid)
+    If, Wf = oracle.render_frozen(p, p, grid)
+    np.testing.assert_array_equal(If, I)
+    np.testing.assert_array_equal(Wf, W)
+    g = np.random.default_rng(27).standard_normal(grid.shape)
+    an = oracle.grad(p, grid, I, W, g)
+    h = 2.5e-4
+    rng = np.random.default_rng(28)
+    for _ in range(24):
+        k = ("mu", "log_scale", "quat", "amp")[rng.integers(4)]
+        j = int(rng.integers(p[k].size))
+        pp = {kk: vv.copy() for kk, vv in p.items()}
+        pm = {kk: vv.copy() for kk, vv in p.items()}
+        pp[k].reshape(-1)[j] = np.float32(p[k].reshape(-1)[j] + h)
+        pm[k].reshape(-1)[j] = np.float32(p[k].reshape(-1)[j] - h)
+        step = float(pp[k].reshape(-1)[j]) - float(pm[k].reshape(-1)[j])
+        fd = float(((oracle.render_frozen(pp, p, grid)[0] - oracle.render_frozen(pm, p, grid)[0]) * g).sum()) / step
+        a = an[k].reshape(-1)[j]
+        assert abs(fd - a) <= 2e-5 * max(abs(a), 1e-2 * np.abs(an[k]).max()) + 1e-9, (k, j, fd, a)
 
 
 def test_quaternion_invariances():
