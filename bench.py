@@ -43,8 +43,11 @@ def parse():
     ap.add_argument("--dims", type=int, nargs=3, default=(256, 256, 128))
     ap.add_argument("--n", type=int, default=500000)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--bx", type=int, default=8, help="brick width along x (4, 8 or 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-scan comparison")
+    ap.add_argument("--batch-steps", type=int, default=20, help="timed steps of the batched comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain device-to-device copy of this many MiB (a known-size "
                          "kernel against which profiler byte counters are calibrated)")
@@ -64,6 +67,95 @@ def traffic_from_profiles(kernel: str):
         return float(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
+
+
+def batch_section(args, dev):
+    """16 uneven single-scan fits: one batched step (all scans, one launch per phase, autotuned brick
+    width, replayed from a HIP graph; then the same with eager launches) against the same 16 fits
+    stepped one scan at a time through the plain single-scan call at the same brick width.  Both
+    start from the same parameters and take the same number of steps; their final parameters must be
+    bitwise equal."""
+    import numpy as np
+    import torch
+
+    from paper_2603_09621_amd import autotune, graph, gs, synth
+
+    t0 = time.time()
+    scans = synth.workload_batch(seed=4)
+    print(f"[bench] batch workload: {len(scans)} scans in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    grids = [gs.Grid(*d) for _, _, d in scans]
+    sets = [gs.Gaussians.from_numpy(p, device=dev) for p, _, _ in scans]
+    obs = [torch.from_numpy(lr).to(dev) for _, lr, _ in scans]
+    batch = gs.Batch([x.n for x in sets], grids)
+    g_all = gs.concat(sets)
+    obs_all = torch.cat([o.reshape(-1) for o in obs])
+    opts = autotune.Tuner().fit_opts(g_all, batch, obs_all, zdown=4, steps=2)
+    print(f"[bench] autotuned brick width {opts.bx}", file=sys.stderr, flush=True)
+    fo = gs.FitOpts(None, opts=opts, zdown=4)
+    stream = torch.cuda.current_stream()
+    K, W = args.batch_steps, 2
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    # batched + graph
+    bins = gs.plan_bins_batch(g_all, batch, opts, headroom=1.5)
+    st = gs.FitState(g_all, nscans=len(batch))
+    buf = gs.FitBuffers(g_all.n, batch, relax=g_all.relax is not None, device=dev, need_dL_dI=False)
+    for _ in range(W):
+        gs.gs_fit_step_batch(st, obs_all, batch, fo, bins, buf)
+    gs.gs_status(bins)
+    fg = graph.FitGraph(st, obs_all, batch, fo, bins, buf, steps=1)
+    ms_batched = timed(fg.replay, K)
+    gs.gs_status(bins)
+    # K more batched steps with eager launches (the graph's gain)
+    ms_eager = timed(lambda: gs.gs_fit_step_batch(st, obs_all, batch, fo, bins, buf), K)
+    gs.gs_status(bins)
+    # plain: every scan on its own, one after the other
+    plain = []
+    for x, gr, o in zip(sets, grids, obs):
+        b1 = gs.plan_bins(x, gr, opts, headroom=1.5)
+        plain.append((x, gs.FitState(x), o, gs.FitOpts(gr, opts=opts, zdown=4), b1,
+                      gs.FitBuffers(x.n, gr, relax=x.relax is not None, device=dev)))
+    for _ in range(W):
+        for x, st1, o, fo1, b1, buf1 in plain:
+            gs.gs_fit_step(st1, o, fo1, b1, buf1)
+
+    def plain_round():
+        for x, st1, o, fo1, b1, buf1 in plain:
+            gs.gs_fit_step(st1, o, fo1, b1, buf1)
+
+    ms_plain = timed(plain_round, K)
+    for _ in range(K):  # the plain fits catch up with the batched one (W + 2K steps each)
+        plain_round()
+    for x, st1, o, fo1, b1, buf1 in plain:
+        gs.gs_status(b1)
+    off = batch.g_offsets
+    equal = all(torch.equal(getattr(g_all, k)[off[j]:off[j + 1]], getattr(x, k))
+                for j, x in enumerate(sets) for k in gs.GROUPS if getattr(x, k) is not None)
+    dims = [list(d) for _, _, d in scans]
+    return {
+        "workload": f"{len(scans)} uneven single-scan fits (HR grids {min(d[0] for d in dims)}..{max(d[0] for d in dims)}"
+                    f" in x/y, {min(d[2] for d in dims)}..{max(d[2] for d in dims)} in z; {g_all.n} Gaussians, "
+                    f"{batch.v_offsets[-1]} HR voxels in total), z-mean-of-4 L1 + Adam",
+        "brick": [opts.bx, opts.by, opts.bz],
+        "steps": K,
+        "ms_per_batched_step": ms_batched / K,
+        "ms_per_plain_round": ms_plain / K,
+        "scan_iters_per_s_batched": len(scans) * K / (ms_batched / 1e3),
+        "scan_iters_per_s_plain": len(scans) * K / (ms_plain / 1e3),
+        "speedup": ms_plain / ms_batched,
+        "hip_graph": True,
+        "bitwise_equal_to_plain": bool(equal),
+        "ms_per_batched_step_eager": ms_eager / K,
+    }
 
 
 def main():
@@ -88,7 +180,7 @@ def main():
 
     grid = gs.Grid(*dims)
     g = gs.Gaussians.from_numpy(p, device=dev)
-    fo = gs.FitOpts(grid)
+    fo = gs.FitOpts(grid, opts=gs.Opts(bx=args.bx))
     obs = torch.from_numpy(lr_obs).to(dev)
     bins = gs.plan_bins(g, grid, fo.opts, headroom=1.5)
     st = gs.FitState(g)
@@ -192,6 +284,12 @@ def main():
                          f"{dims[0]}x{dims[1]}x{dims[2]} / {args.n}-Gaussian workload, "
                          f"{pairs0} useful pairs per step, {cpu_s:.2f} s per step"}
 
+    batched = None
+    if not args.no_batch:
+        del bins, st, buf, g, snap, final
+        torch.cuda.empty_cache()
+        batched = batch_section(args, dev)
+
     out = {
         "metric": "Gaussian-voxel evals/s (fwd+bwd)",
         "value": value,
@@ -216,6 +314,7 @@ def main():
         "kernels_avg_ms": {k: round(v["avg_ms"], 5) for k, v in sorted(kern.items())},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -38,7 +38,8 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
+#define GS_MAX_SCANS 16 /* scans per batch */
 
 enum {
   GS_OK = 0,
@@ -66,8 +67,8 @@ typedef struct {
   float spacing[3]; /* > 0 */
 } gs_grid_t;
 
-/* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4); supported shapes are
- * listed by gs_brick_supported().  cutoff: Mahalanobis truncation radius (3 = the 3-sigma
+/* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4; this build also runs
+ * 4x8x4 and 16x8x4, a choice that changes speed, never results); gs_brick_supported() tells.  cutoff: Mahalanobis truncation radius (3 = the 3-sigma
  * ellipsoid).  eps: denominator regulariser (>= 0). */
 typedef struct {
   int32_t bx, by, bz;
@@ -107,7 +108,8 @@ typedef struct {
   float *mu, *log_scale, *quat, *amp; /* device, [n][3], [n][3], [n][4], [n] */
   float *relax;                        /* device [n], or NULL (r = 1, not optimised) */
   float *m, *v;    /* device [12 n] each: groups mu (3n), log_scale (3n), quat (4n), amp (n), relax (n) */
-  int32_t *step;   /* device scalar: Adam steps taken so far (0 before the first step) */
+  int32_t *step;   /* device: Adam steps taken so far (0 before the first step); one counter per scan
+                      of a batch ([ns]), a scalar for the single-scan calls */
 } gs_fit_state_t;
 
 /* Per-step fit options: HR grid, rasterizer options, z-downsampling factor of the LR observation
@@ -128,8 +130,20 @@ typedef struct {
   gs_grads_t grads;    /* [n]-sized gradient arrays (written); d_mu, d_log_scale, d_quat, d_amp required */
   void *scratch;       /* >= gs_fit_scratch_bytes(&hr) bytes */
   size_t scratch_bytes;
-  float *loss;         /* device scalar: the step's loss */
+  float *loss;         /* device: the step's loss, one per scan of a batch ([ns]) */
 } gs_fit_buffers_t;
+
+/* A batch of independent scans handled by the same launches (each phase of the method is one launch
+ * over the bricks of all scans; §3.3's brick partition applies to each scan's own grid).  Scan k
+ * owns the n[k] Gaussians that follow those of scans 0..k-1 in the concatenated Gaussian set, and
+ * its volumes (I, W, dL_dI: grid[k].nz * ny * nx voxels) and LR observation follow those of scans
+ * 0..k-1 in the concatenated arrays.  Results of every scan are bitwise identical to those of the
+ * single-scan calls on that scan alone.  The single-scan calls are the ns = 1 case. */
+typedef struct {
+  int32_t ns;             /* 1 .. GS_MAX_SCANS */
+  const int64_t *n;       /* host [ns]: Gaussians per scan (>= 0) */
+  const gs_grid_t *grid;  /* host [ns]: grid per scan */
+} gs_batch_t;
 
 /* Device status block (read by gs_status). */
 typedef struct {
@@ -150,6 +164,11 @@ size_t gs_loss_scratch_bytes(int64_t nvox);
 
 /* Bytes of scratch for gs_fit_step on the HR grid hr (0 for an invalid grid). */
 size_t gs_fit_scratch_bytes(const gs_grid_t *hr);
+
+/* Batch forms of the two sizes above (0 for an invalid batch). */
+int gs_workspace_size_batch(const gs_batch_t *batch, const gs_opts_t *opts, int64_t key_capacity,
+                            size_t *bytes /* host out */);
+size_t gs_fit_scratch_bytes_batch(const gs_batch_t *batch);
 
 /* 1 if the brick shape is supported by the kernels of this build, else 0. */
 int gs_brick_supported(int32_t bx, int32_t by, int32_t bz);
@@ -218,6 +237,33 @@ int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_ada
  * the parameters and *step unchanged). */
 int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
                 const gs_fit_buffers_t *buf, void *stream);
+
+/* ---- batches of scans (many scans of uneven size in one launch per phase) ------------------- */
+
+/* Each call below equals its single-scan namesake applied to every scan of `batch`, with g the
+ * concatenated Gaussian set (g->n = sum of batch->n) and every volume argument the concatenation
+ * of the scans' volumes in batch order.  One workspace serves the whole batch
+ * (gs_workspace_size_batch); keys and bricks of all scans share its capacity. */
+int gs_bin_query_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts,
+                       const gs_bins_t *bins, void *stream, int64_t *n_keys /* host out */);
+int gs_bin_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts, const gs_bins_t *bins,
+                 void *stream);
+int gs_render_fwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts,
+                        const gs_bins_t *bins, float *I, float *W, void *stream);
+int gs_count_pairs_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts,
+                         const gs_bins_t *bins, int64_t *d_count, void *stream);
+int gs_render_bwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts,
+                        const gs_bins_t *bins, const float *I, const float *W, const float *dL_dI,
+                        const gs_grads_t *grads, void *stream);
+
+/* One fit step of every scan of the batch (as gs_fit_step per scan; fo->hr is not read, the grids
+ * come from the batch; every scan's nz must be a multiple of fo->zdown).  st holds the concatenated
+ * parameters and moments ([12 n_total] in the group layout over the whole set) and one step counter
+ * per scan; lr_obs the concatenated LR observations; buf->loss receives one loss per scan and
+ * buf->scratch must hold gs_fit_scratch_bytes_batch(batch) bytes.  Scans may be at different steps
+ * (each has its own Adam bias correction). */
+int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_batch_t *batch,
+                      const gs_fit_opts_t *fo, const gs_bins_t *bins, const gs_fit_buffers_t *buf, void *stream);
 
 /* ---- status, errors, profiling ---------------------------------------------------------------- */
 

@@ -75,7 +75,7 @@ void prof_end(hipStream_t s, const char *name) {
 
 // ---- geometry and workspace layout ---------------------------------------------------------------
 
-static bool brick_supported(int bx, int by, int bz) { return bx == 8 && by == 8 && bz == 4; }
+static bool brick_supported(int bx, int by, int bz) { return (bx == 4 || bx == 8 || bx == 16) && by == 8 && bz == 4; }
 
 bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg) {
   bg->nx = grid->nx;
@@ -102,14 +102,14 @@ bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout make_layout(int64_t n, const BrickGrid &bg, int64_t cap) {
+WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap) {
   WsLayout L;
   L.n = n;
   L.cap = cap;
-  L.nbricks = bg.nbricks;
+  L.nbricks = nbricks;
   L.sort_blocks = (int)((cap + kSortTile - 1) / kSortTile);
   int bits = 0;
-  while (bits < 32 && ((int64_t)1 << bits) < bg.nbricks) ++bits;
+  while (bits < 32 && ((int64_t)1 << bits) < nbricks) ++bits;
   L.sort_passes = bits == 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -128,7 +128,7 @@ WsLayout make_layout(int64_t n, const BrickGrid &bg, int64_t cap) {
   L.vals_b = take(sizeof(uint32_t) * (size_t)cap);
   L.list_gid = take(sizeof(uint32_t) * (size_t)cap);
   L.list_slot = take(sizeof(uint32_t) * (size_t)cap);
-  L.brick_off = take(sizeof(uint32_t) * (size_t)(bg.nbricks + 1));
+  L.brick_off = take(sizeof(uint32_t) * (size_t)(nbricks + 1));
   L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
   const int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
   L.scan_tmp = take(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
@@ -174,21 +174,84 @@ static int check_gaussians(const gs_gaussians_t *g) {
   return GS_OK;
 }
 
-static int check_common(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
-                        BrickGrid *bg, WsLayout *L) {
+// Scan table of a batch: Gaussians, bricks and volumes of the scans concatenated in order.  With
+// zdown > 0 the observation offsets and the fit loss scales are filled in as well.
+static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown, ScanTable *T) {
   int rc;
-  if ((rc = check_gaussians(g)) || (rc = check_grid(grid)) || (rc = check_opts(opts))) return rc;
+  if (!bt) return fail(GS_ERR_INVALID_ARG, "batch is NULL");
+  if (bt->ns < 1 || bt->ns > GS_MAX_SCANS)
+    return fail(GS_ERR_INVALID_ARG, "batch size must be in [1, %d] (got %d)", GS_MAX_SCANS, bt->ns);
+  if (!bt->n || !bt->grid) return fail(GS_ERR_INVALID_ARG, "batch n and grid arrays are required");
+  if ((rc = check_opts(opts))) return rc;
+  std::memset(T, 0, sizeof *T);
+  T->ns = bt->ns;
+  int64_t g0 = 0, b0 = 0, v0 = 0, o0 = 0;
+  for (int k = 0; k < bt->ns; ++k) {
+    const gs_grid_t *gr = &bt->grid[k];
+    if ((rc = check_grid(gr))) return rc;
+    if (bt->n[k] < 0) return fail(GS_ERR_INVALID_ARG, "scan %d: n must be >= 0", k);
+    if (zdown > 0 && gr->nz % zdown != 0)
+      return fail(GS_ERR_INVALID_ARG, "scan %d: nz (%d) must be a multiple of zdown (%d)", k, gr->nz, zdown);
+    ScanDesc &sd = T->s[k];
+    make_brick_grid(gr, opts, &sd.bg);
+    sd.g0 = g0;
+    sd.n = bt->n[k];
+    sd.b0 = b0;
+    sd.v0 = v0;
+    sd.o0 = o0;
+    const int64_t nvox = (int64_t)gr->nx * gr->ny * gr->nz;
+    if (zdown > 0) {
+      const int64_t nlr = nvox / zdown;
+      sd.gscale = (float)(1.0 / ((double)zdown * (double)nlr));
+      sd.lscale = (float)(1.0 / (double)nlr);
+      o0 += nlr;
+    }
+    g0 += bt->n[k];
+    b0 += sd.bg.nbricks;
+    v0 += nvox;
+  }
+  T->n_total = g0;
+  T->nbricks_total = b0;
+  if (g0 >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "total Gaussian count must be < 2^31");
+  if (b0 >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
+  if (v0 > ((int64_t)1 << 40)) return fail(GS_ERR_INVALID_ARG, "batch volumes too large");
+  return GS_OK;
+}
+
+static int check_common(const gs_gaussians_t *g, const gs_batch_t *bt, const gs_opts_t *opts, const gs_bins_t *bins,
+                        int32_t zdown, ScanTable *T, WsLayout *L) {
+  int rc;
+  if ((rc = check_gaussians(g)) || (rc = make_table(bt, opts, zdown, T))) return rc;
+  if (g->n != T->n_total)
+    return fail(GS_ERR_INVALID_ARG, "the Gaussian set holds %lld Gaussians, the batch's scans %lld", (long long)g->n,
+                (long long)T->n_total);
   if (!bins || !bins->ws) return fail(GS_ERR_INVALID_ARG, "bins or bins->ws is NULL");
   if (bins->key_capacity < 0 || bins->key_capacity > (int64_t)0x7FFFFF00)
     return fail(GS_ERR_INVALID_ARG, "key_capacity must be in [0, 2^31 - 256]");
-  make_brick_grid(grid, opts, bg);
-  if (bg->nbricks >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
-  *L = make_layout(g->n, *bg, bins->key_capacity);
+  *L = make_layout(T->n_total, T->nbricks_total, bins->key_capacity);
   if ((int64_t)kRadix * L->sort_blocks > (int64_t)kScanTile * 8192 || g->n + 1 > (int64_t)kScanTile * 8192)
     return fail(GS_ERR_INVALID_ARG, "key capacity or n beyond the scan limit");
   if (bins->ws_bytes < L->total)
     return fail(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes given, %zu needed", bins->ws_bytes, L->total);
   return GS_OK;
+}
+
+// The one-scan batch of a single-scan call.
+struct Single {
+  int64_t n;
+  gs_grid_t grid;
+  gs_batch_t b;
+  Single(int64_t n_, const gs_grid_t *g) : n(n_) {
+    if (g) grid = *g;
+    else std::memset(&grid, 0, sizeof grid);
+    b.ns = 1;
+    b.n = &n;
+    b.grid = g ? &grid : nullptr;
+  }
+};
+
+static int64_t bricks_at(const gs_grid_t &g, int bx) {
+  return (int64_t)((g.nx + bx - 1) / bx) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
 }
 
 }  // namespace gs
@@ -201,38 +264,42 @@ const char *gs_last_error(void) { return g_last_error.c_str(); }
 
 int gs_brick_supported(int32_t bx, int32_t by, int32_t bz) { return brick_supported(bx, by, bz) ? 1 : 0; }
 
-int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, int64_t key_capacity, size_t *bytes) {
-  int rc;
-  if (n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
-  if ((rc = check_grid(grid)) || (rc = check_opts(opts))) return rc;
+int gs_workspace_size_batch(const gs_batch_t *batch, const gs_opts_t *opts, int64_t key_capacity, size_t *bytes) {
   if (!bytes) return fail(GS_ERR_INVALID_ARG, "bytes is NULL");
   if (key_capacity < 0) return fail(GS_ERR_INVALID_ARG, "key_capacity must be >= 0");
-  BrickGrid bg;
-  make_brick_grid(grid, opts, &bg);
-  *bytes = make_layout(n, bg, key_capacity).total;
+  ScanTable T;
+  int rc = make_table(batch, opts, 0, &T);
+  if (rc) return rc;
+  *bytes = make_layout(T.n_total, T.nbricks_total, key_capacity).total;
   return GS_OK;
+}
+
+int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, int64_t key_capacity, size_t *bytes) {
+  if (n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+  Single one(n, grid);
+  return gs_workspace_size_batch(&one.b, opts, key_capacity, bytes);
 }
 
 size_t gs_loss_scratch_bytes(int64_t nvox) { return sizeof(float) * (size_t)std::max(1, loss_blocks(nvox)); }
 
-static int bin_front(const gs_gaussians_t *g, const BrickGrid &bg, const gs_opts_t *opts, const gs_bins_t *bins,
+static int bin_front(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
                      const WsLayout &L, hipStream_t s) {
   hipError_t e;
   if ((e = launch_reset(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "reset");
-  if ((e = launch_prep_count(*g, bg, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
+  if ((e = launch_prep_count(T, *g, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
   if ((e = launch_scan_counts(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "scan_counts");
   return GS_OK;
 }
 
-int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
-                 void *stream, int64_t *n_keys) {
-  BrickGrid bg;
+int gs_bin_query_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts, const gs_bins_t *bins,
+                       void *stream, int64_t *n_keys) {
+  ScanTable T;
   WsLayout L;
-  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  int rc = check_common(g, batch, opts, bins, 0, &T, &L);
   if (rc) return rc;
   if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = bin_front(g, bg, opts, bins, L, s))) return rc;
+  if ((rc = bin_front(g, T, opts, bins, L, s))) return rc;
   DevStatus st;
   hipError_t e = hipMemcpyAsync(&st, (char *)bins->ws + L.status, sizeof st, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -242,54 +309,89 @@ int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t
   return GS_OK;
 }
 
+int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                 void *stream, int64_t *n_keys) {
+  Single one(g ? g->n : 0, grid);
+  return gs_bin_query_batch(g, &one.b, opts, bins, stream, n_keys);
+}
+
+static int bin_all(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
+                   const WsLayout &L, hipStream_t s) {
+  int rc;
+  if ((rc = bin_front(g, T, opts, bins, L, s))) return rc;
+  hipError_t e;
+  if ((e = launch_emit(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
+  if ((e = launch_sort(T, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
+  return GS_OK;
+}
+
+int gs_bin_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts, const gs_bins_t *bins,
+                 void *stream) {
+  ScanTable T;
+  WsLayout L;
+  int rc = check_common(g, batch, opts, bins, 0, &T, &L);
+  if (rc) return rc;
+  return bin_all(g, T, opts, bins, L, (hipStream_t)stream);
+}
+
 int gs_bin(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
            void *stream) {
-  BrickGrid bg;
+  Single one(g ? g->n : 0, grid);
+  return gs_bin_batch(g, &one.b, opts, bins, stream);
+}
+
+int gs_render_fwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts, const gs_bins_t *bins,
+                        float *I, float *W, void *stream) {
+  ScanTable T;
   WsLayout L;
-  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  int rc = check_common(g, batch, opts, bins, 0, &T, &L);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  if ((rc = bin_front(g, bg, opts, bins, L, s))) return rc;
-  hipError_t e;
-  if ((e = launch_emit(bg, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
-  if ((e = launch_sort(bg, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
-  return GS_OK;
+  if (!I) return fail(GS_ERR_INVALID_ARG, "I is NULL");
+  hipError_t e = launch_fwd(T, opts->bx, opts->cutoff, opts->eps, bins->ws, L, I, W, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "render_fwd");
 }
 
 int gs_render_fwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
                   float *I, float *W, void *stream) {
-  BrickGrid bg;
+  Single one(g ? g->n : 0, grid);
+  return gs_render_fwd_batch(g, &one.b, opts, bins, I, W, stream);
+}
+
+int gs_count_pairs_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts,
+                         const gs_bins_t *bins, int64_t *d_count, void *stream) {
+  ScanTable T;
   WsLayout L;
-  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  int rc = check_common(g, batch, opts, bins, 0, &T, &L);
   if (rc) return rc;
-  if (!I) return fail(GS_ERR_INVALID_ARG, "I is NULL");
-  hipError_t e = launch_fwd(bg, opts->cutoff, opts->eps, bins->ws, L, I, W, (hipStream_t)stream);
-  return e == hipSuccess ? GS_OK : hip_fail(e, "render_fwd");
+  if (!d_count) return fail(GS_ERR_INVALID_ARG, "d_count is NULL");
+  hipError_t e = launch_count_pairs(T, opts->bx, opts->cutoff, bins->ws, L, d_count, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "count_pairs");
 }
 
 int gs_count_pairs(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
                    int64_t *d_count, void *stream) {
-  BrickGrid bg;
+  Single one(g ? g->n : 0, grid);
+  return gs_count_pairs_batch(g, &one.b, opts, bins, d_count, stream);
+}
+
+int gs_render_bwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts, const gs_bins_t *bins,
+                        const float *I, const float *W, const float *dL_dI, const gs_grads_t *grads, void *stream) {
+  ScanTable T;
   WsLayout L;
-  int rc = check_common(g, grid, opts, bins, &bg, &L);
+  int rc = check_common(g, batch, opts, bins, 0, &T, &L);
   if (rc) return rc;
-  if (!d_count) return fail(GS_ERR_INVALID_ARG, "d_count is NULL");
-  hipError_t e = launch_count_pairs(bg, opts->cutoff, bins->ws, L, d_count, (hipStream_t)stream);
-  return e == hipSuccess ? GS_OK : hip_fail(e, "count_pairs");
+  if (!I || !W || !dL_dI || !grads) return fail(GS_ERR_INVALID_ARG, "I, W, dL_dI and grads are required");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_bwd(T, opts->bx, opts->cutoff, opts->eps, bins->ws, L, I, W, dL_dI, s);
+  if (e != hipSuccess) return hip_fail(e, "render_bwd");
+  e = launch_reduce_chain(*g, bins->ws, L, *grads, s);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_chain");
 }
 
 int gs_render_bwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
                   const float *I, const float *W, const float *dL_dI, const gs_grads_t *grads, void *stream) {
-  BrickGrid bg;
-  WsLayout L;
-  int rc = check_common(g, grid, opts, bins, &bg, &L);
-  if (rc) return rc;
-  if (!I || !W || !dL_dI || !grads) return fail(GS_ERR_INVALID_ARG, "I, W, dL_dI and grads are required");
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_bwd(bg, opts->cutoff, opts->eps, bins->ws, L, I, W, dL_dI, s);
-  if (e != hipSuccess) return hip_fail(e, "render_bwd");
-  e = launch_reduce_chain(*g, bins->ws, L, *grads, s);
-  return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_chain");
+  Single one(g ? g->n : 0, grid);
+  return gs_render_bwd_batch(g, &one.b, opts, bins, I, W, dL_dI, grads, stream);
 }
 
 int gs_loss_mse(const float *I, const float *T, int64_t nvox, float *dL_dI, float *loss, void *scratch,
@@ -316,8 +418,9 @@ int gs_loss_l1_zmean(const float *I, const float *obs, const gs_grid_t *hr, int3
 static int check_state(const gs_fit_state_t *st, const gs_grads_t *gr) {
   if (!st || !gr) return fail(GS_ERR_INVALID_ARG, "state or grads is NULL");
   if (st->n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
-  if (st->n > 0 && (!st->mu || !st->log_scale || !st->quat || !st->amp || !st->m || !st->v || !st->step))
-    return fail(GS_ERR_INVALID_ARG, "state arrays mu, log_scale, quat, amp, m, v, step are required");
+  if (st->n > 0 && (!st->mu || !st->log_scale || !st->quat || !st->amp || !st->m || !st->v))
+    return fail(GS_ERR_INVALID_ARG, "state arrays mu, log_scale, quat, amp, m, v are required");
+  if (!st->step) return fail(GS_ERR_INVALID_ARG, "step is required");
   if (st->n > 0 && (!gr->d_mu || !gr->d_log_scale || !gr->d_quat || !gr->d_amp))
     return fail(GS_ERR_INVALID_ARG, "gradients d_mu, d_log_scale, d_quat, d_amp are required");
   if (st->n > 0 && st->relax && !gr->d_relax) return fail(GS_ERR_INVALID_ARG, "d_relax is required when relax is set");
@@ -334,52 +437,75 @@ int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_ada
   return e == hipSuccess ? GS_OK : hip_fail(e, "adam");
 }
 
-size_t gs_fit_scratch_bytes(const gs_grid_t *hr) {
-  if (!hr || hr->nx <= 0 || hr->ny <= 0 || hr->nz <= 0) return 0;
-  const int64_t nvox = (int64_t)hr->nx * hr->ny * hr->nz;
-  const int64_t nbricks = (int64_t)((hr->nx + 7) / 8) * ((hr->ny + 7) / 8) * ((hr->nz + 3) / 4);
-  return sizeof(float) * (size_t)std::max<int64_t>(std::max(1, loss_blocks(nvox)), nbricks);
+size_t gs_fit_scratch_bytes_batch(const gs_batch_t *batch) {
+  if (!batch || batch->ns < 1 || batch->ns > GS_MAX_SCANS || !batch->grid) return 0;
+  // fused path: one float per brick of every scan at the narrowest supported brick (the most bricks);
+  // separate loss path: the loss reduction of the largest scan
+  int64_t bricks = 0, blocks = 1;
+  for (int k = 0; k < batch->ns; ++k) {
+    const gs_grid_t &g = batch->grid[k];
+    if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0) return 0;
+    bricks += bricks_at(g, 4);
+    blocks = std::max<int64_t>(blocks, loss_blocks((int64_t)g.nx * g.ny * g.nz));
+  }
+  return sizeof(float) * (size_t)std::max(bricks, blocks);
 }
 
-int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
-                const gs_fit_buffers_t *buf, void *stream) {
+size_t gs_fit_scratch_bytes(const gs_grid_t *hr) {
+  if (!hr) return 0;
+  Single one(0, hr);
+  return gs_fit_scratch_bytes_batch(&one.b);
+}
+
+int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_batch_t *batch, const gs_fit_opts_t *fo,
+                      const gs_bins_t *bins, const gs_fit_buffers_t *buf, void *stream) {
   if (!fo || !buf || !lr_obs) return fail(GS_ERR_INVALID_ARG, "fit opts, buffers and lr_obs are required");
   int rc = check_state(st, &buf->grads);
   if (rc) return rc;
   if (fo->loss != 0) return fail(GS_ERR_UNSUPPORTED, "only loss 0 (L1 on the z-mean) is supported");
-  if ((rc = check_grid(&fo->hr))) return rc;
-  if (fo->zdown <= 0 || fo->hr.nz % fo->zdown != 0)
-    return fail(GS_ERR_INVALID_ARG, "hr.nz must be a positive multiple of zdown");
+  if (fo->zdown <= 0) return fail(GS_ERR_INVALID_ARG, "zdown must be positive");
   gs_gaussians_t g{st->n, st->mu, st->log_scale, st->quat, st->amp, st->relax};
-  hipStream_t s = (hipStream_t)stream;
+  ScanTable T;
+  WsLayout L;
+  if ((rc = check_common(&g, batch, &fo->opts, bins, fo->zdown, &T, &L))) return rc;
   if (!buf->I || !buf->W || !buf->loss || !buf->scratch) return fail(GS_ERR_INVALID_ARG, "fit buffers incomplete");
-  if (buf->scratch_bytes < gs_fit_scratch_bytes(&fo->hr))
-    return fail(GS_ERR_INVALID_ARG, "fit scratch too small: %zu bytes given, %zu needed", buf->scratch_bytes,
-                gs_fit_scratch_bytes(&fo->hr));
-  if ((rc = gs_bin(&g, &fo->hr, &fo->opts, bins, stream))) return rc;
-  if ((rc = gs_render_fwd(&g, &fo->hr, &fo->opts, bins, buf->I, buf->W, stream))) return rc;
-  BrickGrid bg;
-  make_brick_grid(&fo->hr, &fo->opts, &bg);
-  const WsLayout L = make_layout(st->n, bg, bins->key_capacity);
-  hipError_t e;
-  if (fo->zdown == fo->opts.bz) {
+  const size_t need = gs_fit_scratch_bytes_batch(batch);
+  if (buf->scratch_bytes < need)
+    return fail(GS_ERR_INVALID_ARG, "fit scratch too small: %zu bytes given, %zu needed", buf->scratch_bytes, need);
+  const bool fused = fo->zdown == fo->opts.bz;
+  if (!fused && !buf->dL_dI)
+    return fail(GS_ERR_INVALID_ARG, "dL_dI is required when zdown differs from the brick depth");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = bin_all(&g, T, &fo->opts, bins, L, s))) return rc;
+  const gs_opts_t &o = fo->opts;
+  hipError_t e = launch_fwd(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, s);
+  if (e != hipSuccess) return hip_fail(e, "render_fwd");
+  if (fused) {
     // the z-mean groups coincide with the brick's z extent: loss fused into the backward's staging,
     // gradient reduction fused with Adam
     float *loss_part = (float *)buf->scratch;
-    const int64_t nlr = (int64_t)fo->hr.nx * fo->hr.ny * (fo->hr.nz / fo->zdown);
-    e = launch_bwd_fit(bg, fo->opts.cutoff, fo->opts.eps, bins->ws, L, buf->I, buf->W, lr_obs, loss_part, s);
+    e = launch_bwd_fit(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, lr_obs, loss_part, s);
     if (e != hipSuccess) return hip_fail(e, "render_bwd");
-    e = launch_reduce_adam(*st, bins->ws, L, buf->grads, fo->adam, loss_part, bg.nbricks, (float)(1.0 / (double)nlr),
-                           buf->loss, s);
+    e = launch_reduce_adam(T, *st, bins->ws, L, buf->grads, fo->adam, loss_part, buf->loss, s);
     return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_adam");
   }
-  if (!buf->dL_dI) return fail(GS_ERR_INVALID_ARG, "dL_dI is required when zdown differs from the brick depth");
-  if ((rc = gs_loss_l1_zmean(buf->I, lr_obs, &fo->hr, fo->zdown, buf->dL_dI, buf->loss, buf->scratch,
-                             buf->scratch_bytes, stream)))
-    return rc;
-  if ((rc = gs_render_bwd(&g, &fo->hr, &fo->opts, bins, buf->I, buf->W, buf->dL_dI, &buf->grads, stream))) return rc;
-  e = launch_adam(*st, buf->grads, fo->adam, bins->ws, s);
-  return e == hipSuccess ? GS_OK : hip_fail(e, "adam");
+  for (int k = 0; k < T.ns; ++k) {
+    const ScanDesc &sd = T.s[k];
+    e = launch_loss_l1z(buf->I + sd.v0, lr_obs + sd.o0, sd.bg.nx, sd.bg.ny, sd.bg.nz, fo->zdown, buf->dL_dI + sd.v0,
+                        buf->loss + k, buf->scratch, s);
+    if (e != hipSuccess) return hip_fail(e, "loss_l1z");
+  }
+  e = launch_bwd(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, buf->dL_dI, s);
+  if (e != hipSuccess) return hip_fail(e, "render_bwd");
+  e = launch_reduce_adam(T, *st, bins->ws, L, buf->grads, fo->adam, nullptr, buf->loss, s);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_adam");
+}
+
+int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
+                const gs_fit_buffers_t *buf, void *stream) {
+  if (!fo) return fail(GS_ERR_INVALID_ARG, "fit opts are required");
+  Single one(st ? st->n : 0, &fo->hr);
+  return gs_fit_step_batch(st, lr_obs, &one.b, fo, bins, buf, stream);
 }
 
 int gs_status(const gs_bins_t *bins, void *stream, gs_status_t *out) {

@@ -128,13 +128,14 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
   return count;
 }
 
-// Fused prep + count: records of Gaussian i and its key count cnt[i].  Thread n writes cnt[n] = 0
-// (the scan's total slot).
-__global__ void k_prep_count(int64_t n, const float *__restrict__ mu, const float *__restrict__ ls,
+// Fused prep + count: records of Gaussian i (of the concatenated set) and its key count cnt[i].
+// Thread n_total writes cnt[n_total] = 0 (the scan's total slot).
+__global__ void k_prep_count(const ScanTable T, const float *__restrict__ mu, const float *__restrict__ ls,
                              const float *__restrict__ quat, const float *__restrict__ amp,
-                             const float *__restrict__ relax, BrickGrid bg, float cutoff, EvalRec *__restrict__ er,
+                             const float *__restrict__ relax, float cutoff, EvalRec *__restrict__ er,
                              CullRec *__restrict__ cr, uint32_t *__restrict__ cnt, DevStatus *st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = T.n_total;
   if (i > n) return;
   if (i == n) {
     cnt[n] = 0u;
@@ -145,15 +146,16 @@ __global__ void k_prep_count(int64_t n, const float *__restrict__ mu, const floa
   make_records(i, mu, ls, quat, amp, relax, cutoff, e, c, st);
   er[i] = e;
   cr[i] = c;
+  const BrickGrid &bg = T.s[T.of_gauss(i)].bg;
   cnt[i] = enumerate_bricks(bg, e, c, cutoff, [](uint32_t, uint32_t) {});
 }
 
-hipError_t launch_prep_count(const gs_gaussians_t &g, const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L,
+hipError_t launch_prep_count(const ScanTable &T, const gs_gaussians_t &g, float cutoff, void *ws, const WsLayout &L,
                              hipStream_t s) {
   char *b = (char *)ws;
-  int blocks = (int)((g.n + 1 + 255) / 256);
+  int blocks = (int)((T.n_total + 1 + 255) / 256);
   prof_begin(s);
-  k_prep_count<<<blocks, 256, 0, s>>>(g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, bg, cutoff,
+  k_prep_count<<<blocks, 256, 0, s>>>(T, g.mu, g.log_scale, g.quat, g.amp, g.relax, cutoff,
                                       (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
                                       (uint32_t *)(b + L.off), (DevStatus *)(b + L.status));
   prof_end(s, "prep_count");
@@ -287,30 +289,31 @@ hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Emit: the j-th key of Gaussian i is written at slot off[i] + j.
+// Emit: the j-th key of Gaussian i is written at slot off[i] + j, with its scan's global brick id.
 
-__global__ void k_emit(int64_t n, BrickGrid bg, float cutoff, const EvalRec *__restrict__ er,
+__global__ void k_emit(const ScanTable T, float cutoff, const EvalRec *__restrict__ er,
                        const CullRec *__restrict__ cr, const uint32_t *__restrict__ off, int64_t cap,
                        const DevStatus *st, uint32_t *__restrict__ key_brick, uint32_t *__restrict__ key_gid) {
   if (st->overflow) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t base = off[i];
-  enumerate_bricks(bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
+  if (i >= T.n_total) return;
+  const ScanDesc &sd = T.s[T.of_gauss(i)];
+  const uint32_t base = off[i], b0 = (uint32_t)sd.b0;
+  enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
     const int64_t slot = (int64_t)base + j;
     if (slot < cap) {
-      key_brick[slot] = brick;
+      key_brick[slot] = b0 + brick;
       key_gid[slot] = (uint32_t)i;
     }
   });
 }
 
-hipError_t launch_emit(const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
-  if (L.n == 0) return hipSuccess;
+hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
+  if (T.n_total == 0) return hipSuccess;
   char *b = (char *)ws;
-  int blocks = (int)((L.n + 255) / 256);
+  int blocks = (int)((T.n_total + 255) / 256);
   prof_begin(s);
-  k_emit<<<blocks, 256, 0, s>>>(L.n, bg, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+  k_emit<<<blocks, 256, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
                                 (const uint32_t *)(b + L.off), L.cap, (const DevStatus *)(b + L.status),
                                 (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid));
   prof_end(s, "emit");
@@ -456,7 +459,7 @@ __global__ void k_brick_offsets(const uint32_t *__restrict__ sorted_brick, const
   brick_off[b] = (uint32_t)lo;
 }
 
-hipError_t launch_sort(const BrickGrid &bg, void *ws, const WsLayout &L, hipStream_t s) {
+hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
   DevStatus *st = (DevStatus *)(b + L.status);
   uint32_t *ka = (uint32_t *)(b + L.key_brick), *kb = (uint32_t *)(b + L.keys_alt);
@@ -489,10 +492,10 @@ hipError_t launch_sort(const BrickGrid &bg, void *ws, const WsLayout &L, hipStre
       vin = vout;
     }
   }
-  const int ob = (int)((bg.nbricks + 1 + 255) / 256);
+  const int ob = (int)((T.nbricks_total + 1 + 255) / 256);
   prof_begin(s);
   k_brick_offsets<<<ob, 256, 0, s>>>((const uint32_t *)(b + L.sorted_keys), st, L.cap, (uint32_t *)(b + L.brick_off),
-                                     bg.nbricks);
+                                     T.nbricks_total);
   prof_end(s, "brick_offsets");
   return hipGetLastError();
 }

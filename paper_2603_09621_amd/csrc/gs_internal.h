@@ -37,7 +37,7 @@ struct DevStatus {
   int32_t spare[12];
 };
 
-// Brick grid geometry.
+// Brick grid geometry of one scan.  Brick shape (bx, 8, 4) with bx in {4, 8, 16}.
 struct BrickGrid {
   int nx, ny, nz;    // voxels
   int bx, by, bz;    // brick shape
@@ -46,6 +46,37 @@ struct BrickGrid {
   float ox, oy, oz;  // origin
   float hx, hy, hz;  // spacing
   float ihx, ihy, ihz;  // 1 / spacing
+};
+
+// Several scans (each its own grid and Gaussian set) are processed by the same launches: their
+// Gaussians, bricks, volumes and observations are concatenated, and every kernel finds its scan in a
+// small table passed by value as a kernel argument.  A single scan is the one-entry table.
+constexpr int kMaxScans = 16;
+
+struct ScanDesc {
+  BrickGrid bg;
+  int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated set
+  int64_t b0;     // first (global) brick of the scan
+  int64_t v0;     // first voxel of the scan's volume in the concatenated volumes
+  int64_t o0;     // first LR voxel of the scan's observation in the concatenated observations
+  float gscale;   // fit loss: dL/dI magnitude 1 / (zdown * nLR)
+  float lscale;   // fit loss: 1 / nLR
+};
+
+struct ScanTable {
+  int32_t ns;
+  int64_t n_total, nbricks_total;
+  ScanDesc s[kMaxScans];
+  __host__ __device__ __forceinline__ int of_gauss(int64_t i) const {
+    int k = 0;
+    while (k + 1 < ns && i >= s[k + 1].g0) ++k;
+    return k;
+  }
+  __host__ __device__ __forceinline__ int of_brick(int64_t b) const {
+    int k = 0;
+    while (k + 1 < ns && b >= s[k + 1].b0) ++k;
+    return k;
+  }
 };
 
 // Radix sort tiling.
@@ -77,31 +108,32 @@ struct WsLayout {
 
 // Host-side helpers (api.cpp).
 bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg);
-WsLayout make_layout(int64_t n, const BrickGrid &bg, int64_t cap);
+WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap);
 
 // Launch bookkeeping for the optional kernel timing (api.cpp).
 void prof_begin(hipStream_t s);
 void prof_end(hipStream_t s, const char *name);
 
 // Kernel launchers (bin.hip, render.hip, fit.hip).  Return hipGetLastError() of the launches.
+// `gauss` holds the concatenated Gaussians of all scans of T.
 hipError_t launch_reset(void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_prep_count(const gs_gaussians_t &g, const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L,
-                             hipStream_t s);
+hipError_t launch_prep_count(const ScanTable &T, const gs_gaussians_t &gauss, float cutoff, void *ws,
+                             const WsLayout &L, hipStream_t s);
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_emit(const BrickGrid &bg, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_sort(const BrickGrid &bg, void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_fwd(const BrickGrid &bg, float cutoff, float eps, const void *ws, const WsLayout &L, float *I,
-                      float *W, hipStream_t s);
-hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws, const WsLayout &L, int64_t *d_count,
-                              hipStream_t s);
-hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
-                      const float *W, const float *dLdI, hipStream_t s);
+hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_fwd(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
+                      float *I, float *W, hipStream_t s);
+hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
+                              int64_t *d_count, hipStream_t s);
+hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+                      const float *I, const float *W, const float *dLdI, hipStream_t s);
+hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+                          const float *I, const float *W, const float *obs, float *loss_part, hipStream_t s);
 hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
                                hipStream_t s);
-hipError_t launch_bwd_fit(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
-                          const float *W, const float *obs, float *loss_part, hipStream_t s);
-hipError_t launch_reduce_adam(const gs_fit_state_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
-                              const gs_adam_t &hp, const float *loss_part, int64_t nb, float loss_scale, float *loss,
+hipError_t launch_reduce_adam(const ScanTable &T, const gs_fit_state_t &g, const void *ws, const WsLayout &L,
+                              const gs_grads_t &gr, const gs_adam_t &hp, const float *loss_part, float *loss,
                               hipStream_t s);
 hipError_t launch_loss_mse(const float *I, const float *T, int64_t nvox, float *g, float *loss, void *scratch,
                            hipStream_t s);

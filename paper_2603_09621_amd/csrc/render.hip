@@ -1,24 +1,26 @@
 // Forward and backward rasterizer kernels (§3.2 Eq. (rendering), §3.3).
 //
-// Forward: one workgroup of 256 threads per 8x8x4 brick; each wave owns a 4x4x4 quarter of the
-// brick.  The brick's Gaussian list is staged through LDS in chunks of 256 records; while staging,
-// each Gaussian is tested against the four quarters and every wave compacts the indices of the
-// Gaussians that may touch its quarter.  A wave then keeps four Gaussians in flight: lanes 16g..16g+15
-// (group g) take list entries g, g+4, g+8, ...; each lane owns one voxel row of 4 voxels along x, sets
-// up the row's quadratic once per Gaussian and evaluates the 4 voxels by Horner's rule, the inclusive
-// cutoff test, one exp2 and the two accumulations (numerator S, denominator W).  The four groups'
-// partial sums of a voxel are added in a fixed order at the end, so the result is bitwise
-// deterministic.
+// Bricks are BX x 8 x 4 voxels (BX in {4, 8, 16}; the paper uses 8 x 8 x 4).  Every launch covers
+// the bricks of all scans of a scan table (one workgroup per brick).
 //
-// Backward: one workgroup of two waves per brick, one Gaussian per lane.  The brick's per-voxel
-// factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by
-// their number of rows in the brick so that the lanes of a wave run the same number of iterations;
-// each lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
-// maximum exponent is below the cutoff, evaluates the 8 voxels of a row unrolled, and accumulates
-// per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
-// folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.
-// The sums of each (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel
-// reduces each Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
+// Forward: BX/2 waves per brick; each wave owns a 4x4x4 quarter of the brick.  The brick's Gaussian
+// list is staged through LDS in chunks; while staging, each Gaussian is tested against the quarters
+// and every wave compacts the indices of the Gaussians that may touch its quarter.  A wave keeps four
+// Gaussians in flight: lanes 16g..16g+15 (group g) take list entries g, g+4, g+8, ...; each lane owns
+// one voxel row of 4 voxels along x, sets up the row's quadratic once per Gaussian and evaluates the 4
+// voxels by Horner's rule, the inclusive cutoff test, one exp2 and the two accumulations (numerator
+// S, denominator W).  The four groups' partial sums of a voxel are added in a fixed order at the end,
+// so the result is bitwise deterministic.
+//
+// Backward: two waves per brick, one Gaussian per lane.  The brick's per-voxel factors
+// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by their
+// number of rows in the brick so that the lanes of a wave run the same number of iterations; each
+// lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
+// maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and accumulates per
+// row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w, folded with the row's
+// (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.  The sums of each
+// (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel reduces each
+// Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,14 +30,13 @@
 
 namespace gs {
 
-constexpr int kFwdThreads = 256;
-constexpr int kFwdChunk = 256;
-
-// Conservative test of one Gaussian against the four 4x4x4 quarters of an 8x8x4 brick
-// (quarter index = sx + 2 sy).  Uses the ellipsoid's x/y extents inside the brick's z-slab and
-// inside each half's x- or y-slab.
+// Conservative test of one Gaussian against the quarters of a BX x 8 x 4 brick (quarter index
+// sx + (BX/4) sy).  Uses the ellipsoid's x/y extents inside the brick's z-slab and inside each
+// quarter column's x- or y-slab.
+template <int BX>
 __device__ __forceinline__ uint32_t quarter_mask(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
                                                  int x0, int y0, int z0) {
+  constexpr int NQX = BX / 4;
   if (c.c1.z == 0.f) return 0u;
   const float mx = e.r0.x, my = e.r0.y, mz = e.r0.z;
   const float sxx = c.c0.x, syy = c.c0.y, szz = c.c0.z, sxy = c.c0.w, sxz = c.c1.x, syz = c.c1.y;
@@ -45,55 +46,62 @@ __device__ __forceinline__ uint32_t quarter_mask(const BrickGrid &bg, const Eval
   float xzl, xzh, yzl, yzh;
   if (!extent_in_slab(mx, mz, sxx, szz, sxz, cutoff, Z0, Z1, tx, xzl, xzh)) return 0u;
   if (!extent_in_slab(my, mz, syy, szz, syz, cutoff, Z0, Z1, ty, yzl, yzh)) return 0u;
-  float X0[2], X1[2], Y0[2], Y1[2];
+  float Y0[2], Y1[2], xyl[2], xyh[2];
+  bool okxy[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    X0[h] = centre(bg.ox, bg.hx, x0 + 4 * h);
-    X1[h] = centre(bg.ox, bg.hx, x0 + 4 * h + 3);
     Y0[h] = centre(bg.oy, bg.hy, y0 + 4 * h);
     Y1[h] = centre(bg.oy, bg.hy, y0 + 4 * h + 3);
-  }
-  float xyl[2], xyh[2], yxl[2], yxh[2];
-  bool okxy[2], okyx[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
     okxy[h] = extent_in_slab(mx, my, sxx, syy, sxy, cutoff, Y0[h], Y1[h], tx, xyl[h], xyh[h]);
-    okyx[h] = extent_in_slab(my, mx, syy, sxx, sxy, cutoff, X0[h], X1[h], ty, yxl[h], yxh[h]);
   }
   uint32_t m = 0;
 #pragma unroll
-  for (int sy = 0; sy < 2; ++sy)
+  for (int sx = 0; sx < NQX; ++sx) {
+    const float X0 = centre(bg.ox, bg.hx, x0 + 4 * sx), X1 = centre(bg.ox, bg.hx, x0 + 4 * sx + 3);
+    float yxl, yxh;
+    if (!extent_in_slab(my, mx, syy, sxx, sxy, cutoff, X0, X1, ty, yxl, yxh)) continue;
+    const float yl = fmaxf(yzl, yxl), yh = fminf(yzh, yxh);
 #pragma unroll
-    for (int sx = 0; sx < 2; ++sx) {
-      if (!okxy[sy] || !okyx[sx]) continue;
-      float xl = fmaxf(xzl, xyl[sy]), xh = fminf(xzh, xyh[sy]);
-      float yl = fmaxf(yzl, yxl[sx]), yh = fminf(yzh, yxh[sx]);
-      if (xl <= X1[sx] && xh >= X0[sx] && yl <= Y1[sy] && yh >= Y0[sy]) m |= 1u << (sx + 2 * sy);
+    for (int sy = 0; sy < 2; ++sy) {
+      if (!okxy[sy]) continue;
+      const float xl = fmaxf(xzl, xyl[sy]), xh = fminf(xzh, xyh[sy]);
+      if (xl <= X1 && xh >= X0 && yl <= Y1[sy] && yh >= Y0[sy]) m |= 1u << (sx + NQX * sy);
     }
+  }
   return m;
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, int64_t n, float cutoff, float eps,
-                                                     const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
-                                                     const uint32_t *__restrict__ list_gid,
-                                                     const uint32_t *__restrict__ brick_off, const DevStatus *st,
-                                                     float *__restrict__ I, float *__restrict__ W,
-                                                     unsigned long long *__restrict__ pair_count) {
+__device__ __forceinline__ void brick_coords(const BrickGrid &bg, int64_t lb, int &x0, int &y0, int &z0) {
+  const int kx = (int)(lb % bg.nbx), ky = (int)((lb / bg.nbx) % bg.nby), kz = (int)(lb / ((int64_t)bg.nbx * bg.nby));
+  x0 = kx * bg.bx;
+  y0 = ky * 8;
+  z0 = kz * 4;
+}
+
+template <int BX, bool COUNT>
+__global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff, float eps,
+                                                 const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
+                                                 const uint32_t *__restrict__ list_gid,
+                                                 const uint32_t *__restrict__ brick_off, const DevStatus *st,
+                                                 float *__restrict__ I, float *__restrict__ W,
+                                                 unsigned long long *__restrict__ pair_count) {
+  constexpr int NT = 32 * BX, NW = BX / 2, NQX = BX / 4;
   if (st->overflow) return;
-  __shared__ EvalRec srec[kFwdChunk];
-  __shared__ uint8_t smask[kFwdChunk];
-  __shared__ uint16_t wlist[kFwdThreads / 64][kFwdChunk];
-  __shared__ float4 sred[kFwdThreads / 64][4][16][2];
-  __shared__ unsigned long long scount[kFwdThreads / 64];
+  __shared__ EvalRec srec[NT];
+  __shared__ uint8_t smask[NT];
+  __shared__ uint16_t wlist[NW][NT];
+  __shared__ float4 sred[NW][4][16][2];
+  __shared__ unsigned long long scount[NW];
 
   const int64_t b = blockIdx.x;
-  const int kx = (int)(b % bg.nbx), ky = (int)((b / bg.nbx) % bg.nby), kz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int x0 = kx * 8, y0 = ky * 8, z0 = kz * 4;
+  const ScanDesc &sd = T.s[T.of_brick(b)];
+  const BrickGrid &bg = sd.bg;
+  int x0, y0, z0;
+  brick_coords(bg, b - sd.b0, x0, y0, z0);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int grp = l >> 4, row = l & 15;
-  const int qx0 = x0 + (w & 1) * 4;
-  const int iy = y0 + (w >> 1) * 4 + (row & 3);
+  const int qx0 = x0 + (w % NQX) * 4;
+  const int iy = y0 + (w / NQX) * 4 + (row & 3);
   const int iz = z0 + (row >> 2);
   const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
   float px[4];
@@ -105,15 +113,15 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, int64_t n, fl
 
   float Wa[4] = {0.f, 0.f, 0.f, 0.f}, Sa[4] = {0.f, 0.f, 0.f, 0.f};
   uint32_t npairs = 0;
-  for (uint32_t c0 = start; c0 < end; c0 += kFwdChunk) {
-    const int cnt = (int)min((uint32_t)kFwdChunk, end - c0);
+  for (uint32_t c0 = start; c0 < end; c0 += NT) {
+    const int cnt = (int)min((uint32_t)NT, end - c0);
     if (t < cnt) {
       const uint32_t gid = list_gid[c0 + t];
-      if (gid < n) {
+      if (gid < T.n_total) {
         const EvalRec e = er[gid];
         const CullRec c = cr[gid];
         srec[t] = e;
-        smask[t] = (uint8_t)quarter_mask(bg, e, c, cutoff, x0, y0, z0);
+        smask[t] = (uint8_t)quarter_mask<BX>(bg, e, c, cutoff, x0, y0, z0);
       } else {
         smask[t] = 0;
       }
@@ -121,8 +129,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, int64_t n, fl
     __syncthreads();
     int nw = 0;
     for (int j0 = 0; j0 < cnt; j0 += 64) {
-      bool has = (j0 + l < cnt) && ((smask[j0 + l] >> w) & 1);
-      uint64_t bal = __ballot(has);
+      const bool has = (j0 + l < cnt) && ((smask[j0 + l] >> w) & 1);
+      const uint64_t bal = __ballot(has);
       if (has) wlist[w][nw + __popcll(bal & lt)] = (uint16_t)(j0 + l);
       nw += __popcll(bal);
     }
@@ -156,7 +164,11 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, int64_t n, fl
     for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
     if (l == 0) scount[w] = v;
     __syncthreads();
-    if (t == 0) atomicAdd(pair_count, scount[0] + scount[1] + scount[2] + scount[3]);
+    if (t == 0) {
+      unsigned long long tot = 0;
+      for (int k = 0; k < NW; ++k) tot += scount[k];
+      atomicAdd(pair_count, tot);
+    }
     return;
   }
   sred[w][grp][row][0] = make_float4(Wa[0], Wa[1], Wa[2], Wa[3]);
@@ -171,8 +183,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(BrickGrid bg, int64_t n, fl
       St.x += s2.x; St.y += s2.y; St.z += s2.z; St.w += s2.w;
     }
     const float4 It = make_float4(St.x / (Wt.x + eps), St.y / (Wt.y + eps), St.z / (Wt.z + eps), St.w / (Wt.w + eps));
-    const int64_t v0 = ((int64_t)iz * bg.ny + iy) * bg.nx + qx0;
-    if ((bg.nx & 3) == 0 && qx0 + 3 < bg.nx) {
+    const int64_t v0 = sd.v0 + ((int64_t)iz * bg.ny + iy) * bg.nx + qx0;
+    if ((bg.nx & 3) == 0 && (sd.v0 & 3) == 0 && qx0 + 3 < bg.nx) {
       *reinterpret_cast<float4 *>(I + v0) = It;
       if (W) *reinterpret_cast<float4 *>(W + v0) = Wt;
     } else {
@@ -191,29 +203,39 @@ __global__ void k_zero_u64(unsigned long long *p) {
   if (threadIdx.x == 0) *p = 0ull;
 }
 
-hipError_t launch_fwd(const BrickGrid &bg, float cutoff, float eps, const void *ws, const WsLayout &L, float *I,
-                      float *W, hipStream_t s) {
+template <bool COUNT>
+static hipError_t fwd_dispatch(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
+                               float *I, float *W, unsigned long long *cnt, hipStream_t s) {
   const char *b = (const char *)ws;
-  prof_begin(s);
-  k_fwd<false><<<(unsigned)bg.nbricks, kFwdThreads, 0, s>>>(
-      bg, L.n, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.brick_off),
-      (const DevStatus *)(b + L.status), I, W, nullptr);
-  prof_end(s, "render_fwd");
+  const unsigned nb = (unsigned)T.nbricks_total;
+  if (nb == 0) return hipSuccess;
+  const EvalRec *er = (const EvalRec *)(b + L.evalrec);
+  const CullRec *cr = (const CullRec *)(b + L.cullrec);
+  const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *bo = (const uint32_t *)(b + L.brick_off);
+  const DevStatus *st = (const DevStatus *)(b + L.status);
+  switch (bx) {
+    case 4: k_fwd<4, COUNT><<<nb, 128, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt); break;
+    case 8: k_fwd<8, COUNT><<<nb, 256, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt); break;
+    default: k_fwd<16, COUNT><<<nb, 512, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt); break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws, const WsLayout &L, int64_t *d_count,
-                              hipStream_t s) {
-  const char *b = (const char *)ws;
+hipError_t launch_fwd(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
+                      float *I, float *W, hipStream_t s) {
+  prof_begin(s);
+  hipError_t e = fwd_dispatch<false>(T, bx, cutoff, eps, ws, L, I, W, nullptr, s);
+  prof_end(s, "render_fwd");
+  return e;
+}
+
+hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
+                              int64_t *d_count, hipStream_t s) {
   prof_begin(s);
   k_zero_u64<<<1, 64, 0, s>>>((unsigned long long *)d_count);
-  k_fwd<true><<<(unsigned)bg.nbricks, kFwdThreads, 0, s>>>(
-      bg, L.n, cutoff, 0.f, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.brick_off),
-      (const DevStatus *)(b + L.status), nullptr, nullptr, (unsigned long long *)d_count);
+  hipError_t e = fwd_dispatch<true>(T, bx, cutoff, 0.f, ws, L, nullptr, nullptr, (unsigned long long *)d_count, s);
   prof_end(s, "count_pairs");
-  return hipGetLastError();
+  return e;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -225,7 +247,6 @@ hipError_t launch_count_pairs(const BrickGrid &bg, float cutoff, const void *ws,
 constexpr int kBwdThreads = 128;
 constexpr int kBwdWindow = 2048;  // keys ordered by work per pass over the brick list
 constexpr int kBwdBuckets = 34;   // rows per key in a brick: 0 .. 32 (bucket 0 = 32 rows)
-constexpr int kRowPad = 9;        // LDS row stride in voxels (8 + 1 pad: rows of a wave hit different banks)
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
 __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
@@ -250,72 +271,81 @@ __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, c
 // z-mean (LR slice z0 / 4): per (x, y) column, LR = (((I0 + I1) + I2) + I3) * 1/4 (the loss kernel's
 // order), dL/dI = sign(LR - obs) * gscale on the column's 4 voxels, and the brick's sum of |LR - obs|
 // goes to loss_part[brick] (also for bricks without Gaussians).  Otherwise dL/dI is read from gI.
-template <bool FIT>
-__global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, int64_t cap, float cutoff, float eps,
+template <int BX, bool FIT>
+__global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cutoff, float eps,
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                      const uint32_t *__restrict__ list_gid,
                                                      const uint32_t *__restrict__ list_slot,
                                                      const uint32_t *__restrict__ brick_off, const DevStatus *st,
                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
                                                      const float *__restrict__ gI, const float *__restrict__ obs,
-                                                     float gscale, float *__restrict__ loss_part,
+                                                     float *__restrict__ loss_part, int64_t cap,
                                                      float4 *__restrict__ part) {
+  constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
   if (st->overflow) return;
-  __shared__ float2 sCI[32 * kRowPad];
+  __shared__ float2 sCI[32 * RP];
   __shared__ uint16_t sorder[kBwdWindow];
   __shared__ uint8_t sbucket[kBwdWindow];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   const int64_t b = blockIdx.x;
-  const int kx = (int)(b % bg.nbx), ky = (int)((b / bg.nbx) % bg.nby), kz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int x0 = kx * 8, y0 = ky * 8, z0 = kz * 4;
+  const ScanDesc &sd = T.s[T.of_brick(b)];
+  const BrickGrid &bg = sd.bg;
+  int x0, y0, z0;
+  brick_coords(bg, b - sd.b0, x0, y0, z0);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const uint32_t start = brick_off[b], end = brick_off[b + 1];
   if (FIT) {
-    // 64 columns of 4 voxels; threads 0..63 (wave 0) own one column each
+    // BX * 8 columns of 4 voxels, one per thread
     float absd = 0.f;
-    if (t < 64) {
-      const int lx = t & 7, ly = t >> 3;
+    if (t < BX * 8) {
+      const int lx = t % BX, ly = t / BX;
       const int gx = x0 + lx, gy = y0 + ly;
       float c4[4] = {0.f, 0.f, 0.f, 0.f}, i4[4] = {0.f, 0.f, 0.f, 0.f};
       if (gx < bg.nx && gy < bg.ny) {
         const int64_t plane = (int64_t)bg.nx * bg.ny;
-        const int64_t g0 = ((int64_t)z0 * bg.ny + gy) * bg.nx + gx;
+        const int64_t g0 = sd.v0 + ((int64_t)z0 * bg.ny + gy) * bg.nx + gx;
 #pragma unroll
         for (int z = 0; z < 4; ++z) i4[z] = Iv[g0 + z * plane];
         const float lr = (((i4[0] + i4[1]) + i4[2]) + i4[3]) * 0.25f;
-        const float d = lr - obs[((int64_t)(z0 >> 2) * bg.ny + gy) * bg.nx + gx];
-        const float sg = d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
+        const float d = lr - obs[sd.o0 + ((int64_t)(z0 >> 2) * bg.ny + gy) * bg.nx + gx];
+        const float sg = d > 0.f ? sd.gscale : (d < 0.f ? -sd.gscale : 0.f);
         absd = fabsf(d);
 #pragma unroll
         for (int z = 0; z < 4; ++z) c4[z] = sg / (Wv[g0 + z * plane] + eps);
       }
 #pragma unroll
-      for (int z = 0; z < 4; ++z) sCI[(z * 8 + ly) * kRowPad + lx] = make_float2(c4[z], i4[z]);
-#pragma unroll
-      for (int d = 32; d > 0; d >>= 1) absd += __shfl_down(absd, d, 64);
-      if (t == 0) loss_part[b] = absd;
+      for (int z = 0; z < 4; ++z) sCI[(z * 8 + ly) * RP + lx] = make_float2(c4[z], i4[z]);
     }
+    // the brick's loss sum: wave 0 reduces the first 64 columns, wave 1 the rest (if any); the two
+    // halves are added by thread 0 in a fixed order
+    float wsum = absd;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) wsum += __shfl_down(wsum, d, 64);
+    __shared__ float swsum[2];
+    if (l == 0) swsum[w] = wsum;
+    __syncthreads();
+    if (t == 0) loss_part[b] = swsum[0] + swsum[1];
   } else {
     if (start == end) return;
     // per voxel of the brick: c = dL/dI / (W + eps) and I; zero outside the grid, so that voxels
     // beyond the grid's edge contribute nothing
-    for (int v = t; v < 256; v += kBwdThreads) {
-      const int lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+    for (int v = t; v < BX * 32; v += kBwdThreads) {
+      const int lx = v % BX, ly = (v / BX) & 7, lz = v / (BX * 8);
       const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
       float c = 0.f, iv = 0.f;
       if (gx < bg.nx && gy < bg.ny && gz < bg.nz) {
-        const int64_t g = ((int64_t)gz * bg.ny + gy) * bg.nx + gx;
+        const int64_t g = sd.v0 + ((int64_t)gz * bg.ny + gy) * bg.nx + gx;
         c = gI[g] / (Wv[g] + eps);
         iv = Iv[g];
       }
-      sCI[(lz * 8 + ly) * kRowPad + lx] = make_float2(c, iv);
+      sCI[(lz * 8 + ly) * RP + lx] = make_float2(c, iv);
     }
   }
   if (start == end) return;
-  float px[8];
+  float px[BX];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) px[k] = centre(bg.ox, bg.hx, x0 + k);
-  const int xe = min(x0 + 7, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
+  for (int k = 0; k < BX; ++k) px[k] = centre(bg.ox, bg.hx, x0 + k);
+  const int xe = min(x0 + BX - 1, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
   for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
     const int L = (int)min((uint32_t)kBwdWindow, end - w0);
     // order the window's keys by their number of rows in the brick, most first, so that the lanes of
@@ -326,7 +356,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
     for (int j = t; j < L; j += kBwdThreads) {
       const uint32_t gid = list_gid[w0 + j];
       int bk = kBwdBuckets - 1;
-      if (gid < n) {
+      if (gid < T.n_total) {
         int xl, xh, yl, yh, zl, zh;
         key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
         if (xl <= xh && yl <= yh && zl <= zh) bk = 32 - (yh - yl + 1) * (zh - zl + 1);
@@ -351,7 +381,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
       const uint32_t k = w0 + sorder[p];
       const uint32_t gid = list_gid[k];
       const uint32_t slot = list_slot[k];
-      if (gid >= n || (int64_t)slot >= cap) continue;
+      if (gid >= T.n_total || (int64_t)slot >= cap) continue;
       const EvalRec R = er[gid];
       const CullRec C = cr[gid];
       const float mx = R.r0.x, A = R.r0.w;
@@ -373,10 +403,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
         const float xs = -bq * inv2a;
         const float qmax = fmaf(0.5f * bq, xs, cq);
         if (qmax >= thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) {
-          const int rb = ((iz - z0) * 8 + (iy - y0)) * kRowPad;
+          const int rb = ((iz - z0) * 8 + (iy - y0)) * RP;
           float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
-          for (int kk = 0; kk < 8; ++kk) {
+          for (int kk = 0; kk < BX; ++kk) {
             const float dx = px[kk] - mx;
             const float q = row_q(a, bq, cq, dx);
             float wt = fast_exp2(q);
@@ -417,30 +447,50 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BrickGrid bg, int64_t n, in
   }
 }
 
-hipError_t launch_bwd(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
-                      const float *W, const float *dLdI, hipStream_t s) {
+template <bool FIT>
+static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+                               const float *I, const float *W, const float *gI, const float *obs, float *loss_part,
+                               hipStream_t s) {
   char *b = (char *)ws;
-  prof_begin(s);
-  k_bwd<false><<<(unsigned)bg.nbricks, kBwdThreads, 0, s>>>(
-      bg, L.n, L.cap, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.list_slot), (const uint32_t *)(b + L.brick_off),
-      (const DevStatus *)(b + L.status), I, W, dLdI, nullptr, 0.f, nullptr, (float4 *)(b + L.partials));
-  prof_end(s, "render_bwd");
+  const unsigned nb = (unsigned)T.nbricks_total;
+  if (nb == 0) return hipSuccess;
+  const EvalRec *er = (const EvalRec *)(b + L.evalrec);
+  const CullRec *cr = (const CullRec *)(b + L.cullrec);
+  const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *ls = (const uint32_t *)(b + L.list_slot);
+  const uint32_t *bo = (const uint32_t *)(b + L.brick_off);
+  const DevStatus *st = (const DevStatus *)(b + L.status);
+  float4 *part = (float4 *)(b + L.partials);
+  switch (bx) {
+    case 4:
+      k_bwd<4, FIT><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
+                                               part);
+      break;
+    case 8:
+      k_bwd<8, FIT><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
+                                               part);
+      break;
+    default:
+      k_bwd<16, FIT><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part,
+                                                L.cap, part);
+      break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_fit(const BrickGrid &bg, float cutoff, float eps, void *ws, const WsLayout &L, const float *I,
-                          const float *W, const float *obs, float *loss_part, hipStream_t s) {
-  char *b = (char *)ws;
-  const int64_t nlr = (int64_t)bg.nx * bg.ny * (bg.nz / 4);
-  const float gscale = (float)(1.0 / (4.0 * (double)nlr));
+hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+                      const float *I, const float *W, const float *dLdI, hipStream_t s) {
   prof_begin(s);
-  k_bwd<true><<<(unsigned)bg.nbricks, kBwdThreads, 0, s>>>(
-      bg, L.n, L.cap, cutoff, eps, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-      (const uint32_t *)(b + L.list_gid), (const uint32_t *)(b + L.list_slot), (const uint32_t *)(b + L.brick_off),
-      (const DevStatus *)(b + L.status), I, W, nullptr, obs, gscale, loss_part, (float4 *)(b + L.partials));
+  hipError_t e = bwd_dispatch<false>(T, bx, cutoff, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
   prof_end(s, "render_bwd");
-  return hipGetLastError();
+  return e;
+}
+
+hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+                          const float *I, const float *W, const float *obs, float *loss_part, hipStream_t s) {
+  prof_begin(s);
+  hipError_t e = bwd_dispatch<true>(T, bx, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
+  prof_end(s, "render_bwd");
+  return e;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -574,7 +624,8 @@ __global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const 
 
 // Fused gradient + Adam for the fit step: the gradient of Gaussian i (as k_reduce_chain, also
 // written to the gradient outputs) and the bias-corrected Adam update of its 12 parameters, moments
-// in the group layout mu (3n), log_scale (3n), quat (4n), amp (n), relax (n).  Step t = *step + 1.
+// in the group layout mu (3n), log_scale (3n), quat (4n), amp (n), relax (n).  Each scan of the table
+// has its own step counter: Gaussian i of scan k takes step t = step[k] + 1.
 struct AdamArgs {
   float lr[5];
   float b1, b2, eps;
@@ -590,7 +641,7 @@ __device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, 
   if (lr != 0.f) p -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
 }
 
-__global__ void k_reduce_adam(int64_t n, float *__restrict__ mu, float *__restrict__ ls, float *__restrict__ quat,
+__global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ mu, float *__restrict__ ls, float *__restrict__ quat,
                               float *__restrict__ amp, float *__restrict__ relax, const uint32_t *__restrict__ off,
                               const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
                               float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
@@ -604,7 +655,7 @@ __global__ void k_reduce_adam(int64_t n, float *__restrict__ mu, float *__restri
   if (i >= n) return;
   float g[12];
   gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
-  const float t = (float)(*step + 1);
+  const float t = (float)(step[T.of_gauss(i)] + 1);
   const float bc1 = -expm1f(t * h.lnb1), bc2 = -expm1f(t * h.lnb2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -628,25 +679,29 @@ __global__ void k_reduce_adam(int64_t n, float *__restrict__ mu, float *__restri
   }
 }
 
-// Fit-step epilogue: loss = (sum of the per-brick partial sums, fixed order) * scale; step += 1.
-__global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ loss_part, int64_t nb, float scale,
+// Fit-step epilogue, one block per scan: loss[s] = (sum of the scan's per-brick partial sums, fixed
+// order) * lscale (skipped when loss_part is NULL: the loss was computed by the loss kernel) and the
+// scan's step counter advances.
+__global__ __launch_bounds__(256) void k_fit_finalize(const ScanTable T, const float *__restrict__ loss_part,
                                                       float *__restrict__ loss, int32_t *__restrict__ step,
                                                       const DevStatus *st) {
   __shared__ float sh[4];
+  const ScanDesc &sd = T.s[blockIdx.x];
   float acc = 0.f;
-  for (int64_t i = threadIdx.x; i < nb; i += 256) acc += loss_part[i];
+  if (loss_part)
+    for (int64_t i = threadIdx.x; i < sd.bg.nbricks; i += 256) acc += loss_part[sd.b0 + i];
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0 && !st->overflow) {
-    *loss = (((sh[0] + sh[1]) + sh[2]) + sh[3]) * scale;
-    *step += 1;
+    if (loss_part) loss[blockIdx.x] = (((sh[0] + sh[1]) + sh[2]) + sh[3]) * sd.lscale;
+    step[blockIdx.x] += 1;
   }
 }
 
-hipError_t launch_reduce_adam(const gs_fit_state_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
-                              const gs_adam_t &hp, const float *loss_part, int64_t nb, float loss_scale, float *loss,
+hipError_t launch_reduce_adam(const ScanTable &T, const gs_fit_state_t &g, const void *ws, const WsLayout &L,
+                              const gs_grads_t &gr, const gs_adam_t &hp, const float *loss_part, float *loss,
                               hipStream_t s) {
   const char *b = (const char *)ws;
   AdamArgs h;
@@ -659,10 +714,10 @@ hipError_t launch_reduce_adam(const gs_fit_state_t &g, const void *ws, const WsL
   prof_begin(s);
   if (g.n > 0)
     k_reduce_adam<<<(unsigned)((g.n + kRedThreads - 1) / kRedThreads), kRedThreads, 0, s>>>(
-        g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, (const uint32_t *)(b + L.off),
+        T, g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, (const uint32_t *)(b + L.off),
         (const float4 *)(b + L.partials), (const DevStatus *)(b + L.status), gr.d_mu, gr.d_log_scale, gr.d_quat,
         gr.d_amp, gr.d_relax, g.m, g.v, g.step, h);
-  k_fit_finalize<<<1, 256, 0, s>>>(loss_part, nb, loss_scale, loss, g.step, (const DevStatus *)(b + L.status));
+  k_fit_finalize<<<(unsigned)T.ns, 256, 0, s>>>(T, loss_part, loss, g.step, (const DevStatus *)(b + L.status));
   prof_end(s, "reduce_adam");
   return hipGetLastError();
 }

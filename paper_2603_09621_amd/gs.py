@@ -85,6 +85,10 @@ class gs_fit_buffers_t(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_size_t), ("loss", _vp)]
 
 
+class gs_batch_t(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int64)), ("grid", ctypes.POINTER(gs_grid_t))]
+
+
 class gs_status_t(ctypes.Structure):
     _fields_ = [("n_keys", ctypes.c_int64), ("overflow", ctypes.c_int32), ("nonfinite", ctypes.c_int32)]
 
@@ -104,6 +108,16 @@ _sigs = {
     "gs_adam_step": [_P(gs_fit_state_t), _P(gs_grads_t), _P(gs_adam_t), _P(gs_bins_t), _vp],
     "gs_fit_step": [_P(gs_fit_state_t), _vp, _P(gs_fit_opts_t), _P(gs_bins_t), _P(gs_fit_buffers_t), _vp],
     "gs_status": [_P(gs_bins_t), _vp, _P(gs_status_t)],
+    "gs_workspace_size_batch": [_P(gs_batch_t), _P(gs_opts_t), ctypes.c_int64, _P(ctypes.c_size_t)],
+    "gs_bin_query_batch": [_P(gs_gaussians_t), _P(gs_batch_t), _P(gs_opts_t), _P(gs_bins_t), _vp,
+                           _P(ctypes.c_int64)],
+    "gs_bin_batch": [_P(gs_gaussians_t), _P(gs_batch_t), _P(gs_opts_t), _P(gs_bins_t), _vp],
+    "gs_render_fwd_batch": [_P(gs_gaussians_t), _P(gs_batch_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp, _vp],
+    "gs_count_pairs_batch": [_P(gs_gaussians_t), _P(gs_batch_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp],
+    "gs_render_bwd_batch": [_P(gs_gaussians_t), _P(gs_batch_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp, _vp,
+                            _P(gs_grads_t), _vp],
+    "gs_fit_step_batch": [_P(gs_fit_state_t), _vp, _P(gs_batch_t), _P(gs_fit_opts_t), _P(gs_bins_t),
+                          _P(gs_fit_buffers_t), _vp],
     "gs_profile_enable": [ctypes.c_int],
     "gs_profile_reset": [],
     "gs_profile_read": [_vp, ctypes.c_int, _vp, _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_int)],
@@ -116,10 +130,14 @@ _lib.gs_loss_scratch_bytes.argtypes = [ctypes.c_int64]
 _lib.gs_loss_scratch_bytes.restype = ctypes.c_size_t
 _lib.gs_fit_scratch_bytes.argtypes = [_P(gs_grid_t)]
 _lib.gs_fit_scratch_bytes.restype = ctypes.c_size_t
+_lib.gs_fit_scratch_bytes_batch.argtypes = [_P(gs_batch_t)]
+_lib.gs_fit_scratch_bytes_batch.restype = ctypes.c_size_t
 _lib.gs_last_error.argtypes = []
 _lib.gs_last_error.restype = ctypes.c_char_p
 
-EXPORTED = tuple(_sigs) + ("gs_loss_scratch_bytes", "gs_fit_scratch_bytes", "gs_last_error")
+EXPORTED = tuple(_sigs) + ("gs_loss_scratch_bytes", "gs_fit_scratch_bytes", "gs_fit_scratch_bytes_batch",
+                           "gs_last_error")
+MAX_SCANS = 16
 
 
 def gs_last_error() -> str:
@@ -205,6 +223,46 @@ class Opts:
 GROUPS = ("mu", "log_scale", "quat", "amp", "relax")
 
 
+class Batch:
+    """Scans handled by the same launches: Gaussian counts and grids, in concatenation order."""
+
+    def __init__(self, ns: Sequence[int], grids: Sequence[Grid]):
+        if len(ns) != len(grids):
+            raise ValueError("one Gaussian count per grid expected")
+        self.ns = [int(n) for n in ns]
+        self.grids = list(grids)
+
+    def __len__(self) -> int:
+        return len(self.ns)
+
+    @property
+    def n_total(self) -> int:
+        return sum(self.ns)
+
+    @property
+    def g_offsets(self):
+        return [sum(self.ns[:k]) for k in range(len(self.ns) + 1)]
+
+    @property
+    def v_offsets(self):
+        return [sum(g.size for g in self.grids[:k]) for k in range(len(self.grids) + 1)]
+
+    def lr_offsets(self, zdown: int):
+        return [sum(g.size // zdown for g in self.grids[:k]) for k in range(len(self.grids) + 1)]
+
+    def split(self, flat: torch.Tensor):
+        """Per-scan [nz, ny, nx] views of a concatenated volume."""
+        o = self.v_offsets
+        return [flat[o[k]:o[k + 1]].view(g.shape) for k, g in enumerate(self.grids)]
+
+    def c(self) -> gs_batch_t:
+        narr = (ctypes.c_int64 * len(self.ns))(*self.ns)
+        garr = (gs_grid_t * len(self.grids))(*[g.c() for g in self.grids])
+        b = gs_batch_t(len(self.ns), narr, garr)
+        b._keep = (narr, garr)  # the arrays must outlive the call
+        return b
+
+
 @dataclass
 class Gaussians:
     """Device tensors of one Gaussian set (float32, contiguous)."""
@@ -251,12 +309,29 @@ def gs_fit_scratch_bytes(grid: "Grid") -> int:
     return int(_lib.gs_fit_scratch_bytes(ctypes.byref(grid.c())))
 
 
-class Bins:
-    """Caller-owned binning workspace (a uint8 device tensor) for one Gaussian count and grid."""
+def gs_workspace_size_batch(batch: Batch, opts: Opts, key_capacity: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.gs_workspace_size_batch(ctypes.byref(batch.c()), ctypes.byref(opts.c()), key_capacity,
+                                        ctypes.byref(out)))
+    return int(out.value)
 
-    def __init__(self, n: int, grid: Grid, opts: Opts, key_capacity: int, device="cuda"):
-        self.n, self.grid, self.opts, self.key_capacity = n, grid, opts, int(key_capacity)
-        self.ws_bytes = gs_workspace_size(n, grid, opts, self.key_capacity)
+
+def gs_fit_scratch_bytes_batch(batch: Batch) -> int:
+    return int(_lib.gs_fit_scratch_bytes_batch(ctypes.byref(batch.c())))
+
+
+class Bins:
+    """Caller-owned binning workspace (a uint8 device tensor) for one Gaussian count and grid, or
+    for a batch of scans (``grid`` a Batch; ``n`` is then ignored)."""
+
+    def __init__(self, n: int, grid, opts: Opts, key_capacity: int, device="cuda"):
+        self.grid, self.opts, self.key_capacity = grid, opts, int(key_capacity)
+        if isinstance(grid, Batch):
+            self.n = grid.n_total
+            self.ws_bytes = gs_workspace_size_batch(grid, opts, self.key_capacity)
+        else:
+            self.n = n
+            self.ws_bytes = gs_workspace_size(n, grid, opts, self.key_capacity)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
 
     def c(self) -> gs_bins_t:
@@ -328,6 +403,38 @@ def gs_loss_l1_zmean(I: torch.Tensor, obs: torch.Tensor, grid: Grid, zdown: int,
                                  _stream(stream)))
 
 
+def gs_bin_query_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    _check(_lib.gs_bin_query_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+                                   ctypes.byref(bins.c()), _stream(stream), ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_bin_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, stream=None) -> None:
+    _check(_lib.gs_bin_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+                             ctypes.byref(bins.c()), _stream(stream)))
+
+
+def gs_render_fwd_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, I: torch.Tensor,
+                        W: Optional[torch.Tensor] = None, stream=None) -> None:
+    _check(_lib.gs_render_fwd_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+                                    ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _stream(stream)))
+
+
+def gs_count_pairs_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, out: torch.Tensor, stream=None) -> None:
+    if out.dtype != torch.int64:
+        raise ValueError("int64 tensor expected")
+    _check(_lib.gs_count_pairs_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+                                     ctypes.byref(bins.c()), _ptr(out), _stream(stream)))
+
+
+def gs_render_bwd_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, I: torch.Tensor, W: torch.Tensor,
+                        dL_dI: torch.Tensor, grads: "Grads", stream=None) -> None:
+    _check(_lib.gs_render_bwd_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+                                    ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _ptr(_f32(dL_dI)),
+                                    ctypes.byref(grads.c()), _stream(stream)))
+
+
 def gs_status(bins: Bins, stream=None, raise_on_error: bool = True):
     st = gs_status_t()
     rc = _lib.gs_status(ctypes.byref(bins.c()), _stream(stream), ctypes.byref(st))
@@ -374,6 +481,38 @@ def plan_bins(g: Gaussians, grid: Grid, opts: Opts, headroom: float = 1.25, min_
     return Bins(g.n, grid, opts, max(min_capacity, int(math.ceil(k * headroom))), device=probe.ws.device)
 
 
+def plan_bins_batch(g: Gaussians, batch: Batch, opts: Opts, headroom: float = 1.25, min_capacity: int = 1024,
+                    stream=None) -> Bins:
+    probe = Bins(0, batch, opts, 0, device=g.amp.device if g.n else "cuda")
+    k = gs_bin_query_batch(g, batch, opts, probe, stream)
+    return Bins(0, batch, opts, max(min_capacity, int(math.ceil(k * headroom))), device=probe.ws.device)
+
+
+def concat(gs_: Sequence[Gaussians]) -> Gaussians:
+    """One Gaussian set holding the given sets in order (the batch layout)."""
+    cat = lambda k: torch.cat([getattr(x, k) for x in gs_]).contiguous()  # noqa: E731
+    relax = None
+    if any(x.relax is not None for x in gs_):
+        relax = torch.cat([x.relax if x.relax is not None else torch.ones_like(x.amp) for x in gs_]).contiguous()
+    return Gaussians(cat("mu"), cat("log_scale"), cat("quat"), cat("amp"), relax)
+
+
+def render_batch(g: Gaussians, batch: Batch, opts: Optional[Opts] = None, bins: Optional[Bins] = None,
+                 want_w: bool = True, stream=None):
+    """Bin + forward of every scan of the batch in one launch per phase.  Returns the concatenated
+    (I, W) (flat float32) and the bins; ``batch.split`` gives the per-scan volumes."""
+    opts = opts or Opts()
+    if bins is None:
+        bins = plan_bins_batch(g, batch, opts, stream=stream)
+    dev = bins.ws.device
+    nv = batch.v_offsets[-1]
+    I = torch.empty(nv, dtype=torch.float32, device=dev)
+    W = torch.empty(nv, dtype=torch.float32, device=dev) if want_w else None
+    gs_bin_batch(g, batch, opts, bins, stream)
+    gs_render_fwd_batch(g, batch, opts, bins, I, W, stream)
+    return I, W, bins
+
+
 def render(g: Gaussians, grid: Grid, opts: Optional[Opts] = None, bins: Optional[Bins] = None, want_w: bool = True,
            stream=None):
     """Bin + forward.  Returns (I, W, bins) with I, W float32 [nz, ny, nx] (W None if not wanted)."""
@@ -406,15 +545,16 @@ class Adam:
 
 
 class FitState:
-    """Parameters (updated in place), Adam moments and the device step counter of one fit."""
+    """Parameters (updated in place), Adam moments and the device step counter(s) of a fit (one
+    counter per scan of a batch)."""
 
-    def __init__(self, g: Gaussians):
+    def __init__(self, g: Gaussians, nscans: int = 1):
         self.g = g
         n = g.n
         dev = g.amp.device
         self.m = torch.zeros(12 * n, dtype=torch.float32, device=dev)
         self.v = torch.zeros(12 * n, dtype=torch.float32, device=dev)
-        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.step = torch.zeros(nscans, dtype=torch.int32, device=dev)
 
     def c(self) -> gs_fit_state_t:
         g = self.g
@@ -428,13 +568,22 @@ def gs_adam_step(st: FitState, grads: Grads, hp: Adam, bins: Optional[Bins] = No
 
 
 class FitBuffers:
-    def __init__(self, n: int, grid: Grid, relax: bool, device="cuda"):
+    """Per-step buffers of a fit on one grid, or on a batch (``grid`` a Batch: concatenated flat
+    volumes, one loss per scan)."""
+
+    def __init__(self, n: int, grid, relax: bool, device="cuda", need_dL_dI: bool = True):
         f = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)  # noqa: E731
-        self.I, self.W, self.dL_dI = f(grid.shape), f(grid.shape), f(grid.shape)
+        if isinstance(grid, Batch):
+            shape, nloss, n = (grid.v_offsets[-1],), len(grid), grid.n_total
+            sb = gs_fit_scratch_bytes_batch(grid)
+        else:
+            shape, nloss = grid.shape, 1
+            sb = max(gs_loss_scratch_bytes(grid.size), gs_fit_scratch_bytes(grid))
+        self.I, self.W = f(shape), f(shape)
+        self.dL_dI = f(shape) if need_dL_dI else None
         self.grads = Grads.empty(n, relax, device)
-        self.scratch = torch.empty(max(gs_loss_scratch_bytes(grid.size), gs_fit_scratch_bytes(grid)),
-                                   dtype=torch.uint8, device=device)
-        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.scratch = torch.empty(sb, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(nloss, dtype=torch.float32, device=device)
 
     def c(self) -> gs_fit_buffers_t:
         return gs_fit_buffers_t(_ptr(self.I), _ptr(self.W), _ptr(self.dL_dI), self.grads.c(), _ptr(self.scratch),
@@ -443,15 +592,26 @@ class FitBuffers:
 
 @dataclass
 class FitOpts:
-    grid: Grid
+    """Fit options; ``grid`` is the HR grid of a single-scan fit (a batch carries its own grids and
+    may leave it None)."""
+
+    grid: Optional[Grid] = None
     opts: Opts = field(default_factory=Opts)
     zdown: int = 4
     adam: Adam = field(default_factory=Adam)
 
     def c(self) -> gs_fit_opts_t:
-        return gs_fit_opts_t(self.grid.c(), self.opts.c(), self.zdown, 0, self.adam.c())
+        grid = self.grid if self.grid is not None else Grid(1, 1, 1)
+        return gs_fit_opts_t(grid.c(), self.opts.c(), self.zdown, 0, self.adam.c())
 
 
 def gs_fit_step(st: FitState, lr_obs: torch.Tensor, fo: FitOpts, bins: Bins, buf: FitBuffers, stream=None) -> None:
     _check(_lib.gs_fit_step(ctypes.byref(st.c()), _ptr(_f32(lr_obs)), ctypes.byref(fo.c()), ctypes.byref(bins.c()),
                             ctypes.byref(buf.c()), _stream(stream)))
+
+
+def gs_fit_step_batch(st: FitState, lr_obs: torch.Tensor, batch: Batch, fo: FitOpts, bins: Bins, buf: FitBuffers,
+                      stream=None) -> None:
+    _check(_lib.gs_fit_step_batch(ctypes.byref(st.c()), _ptr(_f32(lr_obs)), ctypes.byref(batch.c()),
+                                  ctypes.byref(fo.c()), ctypes.byref(bins.c()), ctypes.byref(buf.c()),
+                                  _stream(stream)))

@@ -130,7 +130,8 @@ def phantom(seed, dims: Sequence[int], n_ellipsoids: int = 60, noise: float = 0.
             u = X * np.float32(rot[0, k]) + Y * np.float32(rot[1, k]) + Z * np.float32(rot[2, k])
             rho2 += (u / np.float32(ax[k])) ** 2
         rho = np.sqrt(rho2)
-        m = (1.0 / (1.0 + np.exp(-(1.0 - rho) / edge))).astype(np.float32)
+        with np.errstate(over="ignore"):  # exp overflows to inf far outside: m = 0 there
+            m = (1.0 / (1.0 + np.exp(-(1.0 - rho) / edge))).astype(np.float32)
         m[rho > 2.0] = 0.0
         sub = V[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
         sub *= (1.0 - m)
@@ -199,3 +200,49 @@ def workload_aniso(seed: int = 3, dims=(320, 320, 256), n: int = 2000000):
     p = gaussians_uniform(seed, n, dims, ls_std=0.8, max_ratio=8.0)
     T = uniform_volume(seed + 1000, dims)
     return p, T
+
+
+def _round_to(x: float, m: int) -> int:
+    return max(m, int(round(x / m)) * m)
+
+
+def batch_dims(j: int, nscans: int = 16):
+    """Grid of scan j of the uneven batch: nx = ny = round_8(96 + 160 j / (S - 1)),
+    nz = round_4(96 + 64 j / (S - 1))."""
+    t = j / max(nscans - 1, 1)
+    nxy = _round_to(96 + 160 * t, 8)
+    return (nxy, nxy, _round_to(96 + 64 * t, 4))
+
+
+def lattice_stride(lr_shape, n: int) -> int:
+    """Largest in-plane lattice stride whose site count is still >= n (at least 1)."""
+    nzl, ny, nx = lr_shape
+    s = 1
+    while (nx // (s + 1)) * (ny // (s + 1)) * nzl >= n:
+        s += 1
+    return s
+
+
+def workload_batch(seed: int = 4, nscans: int = 16, f: int = 4, n_range=(5e4, 8e5), workers: int = 8):
+    """Batch of uneven single-scan fits.  Scan j (before shuffling) has the grid of batch_dims(j);
+    its Gaussian count is exp(U(ln lo, ln hi)) (drawn with ``seed``), capped at the number of LR
+    voxels (a stride-1 lattice); its HR phantom uses seed 100 + j, its LR observation is the z-mean of
+    f, and its Gaussians sit on the coarsest in-plane lattice with enough sites (lattice_init, seed
+    200 + j).  The scan order is shuffled with ``seed``.  Returns a list of (params, lr_obs, dims)."""
+    rng = _rng(seed)
+    ns = np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]), nscans))
+    order = rng.permutation(nscans)
+
+    def one(j):
+        dims = batch_dims(int(j), nscans)
+        hr = phantom(100 + int(j), dims)
+        lr = zmean_observation(hr, f)
+        n = int(min(round(ns[j]), lr.size))
+        p = lattice_init(200 + int(j), lr, n, f, stride_xy=lattice_stride(lr.shape, n))
+        return p, lr, dims
+
+    # each scan has its own generators, so running them on threads changes nothing
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        return list(ex.map(one, order))

@@ -56,3 +56,33 @@ def test_workspace_grows_with_n_and_capacity():
     assert c - b >= 100000 * (2 * 4 + 48)
     assert gs.gs_loss_scratch_bytes(1) >= 4
     assert gs.gs_loss_scratch_bytes(10 ** 7) >= 4 * (10 ** 7 // 4096)
+
+
+def test_brick_shapes():
+    for bx in (4, 8, 16):
+        assert gs.brick_supported(bx, 8, 4)
+    for shape in ((8, 4, 4), (8, 8, 8), (2, 8, 4), (32, 8, 4), (12, 8, 4)):
+        assert not gs.brick_supported(*shape)
+
+
+def test_batch_sizes_and_checks():
+    o = gs.Opts()
+    grids = [gs.Grid(24, 16, 8), gs.Grid(40, 8, 12), gs.Grid(8, 8, 4)]
+    ns = [100, 0, 37]
+    b = gs.Batch(ns, grids)
+    # a batch of one scan sizes like the single-scan call
+    for k in range(3):
+        one = gs.Batch([ns[k]], [grids[k]])
+        assert gs.gs_workspace_size_batch(one, o, 500) == gs.gs_workspace_size(ns[k], grids[k], o, 500)
+        assert gs.gs_fit_scratch_bytes_batch(one) == gs.gs_fit_scratch_bytes(grids[k])
+    whole = gs.gs_workspace_size_batch(b, o, 500)
+    assert whole >= gs.gs_workspace_size(sum(ns), grids[0], o, 500)
+    # fit scratch: one float per brick of the narrowest brick shape, summed over the scans
+    bricks4 = sum(-(-g.nx // 4) * -(-g.ny // 8) * -(-g.nz // 4) for g in grids)
+    assert gs.gs_fit_scratch_bytes_batch(b) >= 4 * bricks4
+    for bad in (gs.Batch([], []), gs.Batch([1] * 17, [grids[0]] * 17), gs.Batch([-1], [grids[0]]),
+                gs.Batch([1], [gs.Grid(0, 4, 4)])):
+        with pytest.raises(gs.GSError) as e:
+            gs.gs_workspace_size_batch(bad, o, 10)
+        assert e.value.code == gs.GS_ERR_INVALID_ARG
+    assert gs.gs_fit_scratch_bytes_batch(gs.Batch([], [])) == 0

@@ -1,0 +1,185 @@
+"""Brick widths and batches of scans.
+
+* Every supported brick width (4, 8, 16 voxels along x; 8 x 4 in y x z) matches the oracle at the
+  parity tolerances, and the useful-pair count (an integer) is the same for all widths.
+* A batch of uneven scans (different grids, spacings and Gaussian counts, one launch per phase)
+  gives, for every scan, bitwise the same forward, gradients and fit steps as the single-scan
+  calls on that scan alone.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_09621_amd import synth
+from tests import cases
+from tests.gpu_util import assert_fwd_close, assert_grad_close, gs_mod, np64, say, to_grid
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = (4, 8, 16)
+
+
+def _case(seed, dims, n, std=0.5, ratio=6.0, ls_mean=None):
+    p, grid = cases.small_case(seed, dims=dims, n=n, ls_std=std, max_ratio=ratio, ls_mean=ls_mean)
+    p["relax"] = np.random.default_rng(seed).uniform(0.3, 1.0, n).astype(np.float32)
+    return p, grid
+
+
+@pytest.mark.parametrize("bx", WIDTHS)
+def test_brick_width_matches_oracle(bx):
+    gs = gs_mod()
+    for seed, dims, n, lsm in ((201, (37, 26, 14), 300, None), (202, (44, 40, 20), 40, math.log(4.0))):
+        p, grid = _case(seed, dims, n, ls_mean=lsm)
+        say("brick width", bx, grid.shape, n)
+        g = gs.Gaussians.from_numpy(p)
+        ggrid = to_grid(grid)
+        opts = gs.Opts(bx=bx)
+        I, W, bins = gs.render(g, ggrid, opts)
+        gs.gs_status(bins)
+        Io, Wo, _ = oracle.render(p, grid)
+        assert_fwd_close(np64(W), Wo, f"bx{bx} W")
+        assert_fwd_close(np64(I), Io, f"bx{bx} I")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gs.gs_count_pairs(g, ggrid, opts, bins, cnt)
+        assert int(cnt.item()) == oracle.count_pairs(p, grid)
+        T = synth.uniform_volume(seed, dims)
+        _, go = oracle.mse_loss(Io, T)
+        I32, W32, g32 = (x.astype(np.float32) for x in (Io, Wo, go))
+        d = torch.device("cuda")
+        grads = gs.backward(g, ggrid, opts, bins, torch.from_numpy(I32).to(d), torch.from_numpy(W32).to(d),
+                            torch.from_numpy(g32).to(d))
+        ref = oracle.grad(p, grid, I32.astype(np.float64), W32.astype(np.float64), g32.astype(np.float64))
+        for k in oracle.GROUPS:
+            assert_grad_close(np64(getattr(grads, k)), ref[k], f"bx{bx} d_{k}")
+
+
+# uneven scans: ragged dims, non-unit spacing and origin, an empty Gaussian set
+SCANS = [
+    (211, (20, 18, 12), 80, (0.5, 0.5, 0.5), (1.0, 1.0, 1.0)),
+    (212, (33, 17, 9), 250, (0.25, 0.5, 0.75), (0.7, 1.2, 1.5)),
+    (213, (16, 16, 8), 0, (0.5, 0.5, 0.5), (1.0, 1.0, 1.0)),
+    (214, (41, 30, 22), 500, (0.5, 0.5, 0.5), (1.0, 1.0, 1.0)),
+]
+
+
+def _scan(seed, dims, n, origin, spacing):
+    gs = gs_mod()
+    rng = np.random.default_rng(seed)
+    if n == 0:
+        p = {"mu": np.zeros((0, 3), np.float32), "log_scale": np.zeros((0, 3), np.float32),
+             "quat": np.zeros((0, 4), np.float32), "amp": np.zeros(0, np.float32), "relax": np.zeros(0, np.float32)}
+    else:
+        p = synth.gaussians_uniform(seed, n, dims, ls_std=0.4, max_ratio=5.0)
+        p["mu"] = (np.asarray(origin, np.float32) + p["mu"] * np.asarray(spacing, np.float32)
+                   - 0.5 * np.asarray(spacing, np.float32)).astype(np.float32)
+        p["relax"] = rng.uniform(0.4, 1.0, n).astype(np.float32)
+    grid = gs.Grid(*dims, origin=origin, spacing=spacing)
+    return p, grid
+
+
+@pytest.mark.parametrize("bx", (8, 16))
+def test_batch_render_and_gradient_equal_single(bx):
+    gs = gs_mod()
+    scans = [_scan(*s) for s in SCANS]
+    opts = gs.Opts(bx=bx)
+    singles = []
+    for k, (p, grid) in enumerate(scans):
+        g = gs.Gaussians.from_numpy(p)
+        I, W, bins = gs.render(g, grid, opts)
+        gs.gs_status(bins)
+        gI = torch.from_numpy(synth.uniform_volume(300 + k, (grid.nx, grid.ny, grid.nz)) - 0.5).cuda()
+        grads = gs.backward(g, grid, opts, bins, I, W, gI)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gs.gs_count_pairs(g, grid, opts, bins, cnt)
+        singles.append((I, W, gI, grads, int(cnt.item())))
+    batch = gs.Batch([p["amp"].shape[0] for p, _ in scans], [grid for _, grid in scans])
+    say("batch render", bx, [g.shape for g in batch.grids], batch.ns)
+    gall = gs.concat([gs.Gaussians.from_numpy(p) for p, _ in scans])
+    I, W, bins = gs.render_batch(gall, batch, opts)
+    gs.gs_status(bins)
+    for k, (Ik, Wk) in enumerate(zip(batch.split(I), batch.split(W))):
+        assert torch.equal(Ik, singles[k][0]), f"scan {k} I"
+        assert torch.equal(Wk, singles[k][1]), f"scan {k} W"
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gs.gs_count_pairs_batch(gall, batch, opts, bins, cnt)
+    assert int(cnt.item()) == sum(s[4] for s in singles)
+    gI = torch.cat([s[2].reshape(-1) for s in singles])
+    grads = gs.Grads.empty(gall.n, relax=True)
+    gs.gs_render_bwd_batch(gall, batch, opts, bins, I, W, gI, grads)
+    o = batch.g_offsets
+    for k in range(len(scans)):
+        for name in oracle.GROUPS:
+            got, want = getattr(grads, name)[o[k]:o[k + 1]], getattr(singles[k][3], name)
+            assert torch.equal(got, want), f"scan {k} d_{name}"
+    # and one scan of the batch against the oracle
+    p, grid = scans[1]
+    og = oracle.Grid(grid.nx, grid.ny, grid.nz, grid.origin, grid.spacing)
+    Io, Wo, _ = oracle.render(p, og)
+    clean = oracle.ambiguous_voxels(p, og, cases.BAND) == 0
+    assert_fwd_close(np64(batch.split(I)[1])[clean], Io[clean], "batch scan 1 I")
+
+
+FIT_SCANS = [(221, (32, 24, 16), 500), (222, (24, 40, 8), 300), (223, (40, 16, 12), 400)]
+
+
+def _fit_scan(seed, dims, n, zdown):
+    hr = synth.phantom(seed, dims)
+    lr_obs = synth.zmean_observation(hr, zdown)
+    p = synth.lattice_init(seed + 1, lr_obs, n, f=zdown)
+    return p, lr_obs
+
+
+@pytest.mark.parametrize("zdown", (4, 2))
+def test_batch_fit_steps_equal_single(zdown):
+    """Three fit steps of three uneven scans in one batch, bitwise equal to three separate fits; the
+    scans start at different Adam steps (each keeps its own counter and bias correction)."""
+    gs = gs_mod()
+    data = [_fit_scan(s, d, n, zdown) for s, d, n in FIT_SCANS]
+    grids = [gs.Grid(*d) for _, d, _ in FIT_SCANS]
+    start = [2, 0, 5]
+    nsteps = 3
+    singles = []
+    for k, ((p, obs), grid) in enumerate(zip(data, grids)):
+        g = gs.Gaussians.from_numpy(p)
+        fo = gs.FitOpts(grid, zdown=zdown)
+        bins = gs.plan_bins(g, grid, fo.opts, headroom=2.0)
+        st = gs.FitState(g)
+        st.step.fill_(start[k])
+        buf = gs.FitBuffers(g.n, grid, relax=True)
+        obs_t = torch.from_numpy(obs).cuda()
+        losses = []
+        for _ in range(nsteps):
+            gs.gs_fit_step(st, obs_t, fo, bins, buf)
+            losses.append(buf.loss.clone())
+        gs.gs_status(bins)
+        singles.append((g, st, torch.cat(losses)))
+    batch = gs.Batch([p["amp"].shape[0] for p, _ in data], grids)
+    say("batch fit", zdown, [g.shape for g in grids], batch.ns)
+    gall = gs.concat([gs.Gaussians.from_numpy(p) for p, _ in data])
+    fo = gs.FitOpts(None, zdown=zdown)
+    bins = gs.plan_bins_batch(gall, batch, fo.opts, headroom=2.0)
+    st = gs.FitState(gall, nscans=len(batch))
+    st.step.copy_(torch.tensor(start, dtype=torch.int32))
+    buf = gs.FitBuffers(gall.n, batch, relax=True)
+    obs_all = torch.from_numpy(np.concatenate([o.reshape(-1) for _, o in data])).cuda()
+    losses = []
+    for _ in range(nsteps):
+        gs.gs_fit_step_batch(st, obs_all, batch, fo, bins, buf)
+        losses.append(buf.loss.clone())
+    gs.gs_status(bins)
+    losses = torch.stack(losses)  # [steps, scans]
+    o = batch.g_offsets
+    for k, (g1, st1, l1) in enumerate(singles):
+        for name in oracle.GROUPS:
+            assert torch.equal(getattr(gall, name)[o[k]:o[k + 1]], getattr(g1, name)), f"scan {k} {name}"
+        assert torch.equal(losses[:, k], l1), f"scan {k} loss"
+        assert int(st.step[k].item()) == start[k] + nsteps
+        n = g1.n
+        # moments: group layout over the concatenated set vs over the scan's own set
+        for gi, (c, w) in enumerate(((0, 3), (3, 3), (6, 4), (10, 1), (11, 1))):
+            a = st.m[c * gall.n + w * o[k]: c * gall.n + w * o[k + 1]]
+            b = st1.m[c * n: c * n + w * n]
+            assert torch.equal(a, b), f"scan {k} m group {gi}"
