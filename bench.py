@@ -48,25 +48,30 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-scan comparison")
     ap.add_argument("--batch-steps", type=int, default=20, help="timed steps of the batched comparison")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of Poisson arrivals for the request-loop section (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain device-to-device copy of this many MiB (a known-size "
                          "kernel against which profiler byte counters are calibrated)")
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
-    current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
-    src = os.path.join(ROOT, "paper_2603_09621_amd", "csrc", "render.hip")
-    try:
-        rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if rec.get("source_sha256") != sha:
-            return None
-        return float(rec["hbm_bytes_per_launch"])
-    except (OSError, ValueError, KeyError):
-        return None
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from a committed counter summary
+    (profiles/*_traffic.json), if it was taken on the current kernel source; else None."""
+    import glob
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))):
+        try:
+            rec = json.load(open(path))
+            if rec.get("kernel") != kernel or rec.get("workload_key") != workload:
+                continue
+            sha = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
+            if rec.get("source_sha256") == sha:
+                return float(rec["hbm_bytes_per_launch"])
+        except (OSError, ValueError, KeyError):
+            continue
+    return None
 
 
 def batch_section(args, dev):
@@ -250,7 +255,7 @@ def main():
     achieved = U_step * c / (t_k / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": traffic_from_profiles(dom)}
+                "traffic": traffic_from_profiles(dom, f"fit {dims[0]}x{dims[1]}x{dims[2]} n={args.n} bx={args.bx}")}
 
     if args.copy_probe_mib > 0:
         nbytes = args.copy_probe_mib << 20
@@ -289,6 +294,13 @@ def main():
         del bins, st, buf, g, snap, final
         torch.cuda.empty_cache()
         batched = batch_section(args, dev)
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_2603_09621_amd import serve
+
+        torch.cuda.empty_cache()
+        serving = serve.run_workload(duration=args.serve_seconds,
+                                     log=lambda m: print("[bench]", m, file=sys.stderr, flush=True))
 
     out = {
         "metric": "Gaussian-voxel evals/s (fwd+bwd)",
@@ -315,6 +327,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

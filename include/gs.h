@@ -67,6 +67,10 @@ typedef struct {
   float spacing[3]; /* > 0 */
 } gs_grid_t;
 
+/* opts.flags bits */
+#define GS_FLAG_FORWARD_ONLY 1u /* workspace without the backward's partial sums (48 B per key less);
+                                   the backward and the fit reject such options */
+
 /* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4; this build also runs
  * 4x8x4 and 16x8x4, a choice that changes speed, never results); gs_brick_supported() tells.  cutoff: Mahalanobis truncation radius (3 = the 3-sigma
  * ellipsoid).  eps: denominator regulariser (>= 0). */
@@ -74,7 +78,7 @@ typedef struct {
   int32_t bx, by, bz;
   float cutoff;
   float eps;
-  uint32_t flags; /* reserved, must be 0 */
+  uint32_t flags; /* GS_FLAG_* bits; the same flags must be used for sizing and for every call */
 } gs_opts_t;
 
 /* Binning workspace: caller-owned device memory of gs_workspace_size() bytes for `key_capacity`
@@ -135,14 +139,19 @@ typedef struct {
 
 /* A batch of independent scans handled by the same launches (each phase of the method is one launch
  * over the bricks of all scans; §3.3's brick partition applies to each scan's own grid).  Scan k
- * owns the n[k] Gaussians that follow those of scans 0..k-1 in the concatenated Gaussian set, and
- * its volumes (I, W, dL_dI: grid[k].nz * ny * nx voxels) and LR observation follow those of scans
- * 0..k-1 in the concatenated arrays.  Results of every scan are bitwise identical to those of the
- * single-scan calls on that scan alone.  The single-scan calls are the ns = 1 case. */
+ * owns the n[k] Gaussians that follow those of scans 0..k-1 in the concatenated Gaussian numbering,
+ * and its volumes (I, W, dL_dI: grid[k].nz * ny * nx voxels) and LR observation follow those of
+ * scans 0..k-1 in the concatenated arrays.  Results of every scan are bitwise identical to those of
+ * the single-scan calls on that scan alone.  The single-scan calls are the ns = 1 case.
+ * The Gaussians come either from one concatenated set (the `g` argument of the calls, sets = NULL)
+ * or, for gs_bin_query_batch, gs_bin_batch, gs_render_fwd_batch and gs_count_pairs_batch only, from
+ * one set per scan (sets[k], with sets[k].n == n[k]; then `g` must be NULL): resident sets are then
+ * rendered together without being copied into one array. */
 typedef struct {
-  int32_t ns;             /* 1 .. GS_MAX_SCANS */
-  const int64_t *n;       /* host [ns]: Gaussians per scan (>= 0) */
-  const gs_grid_t *grid;  /* host [ns]: grid per scan */
+  int32_t ns;                  /* 1 .. GS_MAX_SCANS */
+  const int64_t *n;            /* host [ns]: Gaussians per scan (>= 0) */
+  const gs_grid_t *grid;       /* host [ns]: grid per scan */
+  const gs_gaussians_t *sets;  /* host [ns] or NULL (see above) */
 } gs_batch_t;
 
 /* Device status block (read by gs_status). */

@@ -23,6 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
 SOURCES = {
     "bin.hip": ["-ffp-contract=off"],
     "render.hip": ["-ffp-contract=off"],
+    "reduce.hip": ["-ffp-contract=off"],
     "fit.hip": ["-ffp-contract=off"],
     "api.cpp": ["-x", "hip"],
 }

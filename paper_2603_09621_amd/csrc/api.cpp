@@ -102,7 +102,7 @@ bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap) {
+WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
   WsLayout L;
   L.n = n;
   L.cap = cap;
@@ -132,7 +132,7 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap) {
   L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
   const int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
   L.scan_tmp = take(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
-  L.partials = take(sizeof(float) * 12 * (size_t)cap);
+  L.partials = take(partials ? sizeof(float) * 12 * (size_t)cap : 0);
   L.total = o;
   // pass p writes keys to keys_alt when p is even, key_brick when odd
   L.sorted_keys = ((L.sort_passes - 1) & 1) ? L.key_brick : L.keys_alt;
@@ -161,7 +161,7 @@ static int check_opts(const gs_opts_t *opts) {
     return fail(GS_ERR_UNSUPPORTED, "brick %dx%dx%d not supported by this build", opts->bx, opts->by, opts->bz);
   if (!(opts->cutoff > 0.f) || !std::isfinite(opts->cutoff)) return fail(GS_ERR_INVALID_ARG, "cutoff must be > 0");
   if (!(opts->eps >= 0.f) || !std::isfinite(opts->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be >= 0");
-  if (opts->flags != 0) return fail(GS_ERR_INVALID_ARG, "flags must be 0");
+  if ((opts->flags & ~(uint32_t)GS_FLAG_FORWARD_ONLY) != 0) return fail(GS_ERR_INVALID_ARG, "unknown flags");
   return GS_OK;
 }
 
@@ -218,18 +218,53 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
   return GS_OK;
 }
 
-static int check_common(const gs_gaussians_t *g, const gs_batch_t *bt, const gs_opts_t *opts, const gs_bins_t *bins,
-                        int32_t zdown, ScanTable *T, WsLayout *L) {
+// Gaussian parameters of every scan: from the per-scan sets of the batch if it has them (then g must
+// be NULL), else from the concatenated set g.
+static int bind_gaussians(const gs_gaussians_t *g, const gs_batch_t *bt, ScanTable *T) {
   int rc;
-  if ((rc = check_gaussians(g)) || (rc = make_table(bt, opts, zdown, T))) return rc;
+  if (bt->sets) {
+    if (g) return fail(GS_ERR_INVALID_ARG, "give either per-scan sets in the batch or one concatenated set, not both");
+    for (int k = 0; k < T->ns; ++k) {
+      const gs_gaussians_t &sk = bt->sets[k];
+      if ((rc = check_gaussians(&sk))) return rc;
+      if (sk.n != bt->n[k])
+        return fail(GS_ERR_INVALID_ARG, "scan %d: set holds %lld Gaussians, batch n says %lld", k, (long long)sk.n,
+                    (long long)bt->n[k]);
+      ScanDesc &sd = T->s[k];
+      sd.mu = sk.mu;
+      sd.ls = sk.log_scale;
+      sd.quat = sk.quat;
+      sd.amp = sk.amp;
+      sd.relax = sk.relax;
+    }
+    return GS_OK;
+  }
+  if ((rc = check_gaussians(g))) return rc;
   if (g->n != T->n_total)
     return fail(GS_ERR_INVALID_ARG, "the Gaussian set holds %lld Gaussians, the batch's scans %lld", (long long)g->n,
                 (long long)T->n_total);
+  for (int k = 0; k < T->ns; ++k) {
+    ScanDesc &sd = T->s[k];
+    const int64_t o = sd.g0;
+    const bool any = g->n > 0;
+    sd.mu = any ? g->mu + 3 * o : nullptr;
+    sd.ls = any ? g->log_scale + 3 * o : nullptr;
+    sd.quat = any ? g->quat + 4 * o : nullptr;
+    sd.amp = any ? g->amp + o : nullptr;
+    sd.relax = any && g->relax ? g->relax + o : nullptr;
+  }
+  return GS_OK;
+}
+
+static int check_common(const gs_gaussians_t *g, const gs_batch_t *bt, const gs_opts_t *opts, const gs_bins_t *bins,
+                        int32_t zdown, ScanTable *T, WsLayout *L) {
+  int rc;
+  if ((rc = make_table(bt, opts, zdown, T)) || (rc = bind_gaussians(g, bt, T))) return rc;
   if (!bins || !bins->ws) return fail(GS_ERR_INVALID_ARG, "bins or bins->ws is NULL");
   if (bins->key_capacity < 0 || bins->key_capacity > (int64_t)0x7FFFFF00)
     return fail(GS_ERR_INVALID_ARG, "key_capacity must be in [0, 2^31 - 256]");
-  *L = make_layout(T->n_total, T->nbricks_total, bins->key_capacity);
-  if ((int64_t)kRadix * L->sort_blocks > (int64_t)kScanTile * 8192 || g->n + 1 > (int64_t)kScanTile * 8192)
+  *L = make_layout(T->n_total, T->nbricks_total, bins->key_capacity, !(opts->flags & GS_FLAG_FORWARD_ONLY));
+  if ((int64_t)kRadix * L->sort_blocks > (int64_t)kScanTile * 8192 || T->n_total + 1 > (int64_t)kScanTile * 8192)
     return fail(GS_ERR_INVALID_ARG, "key capacity or n beyond the scan limit");
   if (bins->ws_bytes < L->total)
     return fail(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes given, %zu needed", bins->ws_bytes, L->total);
@@ -247,6 +282,7 @@ struct Single {
     b.ns = 1;
     b.n = &n;
     b.grid = g ? &grid : nullptr;
+    b.sets = nullptr;
   }
 };
 
@@ -270,7 +306,7 @@ int gs_workspace_size_batch(const gs_batch_t *batch, const gs_opts_t *opts, int6
   ScanTable T;
   int rc = make_table(batch, opts, 0, &T);
   if (rc) return rc;
-  *bytes = make_layout(T.n_total, T.nbricks_total, key_capacity).total;
+  *bytes = make_layout(T.n_total, T.nbricks_total, key_capacity, !(opts->flags & GS_FLAG_FORWARD_ONLY)).total;
   return GS_OK;
 }
 
@@ -286,7 +322,7 @@ static int bin_front(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_
                      const WsLayout &L, hipStream_t s) {
   hipError_t e;
   if ((e = launch_reset(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "reset");
-  if ((e = launch_prep_count(T, *g, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
+  if ((e = launch_prep_count(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
   if ((e = launch_scan_counts(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "scan_counts");
   return GS_OK;
 }
@@ -380,6 +416,8 @@ int gs_render_bwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const 
   WsLayout L;
   int rc = check_common(g, batch, opts, bins, 0, &T, &L);
   if (rc) return rc;
+  if (batch->sets) return fail(GS_ERR_INVALID_ARG, "the backward takes one concatenated Gaussian set");
+  if (opts->flags & GS_FLAG_FORWARD_ONLY) return fail(GS_ERR_INVALID_ARG, "forward-only workspace: no backward");
   if (!I || !W || !dL_dI || !grads) return fail(GS_ERR_INVALID_ARG, "I, W, dL_dI and grads are required");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_bwd(T, opts->bx, opts->cutoff, opts->eps, bins->ws, L, I, W, dL_dI, s);
@@ -464,6 +502,8 @@ int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_ba
   if (rc) return rc;
   if (fo->loss != 0) return fail(GS_ERR_UNSUPPORTED, "only loss 0 (L1 on the z-mean) is supported");
   if (fo->zdown <= 0) return fail(GS_ERR_INVALID_ARG, "zdown must be positive");
+  if (batch && batch->sets) return fail(GS_ERR_INVALID_ARG, "the fit takes one concatenated Gaussian set");
+  if (fo->opts.flags & GS_FLAG_FORWARD_ONLY) return fail(GS_ERR_INVALID_ARG, "forward-only workspace: no fit");
   gs_gaussians_t g{st->n, st->mu, st->log_scale, st->quat, st->amp, st->relax};
   ScanTable T;
   WsLayout L;

@@ -128,12 +128,11 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
   return count;
 }
 
-// Fused prep + count: records of Gaussian i (of the concatenated set) and its key count cnt[i].
-// Thread n_total writes cnt[n_total] = 0 (the scan's total slot).
-__global__ void k_prep_count(const ScanTable T, const float *__restrict__ mu, const float *__restrict__ ls,
-                             const float *__restrict__ quat, const float *__restrict__ amp,
-                             const float *__restrict__ relax, float cutoff, EvalRec *__restrict__ er,
-                             CullRec *__restrict__ cr, uint32_t *__restrict__ cnt, DevStatus *st) {
+// Fused prep + count: records of Gaussian i (of the concatenated numbering; its parameters are
+// entry i - g0 of its scan's arrays) and its key count cnt[i].  Thread n_total writes cnt[n_total] = 0
+// (the scan's total slot).
+__global__ void k_prep_count(const ScanTable T, float cutoff, EvalRec *__restrict__ er, CullRec *__restrict__ cr,
+                             uint32_t *__restrict__ cnt, DevStatus *st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = T.n_total;
   if (i > n) return;
@@ -141,22 +140,20 @@ __global__ void k_prep_count(const ScanTable T, const float *__restrict__ mu, co
     cnt[n] = 0u;
     return;
   }
+  const ScanDesc &sd = T.s[T.of_gauss(i)];
   EvalRec e;
   CullRec c;
-  make_records(i, mu, ls, quat, amp, relax, cutoff, e, c, st);
+  make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, c, st);
   er[i] = e;
   cr[i] = c;
-  const BrickGrid &bg = T.s[T.of_gauss(i)].bg;
-  cnt[i] = enumerate_bricks(bg, e, c, cutoff, [](uint32_t, uint32_t) {});
+  cnt[i] = enumerate_bricks(sd.bg, e, c, cutoff, [](uint32_t, uint32_t) {});
 }
 
-hipError_t launch_prep_count(const ScanTable &T, const gs_gaussians_t &g, float cutoff, void *ws, const WsLayout &L,
-                             hipStream_t s) {
+hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
   int blocks = (int)((T.n_total + 1 + 255) / 256);
   prof_begin(s);
-  k_prep_count<<<blocks, 256, 0, s>>>(T, g.mu, g.log_scale, g.quat, g.amp, g.relax, cutoff,
-                                      (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
+  k_prep_count<<<blocks, 256, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
                                       (uint32_t *)(b + L.off), (DevStatus *)(b + L.status));
   prof_end(s, "prep_count");
   return hipGetLastError();

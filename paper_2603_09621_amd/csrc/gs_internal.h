@@ -55,7 +55,10 @@ constexpr int kMaxScans = 16;
 
 struct ScanDesc {
   BrickGrid bg;
-  int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated set
+  // the scan's own Gaussian parameters (n entries each; relax may be NULL); for a concatenated set
+  // these point into it at Gaussian g0
+  const float *mu, *ls, *quat, *amp, *relax;
+  int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated numbering
   int64_t b0;     // first (global) brick of the scan
   int64_t v0;     // first voxel of the scan's volume in the concatenated volumes
   int64_t o0;     // first LR voxel of the scan's observation in the concatenated observations
@@ -79,6 +82,9 @@ struct ScanTable {
   }
 };
 
+// the table travels by value as a kernel argument (at most 4 KB of arguments per launch)
+static_assert(sizeof(ScanTable) <= 3072, "scan table too large for a kernel argument");
+
 // Radix sort tiling.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
@@ -96,7 +102,8 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 //        (keys are numbered Gaussian-major) and off[n] = the key count.
 //   key_brick, key_gid: uint32 [cap] keys in slot order; keys_alt, vals_a, vals_b: radix ping-pong.
 //   list_gid, list_slot: uint32 [cap] the keys sorted by brick: Gaussian index and key slot.
-//   brick_off: uint32 [B + 1] brick list offsets.  partials: 48 B per key slot (backward).
+//   brick_off: uint32 [B + 1] brick list offsets.  partials: 48 B per key slot (backward; absent in a
+//   forward-only workspace).
 struct WsLayout {
   int64_t n = 0, cap = 0, nbricks = 0;
   int sort_blocks = 0;  // tiles per radix pass (covers cap keys)
@@ -108,17 +115,16 @@ struct WsLayout {
 
 // Host-side helpers (api.cpp).
 bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg);
-WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap);
+WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials);
 
 // Launch bookkeeping for the optional kernel timing (api.cpp).
 void prof_begin(hipStream_t s);
 void prof_end(hipStream_t s, const char *name);
 
-// Kernel launchers (bin.hip, render.hip, fit.hip).  Return hipGetLastError() of the launches.
-// `gauss` holds the concatenated Gaussians of all scans of T.
+// Kernel launchers (bin.hip, render.hip, reduce.hip, fit.hip).  Return hipGetLastError() of the
+// launches.  `g` / `st` hold the concatenated Gaussians of all scans of T.
 hipError_t launch_reset(void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_prep_count(const ScanTable &T, const gs_gaussians_t &gauss, float cutoff, void *ws,
-                             const WsLayout &L, hipStream_t s);
+hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s);

@@ -13,12 +13,12 @@
 // so the result is bitwise deterministic.
 //
 // Backward: two waves per brick, one Gaussian per lane.  The brick's per-voxel factors
-// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by their
-// number of rows in the brick so that the lanes of a wave run the same number of iterations; each
-// lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
-// maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and accumulates per
-// row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w, folded with the row's
-// (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.  The sums of each
+// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; a first pass marks, per key, the
+// 4-voxel row segments its ellipsoid may touch, the keys are ordered by that count so that the lanes
+// of a wave run the same number of iterations, and each lane walks exactly its marked segments,
+// evaluates their 4 voxels unrolled and accumulates the moments sum(k), sum(k dx), sum(k dx^2) and
+// sum(c w) of k = dL/dw * w, folded with the row's (dy, dz) into the 11 brick-local sums of
+// (1, delta, delta delta^T) and dA.  The sums of each
 // (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel reduces each
 // Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
@@ -243,10 +243,19 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p0 = (sum c w, sum k, sum k dx, sum k dy), p1 = (sum k dz, sum k dx dx, sum k dy dy, sum k dz dz),
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
+//
+// Work unit: one 4-voxel segment of one brick row (a brick has 32 rows of BX voxels, BX / 4
+// segments each).  A first pass over a window of the brick's keys marks, per key, the units its
+// ellipsoid may touch: for each row of the key's voxel box, the exponent's maximum over each
+// segment (the row's quadratic at its vertex clamped to the segment) is compared with the cutoff
+// with a rounding allowance, so a unit holding a pair with d^2 <= 9 is never left out.  Keys are then
+// ordered by their unit count (an LDS counting sort; a key's result does not depend on where it
+// runs), and every lane walks exactly its key's marked units, so the lanes of a wave run similar
+// trip counts and no lane idles on untouched rows.  The per-pair predicate inside a unit is the same
+// as in the forward, so both take the same inclusion decisions.
 
 constexpr int kBwdThreads = 128;
-constexpr int kBwdWindow = 2048;  // keys ordered by work per pass over the brick list
-constexpr int kBwdBuckets = 34;   // rows per key in a brick: 0 .. 32 (bucket 0 = 32 rows)
+constexpr int kBwdWindow = 1024;  // keys ordered by work per pass over the brick list
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
 __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
@@ -281,12 +290,16 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
                                                      const float *__restrict__ gI, const float *__restrict__ obs,
                                                      float *__restrict__ loss_part, int64_t cap,
                                                      float4 *__restrict__ part) {
-  constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
+  constexpr int RP = BX + 1;     // LDS row stride in voxels (pad: rows of a wave hit different banks)
+  constexpr int NS = BX / 4;     // segments per brick row
+  constexpr int NU = 32 * NS;    // units per brick
+  constexpr int NB = NU + 2;     // buckets: NU - (unit count), and one for invalid keys
   if (st->overflow) return;
   __shared__ float2 sCI[32 * RP];
+  __shared__ uint32_t smask[NS][kBwdWindow];  // per key and segment column: bit = brick row lz * 8 + ly
   __shared__ uint16_t sorder[kBwdWindow];
   __shared__ uint8_t sbucket[kBwdWindow];
-  __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
+  __shared__ uint32_t bcount[NB], bcursor[NB];
   const int64_t b = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_brick(b)];
   const BrickGrid &bg = sd.bg;
@@ -348,26 +361,51 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   const int xe = min(x0 + BX - 1, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
   for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
     const int L = (int)min((uint32_t)kBwdWindow, end - w0);
-    // order the window's keys by their number of rows in the brick, most first, so that the lanes of
-    // a wave run the same number of row iterations (each key's result is independent of where it
-    // runs, so the order does not change any result)
-    if (t < kBwdBuckets) bcount[t] = 0u;
+    for (int k = t; k < NB; k += kBwdThreads) bcount[k] = 0u;
     __syncthreads();
+    // pass 1: the units each key may touch
     for (int j = t; j < L; j += kBwdThreads) {
       const uint32_t gid = list_gid[w0 + j];
-      int bk = kBwdBuckets - 1;
+      uint32_t m[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) m[s] = 0u;
+      int bk = NB - 1;
       if (gid < T.n_total) {
+        const EvalRec R = er[gid];
         int xl, xh, yl, yh, zl, zh;
-        key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
-        if (xl <= xh && yl <= yh && zl <= zh) bk = 32 - (yh - yl + 1) * (zh - zl + 1);
+        key_box(bg, R, cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+        if (xl <= xh && yl <= yh && zl <= zh) {
+          const float mx = R.r0.x, a = R.r1.x, thr = R.r1.w;
+          const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
+          for (int iz = zl; iz <= zh; ++iz)
+            for (int iy = yl; iy <= yh; ++iy) {
+              float dy, dz, bq, cq;
+              row_coeffs(R, centre(bg.oy, bg.hy, iy), centre(bg.oz, bg.hz, iz), dy, dz, bq, cq);
+              const float xs = -bq * inv2a;
+              const float lim = thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq));
+              const uint32_t bit = 1u << ((iz - z0) * 8 + (iy - y0));
+#pragma unroll
+              for (int s = 0; s < NS; ++s) {
+                if (x0 + 4 * s > xh || x0 + 4 * s + 3 < xl) continue;
+                const float xc = fminf(fmaxf(xs, px[4 * s] - mx), px[4 * s + 3] - mx);
+                if (row_q(a, bq, cq, xc) >= lim) m[s] |= bit;
+              }
+            }
+          int cnt = 0;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) cnt += __popc(m[s]);
+          bk = NU - cnt;
+        }
       }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) smask[s][j] = m[s];
       sbucket[j] = (uint8_t)bk;
       atomicAdd(&bcount[bk], 1u);
     }
     __syncthreads();
     if (t == 0) {
       uint32_t run = 0;
-      for (int k = 0; k < kBwdBuckets; ++k) {
+      for (int k = 0; k < NB; ++k) {
         bcursor[k] = run;
         run += bcount[k];
       }
@@ -375,68 +413,84 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     __syncthreads();
     for (int j = t; j < L; j += kBwdThreads) sorder[atomicAdd(&bcursor[sbucket[j]], 1u)] = (uint16_t)j;
     __syncthreads();
+    // pass 2: each lane walks its key's units
     for (int c0 = w * 64; c0 < L; c0 += kBwdThreads) {
       const int p = c0 + l;
       if (p >= L) continue;
-      const uint32_t k = w0 + sorder[p];
+      const int j = sorder[p];
+      const uint32_t k = w0 + j;
       const uint32_t gid = list_gid[k];
       const uint32_t slot = list_slot[k];
       if (gid >= T.n_total || (int64_t)slot >= cap) continue;
       const EvalRec R = er[gid];
-      const CullRec C = cr[gid];
-      const float mx = R.r0.x, A = R.r0.w;
-      const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
-      int xl, xh, yl, yh, zl, zh;
-      key_box(bg, R, C, cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+      const float mx = R.r0.x, A = R.r0.w, a = R.r1.x, thr = R.r1.w;
+      uint32_t m[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) m[s] = smask[s][j];
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-      const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
-      const int ny_k = yh - yl + 1;
-      const int nrows = (xl <= xh && yl <= yh && zl <= zh) ? ny_k * (zh - zl + 1) : 0;
-      int iy = yl, iz = zl;
-      for (int r = 0; r < nrows; ++r) {
-        const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
-        float dy, dz, bq, cq;
-        row_coeffs(R, py, pz, dy, dz, bq, cq);
-        // the row's maximum of q is at dx* = -b / (2a); rows whose maximum is clearly below the
-        // cutoff hold no pair
-        const float xs = -bq * inv2a;
-        const float qmax = fmaf(0.5f * bq, xs, cq);
-        if (qmax >= thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) {
-          const int rb = ((iz - z0) * 8 + (iy - y0)) * RP;
-          float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+      while (true) {
+        // next unit: the lowest set bit of the first non-empty segment column
+        int s = -1;
 #pragma unroll
-          for (int kk = 0; kk < BX; ++kk) {
-            const float dx = px[kk] - mx;
-            const float q = row_q(a, bq, cq, dx);
-            float wt = fast_exp2(q);
-            wt = q >= thr ? wt : 0.f;
-            const float2 ci = sCI[rb + kk];
-            const float tt = ci.x * wt;
-            const float kap = (A - ci.y) * tt;
+        for (int q = NS - 1; q >= 0; --q)
+          if (m[q]) s = q;
+        if (s < 0) break;
+        uint32_t cur = 0u;
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+          if (q == s) cur = m[q];
+        const int bit = __builtin_ctz(cur);
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+          if (q == s) m[q] = cur & (cur - 1u);
+        float xs4[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          xs4[kk] = px[kk];
+#pragma unroll
+          for (int q = 1; q < NS; ++q)
+            if (q == s) xs4[kk] = px[4 * q + kk];
+        }
+        const int iy = y0 + (bit & 7), iz = z0 + (bit >> 3);
+        float dy, dz, bq, cq;
+        row_coeffs(R, centre(bg.oy, bg.hy, iy), centre(bg.oz, bg.hz, iz), dy, dz, bq, cq);
+        const float2 *ci = sCI + bit * RP + 4 * s;
+        float tA, m0, m1, m2;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const float dx = xs4[kk] - mx;
+          const float q = row_q(a, bq, cq, dx);
+          float wt = fast_exp2(q);
+          wt = q >= thr ? wt : 0.f;
+          const float2 c2 = ci[kk];
+          const float tt = c2.x * wt;
+          const float kap = (A - c2.y) * tt;
+          const float u = kap * dx;
+          if (kk == 0) {
+            tA = tt;
+            m0 = kap;
+            m1 = u;
+            m2 = u * dx;
+          } else {
             tA += tt;
             m0 += kap;
-            const float u = kap * dx;
             m1 += u;
             m2 = fmaf(u, dx, m2);
           }
-          sA += tA;
-          sk += m0;
-          skx += m1;
-          sky = fmaf(m0, dy, sky);
-          skz = fmaf(m0, dz, skz);
-          mxx += m2;
-          mxy = fmaf(m1, dy, mxy);
-          mxz = fmaf(m1, dz, mxz);
-          const float m0dy = m0 * dy;
-          myy = fmaf(m0dy, dy, myy);
-          myz = fmaf(m0dy, dz, myz);
-          mzz = fmaf(m0 * dz, dz, mzz);
         }
-        if (++iy > yh) {
-          iy = yl;
-          ++iz;
-        }
+        sA += tA;
+        sk += m0;
+        skx += m1;
+        sky = fmaf(m0, dy, sky);
+        skz = fmaf(m0, dz, skz);
+        mxx += m2;
+        mxy = fmaf(m1, dy, mxy);
+        mxz = fmaf(m1, dz, mxz);
+        const float m0dy = m0 * dy;
+        myy = fmaf(m0dy, dy, myy);
+        myz = fmaf(m0dy, dz, myz);
+        mzz = fmaf(m0 * dz, dz, mzz);
       }
       float4 *o = part + (int64_t)slot * 3;
       o[0] = make_float4(sA, sk, skx, sky);
@@ -491,248 +545,6 @@ hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, v
   hipError_t e = bwd_dispatch<true>(T, bx, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
   prof_end(s, "render_bwd");
   return e;
-}
-
-// ------------------------------------------------------------------------------------------------
-// Per-Gaussian reduction of the brick partials (slot order) and chain rule:
-//   dmu = P sum(k delta);  dL/dP = -1/2 sum(k delta delta^T);  dA = sum(c w);  dr = sum(k) / r;
-//   P = R D R^T, D = diag(exp(-2 s)):  ds_k = -2 D_k (R^T G R)_kk,  dR = 2 G R D,
-//   dqhat from dR through the rotation of a unit quaternion, dq = (dqhat - (qhat.dqhat) qhat) / |q|.
-
-// Per-Gaussian sums of the brick partials, for the 256 consecutive Gaussians of a block: the
-// block's partials (contiguous, since keys are numbered Gaussian-major) are loaded cooperatively
-// through LDS in chunks, and each thread adds its own Gaussian's partials in slot order.
-constexpr int kRedThreads = 256;
-constexpr int kRedChunk = 768;  // partials per LDS chunk (36 KB)
-
-__device__ __forceinline__ void block_partial_sums(int64_t i0, int64_t n, const uint32_t *__restrict__ off,
-                                                   const float4 *__restrict__ part, float4 *sp, float4 &a0,
-                                                   float4 &a1, float4 &a2) {
-  const int t = threadIdx.x;
-  const int64_t i = i0 + t;
-  const int64_t iend = min(i0 + (int64_t)kRedThreads, n);
-  const uint32_t sb = off[i0], se = off[iend];
-  const uint32_t my0 = i < n ? off[i] : se, my1 = i < n ? off[i + 1] : se;
-  a0 = make_float4(0, 0, 0, 0);
-  a1 = a0;
-  a2 = a0;
-  for (uint32_t c0 = sb; c0 < se; c0 += kRedChunk) {
-    const int m = (int)min((uint32_t)kRedChunk, se - c0);
-    __syncthreads();
-    for (int k = t; k < 3 * m; k += kRedThreads) sp[k] = part[(int64_t)c0 * 3 + k];
-    __syncthreads();
-    const uint32_t lo = max(my0, c0), hi = min(my1, c0 + (uint32_t)m);
-    for (uint32_t s = lo; s < hi; ++s) {
-      const int q = (int)(s - c0) * 3;
-      const float4 p0 = sp[q], p1 = sp[q + 1], p2 = sp[q + 2];
-      a0.x += p0.x; a0.y += p0.y; a0.z += p0.z; a0.w += p0.w;
-      a1.x += p1.x; a1.y += p1.y; a1.z += p1.z; a1.w += p1.w;
-      a2.x += p2.x; a2.y += p2.y; a2.z += p2.z;
-    }
-  }
-}
-
-// Gradient of Gaussian i from its summed partials (a0, a1, a2) and its raw parameters.
-// g[0..2] = dmu, g[3..5] = dlog_scale, g[6..9] = dquat, g[10] = dA, g[11] = dr (r = 1 if relax NULL).
-__device__ __forceinline__ void gauss_grad(int64_t i, const float *__restrict__ quat, const float *__restrict__ ls,
-                                           const float *__restrict__ relax, float4 a0, float4 a1, float4 a2,
-                                           float g[12]) {
-  const float sA = a0.x, sk = a0.y;
-  const float kd[3] = {a0.z, a0.w, a1.x};
-  // G = dL/dP = -1/2 M (symmetric)
-  const float G[3][3] = {{-0.5f * a1.y, -0.5f * a2.x, -0.5f * a2.y},
-                         {-0.5f * a2.x, -0.5f * a1.z, -0.5f * a2.z},
-                         {-0.5f * a2.y, -0.5f * a2.z, -0.5f * a1.w}};
-  const float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
-  float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  if (!(qn > 0.f) || !isfinite(qn)) qn = 1.f;
-  const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
-  const float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                         {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                         {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-  const float D[3] = {expf(-2.f * ls[3 * i]), expf(-2.f * ls[3 * i + 1]), expf(-2.f * ls[3 * i + 2])};
-  float P[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) P[r][c] = R[r][0] * D[0] * R[c][0] + R[r][1] * D[1] * R[c][1] + R[r][2] * D[2] * R[c][2];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) g[r] = P[r][0] * kd[0] + P[r][1] * kd[1] + P[r][2] * kd[2];
-  float GR[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) GR[r][c] = G[r][0] * R[0][c] + G[r][1] * R[1][c] + G[r][2] * R[2][c];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float rtgr = R[0][k] * GR[0][k] + R[1][k] * GR[1][k] + R[2][k] * GR[2][k];
-    g[3 + k] = -2.f * D[k] * rtgr;
-  }
-  float dR[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) dR[r][c] = 2.f * GR[r][c] * D[c];
-  const float gw = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
-  const float gx = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] +
-                          z * dR[2][0] + w * dR[2][1] - 2.f * x * dR[2][2]);
-  const float gy = 2.f * (-2.f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
-                          w * dR[2][0] + z * dR[2][1] - 2.f * y * dR[2][2]);
-  const float gz = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
-                          y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
-  const float dot = w * gw + x * gx + y * gy + z * gz;
-  g[6] = (gw - dot * w) / qn;
-  g[7] = (gx - dot * x) / qn;
-  g[8] = (gy - dot * y) / qn;
-  g[9] = (gz - dot * z) / qn;
-  g[10] = sA;
-  g[11] = relax ? sk / relax[i] : sk;
-}
-
-__global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const float *__restrict__ ls,
-                               const float *__restrict__ relax, const uint32_t *__restrict__ off,
-                               const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
-                               float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
-                               float *__restrict__ d_relax) {
-  if (st->overflow) return;
-  __shared__ float4 sp[3 * kRedChunk];
-  const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
-  float4 a0, a1, a2;
-  block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
-  if (i >= n) return;
-  float g[12];
-  gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
-  if (d_mu) {
-    d_mu[3 * i] = g[0];
-    d_mu[3 * i + 1] = g[1];
-    d_mu[3 * i + 2] = g[2];
-  }
-  if (d_ls) {
-    d_ls[3 * i] = g[3];
-    d_ls[3 * i + 1] = g[4];
-    d_ls[3 * i + 2] = g[5];
-  }
-  if (d_quat) {
-    d_quat[4 * i] = g[6];
-    d_quat[4 * i + 1] = g[7];
-    d_quat[4 * i + 2] = g[8];
-    d_quat[4 * i + 3] = g[9];
-  }
-  if (d_amp) d_amp[i] = g[10];
-  if (d_relax) d_relax[i] = g[11];
-}
-
-// Fused gradient + Adam for the fit step: the gradient of Gaussian i (as k_reduce_chain, also
-// written to the gradient outputs) and the bias-corrected Adam update of its 12 parameters, moments
-// in the group layout mu (3n), log_scale (3n), quat (4n), amp (n), relax (n).  Each scan of the table
-// has its own step counter: Gaussian i of scan k takes step t = step[k] + 1.
-struct AdamArgs {
-  float lr[5];
-  float b1, b2, eps;
-  float lnb1, lnb2;  // ln of the betas: the bias corrections are 1 - beta^t = -expm1(t ln beta)
-};
-
-__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, float lr, float b1, float b2, float eps,
-                                         float bc1, float bc2) {
-  const float mm = fmaf(b1, m, (1.f - b1) * g);
-  const float vv = fmaf(b2, v, (1.f - b2) * g * g);
-  m = mm;
-  v = vv;
-  if (lr != 0.f) p -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
-}
-
-__global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ mu, float *__restrict__ ls, float *__restrict__ quat,
-                              float *__restrict__ amp, float *__restrict__ relax, const uint32_t *__restrict__ off,
-                              const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
-                              float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
-                              float *__restrict__ d_relax, float *__restrict__ m, float *__restrict__ v,
-                              const int32_t *__restrict__ step, AdamArgs h) {
-  if (st->overflow) return;
-  __shared__ float4 sp[3 * kRedChunk];
-  const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
-  float4 a0, a1, a2;
-  block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
-  if (i >= n) return;
-  float g[12];
-  gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
-  const float t = (float)(step[T.of_gauss(i)] + 1);
-  const float bc1 = -expm1f(t * h.lnb1), bc2 = -expm1f(t * h.lnb2);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    d_mu[3 * i + a] = g[a];
-    d_ls[3 * i + a] = g[3 + a];
-    adam_one(mu[3 * i + a], g[a], m[3 * i + a], v[3 * i + a], h.lr[0], h.b1, h.b2, h.eps, bc1, bc2);
-    adam_one(ls[3 * i + a], g[3 + a], m[3 * n + 3 * i + a], v[3 * n + 3 * i + a], h.lr[1], h.b1, h.b2, h.eps, bc1,
-             bc2);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    d_quat[4 * i + a] = g[6 + a];
-    adam_one(quat[4 * i + a], g[6 + a], m[6 * n + 4 * i + a], v[6 * n + 4 * i + a], h.lr[2], h.b1, h.b2, h.eps, bc1,
-             bc2);
-  }
-  d_amp[i] = g[10];
-  adam_one(amp[i], g[10], m[10 * n + i], v[10 * n + i], h.lr[3], h.b1, h.b2, h.eps, bc1, bc2);
-  if (relax) {
-    if (d_relax) d_relax[i] = g[11];
-    adam_one(relax[i], g[11], m[11 * n + i], v[11 * n + i], h.lr[4], h.b1, h.b2, h.eps, bc1, bc2);
-  }
-}
-
-// Fit-step epilogue, one block per scan: loss[s] = (sum of the scan's per-brick partial sums, fixed
-// order) * lscale (skipped when loss_part is NULL: the loss was computed by the loss kernel) and the
-// scan's step counter advances.
-__global__ __launch_bounds__(256) void k_fit_finalize(const ScanTable T, const float *__restrict__ loss_part,
-                                                      float *__restrict__ loss, int32_t *__restrict__ step,
-                                                      const DevStatus *st) {
-  __shared__ float sh[4];
-  const ScanDesc &sd = T.s[blockIdx.x];
-  float acc = 0.f;
-  if (loss_part)
-    for (int64_t i = threadIdx.x; i < sd.bg.nbricks; i += 256) acc += loss_part[sd.b0 + i];
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0 && !st->overflow) {
-    if (loss_part) loss[blockIdx.x] = (((sh[0] + sh[1]) + sh[2]) + sh[3]) * sd.lscale;
-    step[blockIdx.x] += 1;
-  }
-}
-
-hipError_t launch_reduce_adam(const ScanTable &T, const gs_fit_state_t &g, const void *ws, const WsLayout &L,
-                              const gs_grads_t &gr, const gs_adam_t &hp, const float *loss_part, float *loss,
-                              hipStream_t s) {
-  const char *b = (const char *)ws;
-  AdamArgs h;
-  for (int k = 0; k < 5; ++k) h.lr[k] = hp.lr[k];
-  h.b1 = hp.beta1;
-  h.b2 = hp.beta2;
-  h.eps = hp.eps;
-  h.lnb1 = (float)std::log((double)hp.beta1);
-  h.lnb2 = (float)std::log((double)hp.beta2);
-  prof_begin(s);
-  if (g.n > 0)
-    k_reduce_adam<<<(unsigned)((g.n + kRedThreads - 1) / kRedThreads), kRedThreads, 0, s>>>(
-        T, g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, (const uint32_t *)(b + L.off),
-        (const float4 *)(b + L.partials), (const DevStatus *)(b + L.status), gr.d_mu, gr.d_log_scale, gr.d_quat,
-        gr.d_amp, gr.d_relax, g.m, g.v, g.step, h);
-  k_fit_finalize<<<(unsigned)T.ns, 256, 0, s>>>(T, loss_part, loss, g.step, (const DevStatus *)(b + L.status));
-  prof_end(s, "reduce_adam");
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
-                               hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-  const char *b = (const char *)ws;
-  prof_begin(s);
-  k_reduce_chain<<<(unsigned)((g.n + kRedThreads - 1) / kRedThreads), kRedThreads, 0, s>>>(
-      g.n, g.quat, g.log_scale, g.relax, (const uint32_t *)(b + L.off), (const float4 *)(b + L.partials),
-      (const DevStatus *)(b + L.status), gr.d_mu, gr.d_log_scale, gr.d_quat, gr.d_amp,
-      g.relax ? gr.d_relax : nullptr);
-  prof_end(s, "reduce_chain");
-  return hipGetLastError();
 }
 
 }  // namespace gs

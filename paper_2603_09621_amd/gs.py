@@ -86,7 +86,8 @@ class gs_fit_buffers_t(ctypes.Structure):
 
 
 class gs_batch_t(ctypes.Structure):
-    _fields_ = [("ns", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int64)), ("grid", ctypes.POINTER(gs_grid_t))]
+    _fields_ = [("ns", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int64)), ("grid", ctypes.POINTER(gs_grid_t)),
+                ("sets", ctypes.POINTER(gs_gaussians_t))]
 
 
 class gs_status_t(ctypes.Structure):
@@ -208,6 +209,9 @@ class Grid:
         return Grid(nx, ny, nz, tuple(0.5 * s for s in sp), sp)
 
 
+FLAG_FORWARD_ONLY = 1
+
+
 @dataclass
 class Opts:
     bx: int = 8
@@ -215,22 +219,31 @@ class Opts:
     bz: int = 4
     cutoff: float = 3.0
     eps: float = 1e-8
+    forward_only: bool = False  # workspace without the backward's partial sums
 
     def c(self) -> gs_opts_t:
-        return gs_opts_t(self.bx, self.by, self.bz, self.cutoff, self.eps, 0)
+        return gs_opts_t(self.bx, self.by, self.bz, self.cutoff, self.eps,
+                         FLAG_FORWARD_ONLY if self.forward_only else 0)
 
 
 GROUPS = ("mu", "log_scale", "quat", "amp", "relax")
 
 
 class Batch:
-    """Scans handled by the same launches: Gaussian counts and grids, in concatenation order."""
+    """Scans handled by the same launches: Gaussian counts and grids, in concatenation order.  With
+    ``sets`` (one Gaussians per scan) the bin/render/count calls read every scan's own tensors and
+    take ``g=None``."""
 
-    def __init__(self, ns: Sequence[int], grids: Sequence[Grid]):
-        if len(ns) != len(grids):
-            raise ValueError("one Gaussian count per grid expected")
+    def __init__(self, ns: Sequence[int], grids: Sequence[Grid], sets: Optional[Sequence["Gaussians"]] = None):
+        if len(ns) != len(grids) or (sets is not None and len(sets) != len(ns)):
+            raise ValueError("one Gaussian count (and set) per grid expected")
         self.ns = [int(n) for n in ns]
         self.grids = list(grids)
+        self.sets = None if sets is None else list(sets)
+
+    @staticmethod
+    def of_sets(sets: Sequence["Gaussians"], grids: Sequence[Grid]) -> "Batch":
+        return Batch([s.n for s in sets], grids, sets)
 
     def __len__(self) -> int:
         return len(self.ns)
@@ -258,8 +271,11 @@ class Batch:
     def c(self) -> gs_batch_t:
         narr = (ctypes.c_int64 * len(self.ns))(*self.ns)
         garr = (gs_grid_t * len(self.grids))(*[g.c() for g in self.grids])
-        b = gs_batch_t(len(self.ns), narr, garr)
-        b._keep = (narr, garr)  # the arrays must outlive the call
+        sarr = None
+        if self.sets is not None:
+            sarr = (gs_gaussians_t * len(self.sets))(*[x.c() for x in self.sets])
+        b = gs_batch_t(len(self.ns), narr, garr, sarr)
+        b._keep = (narr, garr, sarr)  # the arrays must outlive the call
         return b
 
 
@@ -403,28 +419,32 @@ def gs_loss_l1_zmean(I: torch.Tensor, obs: torch.Tensor, grid: Grid, zdown: int,
                                  _stream(stream)))
 
 
+def _gptr(g: Optional["Gaussians"]):
+    return None if g is None else ctypes.byref(g.c())
+
+
 def gs_bin_query_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, stream=None) -> int:
     out = ctypes.c_int64(0)
-    _check(_lib.gs_bin_query_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+    _check(_lib.gs_bin_query_batch(_gptr(g), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
                                    ctypes.byref(bins.c()), _stream(stream), ctypes.byref(out)))
     return int(out.value)
 
 
 def gs_bin_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, stream=None) -> None:
-    _check(_lib.gs_bin_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+    _check(_lib.gs_bin_batch(_gptr(g), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
                              ctypes.byref(bins.c()), _stream(stream)))
 
 
 def gs_render_fwd_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, I: torch.Tensor,
                         W: Optional[torch.Tensor] = None, stream=None) -> None:
-    _check(_lib.gs_render_fwd_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+    _check(_lib.gs_render_fwd_batch(_gptr(g), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
                                     ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _stream(stream)))
 
 
 def gs_count_pairs_batch(g: Gaussians, batch: Batch, opts: Opts, bins: Bins, out: torch.Tensor, stream=None) -> None:
     if out.dtype != torch.int64:
         raise ValueError("int64 tensor expected")
-    _check(_lib.gs_count_pairs_batch(ctypes.byref(g.c()), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
+    _check(_lib.gs_count_pairs_batch(_gptr(g), ctypes.byref(batch.c()), ctypes.byref(opts.c()),
                                      ctypes.byref(bins.c()), _ptr(out), _stream(stream)))
 
 
@@ -481,9 +501,11 @@ def plan_bins(g: Gaussians, grid: Grid, opts: Opts, headroom: float = 1.25, min_
     return Bins(g.n, grid, opts, max(min_capacity, int(math.ceil(k * headroom))), device=probe.ws.device)
 
 
-def plan_bins_batch(g: Gaussians, batch: Batch, opts: Opts, headroom: float = 1.25, min_capacity: int = 1024,
-                    stream=None) -> Bins:
-    probe = Bins(0, batch, opts, 0, device=g.amp.device if g.n else "cuda")
+def plan_bins_batch(g: Optional[Gaussians], batch: Batch, opts: Opts, headroom: float = 1.25,
+                    min_capacity: int = 1024, stream=None) -> Bins:
+    """Workspace for the batch with room for its exact key count times ``headroom`` (g None: the
+    batch's own sets)."""
+    probe = Bins(0, batch, opts, 0, device="cuda")
     k = gs_bin_query_batch(g, batch, opts, probe, stream)
     return Bins(0, batch, opts, max(min_capacity, int(math.ceil(k * headroom))), device=probe.ws.device)
 
@@ -497,7 +519,7 @@ def concat(gs_: Sequence[Gaussians]) -> Gaussians:
     return Gaussians(cat("mu"), cat("log_scale"), cat("quat"), cat("amp"), relax)
 
 
-def render_batch(g: Gaussians, batch: Batch, opts: Optional[Opts] = None, bins: Optional[Bins] = None,
+def render_batch(g: Optional[Gaussians], batch: Batch, opts: Optional[Opts] = None, bins: Optional[Bins] = None,
                  want_w: bool = True, stream=None):
     """Bin + forward of every scan of the batch in one launch per phase.  Returns the concatenated
     (I, W) (flat float32) and the bins; ``batch.split`` gives the per-scan volumes."""

@@ -246,3 +246,63 @@ def workload_batch(seed: int = 4, nscans: int = 16, f: int = 4, n_range=(5e4, 8e
 
     with ThreadPoolExecutor(max(1, workers)) as ex:
         return list(ex.map(one, order))
+
+
+def serving_sets(seed: int = 5, count: int = 32, n_range=(1e5, 2e6), box_xy=(48, 80), box_z=(32, 48)):
+    """Resident Gaussian sets of the request loop.  Per set: N = exp(U(ln lo, ln hi)); LR box
+    nx = ny ~ U{box_xy}, nz ~ U{box_z} (LR voxels of unit spacing, centres at 0.5, 1.5, ...);
+    mu ~ U(box); log-scales ~ N(ln(0.75 l), 0.3) per axis with l = (V_LR / N)^(1/3) (the mean
+    spacing of the Gaussians); uniform random rotations; A ~ U(0, 1); r = 1.  Set k uses seed
+    (seed, k).  Returns a list of (params, (nx, ny, nz))."""
+    rng = _rng(seed)
+    ns = np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]), count)).round().astype(np.int64)
+    nxy = rng.integers(box_xy[0], box_xy[1] + 1, count)
+    nzs = rng.integers(box_z[0], box_z[1] + 1, count)
+    out = []
+    for k in range(count):
+        dims = (int(nxy[k]), int(nxy[k]), int(nzs[k]))
+        n = int(ns[k])
+        ell = (dims[0] * dims[1] * dims[2] / n) ** (1.0 / 3.0)
+        p = gaussians_uniform((seed, k), n, dims, ls_mean=float(np.log(0.75 * ell)), ls_std=0.3)
+        out.append((p, dims))
+    return out
+
+
+def serving_arrivals(seed: int = 5, rate: float = 50.0, duration: float = 120.0, nsets: int = 32,
+                     scales=(2.0, 2.5, 3.0, 4.0), fit_fraction: float = 0.1, fit_pool: int = 4):
+    """Poisson arrivals at ``rate`` per second over ``duration`` seconds.  Each request is a render
+    (probability 1 - fit_fraction: a uniform set and a uniform scale) or a fit (a uniform member
+    of a pool of ``fit_pool`` scans).  Returns a list of (t, "render", set_id, scale) and
+    (t, "fit", pool_index, None)."""
+    rng = _rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        if rng.random() < fit_fraction:
+            out.append((t, "fit", int(rng.integers(fit_pool)), None))
+        else:
+            out.append((t, "render", int(rng.integers(nsets)), float(scales[int(rng.integers(len(scales)))])))
+
+
+def serving_fit_pool(seed: int = 6, count: int = 4, n_max: int = 200000, f: int = 4, workers: int = 8):
+    """Scans for the fit requests of the request loop: uneven-batch grids (batch_dims of a uniform
+    index), phantom HR (seed (seed, k)), LR = z-mean of f, Gaussian count exp(U(ln 5e4, ln n_max))
+    on the coarsest lattice with enough sites.  Returns a list of (params, lr_obs, dims)."""
+    rng = _rng(seed)
+    js = rng.integers(0, 16, count)
+    ns = np.exp(rng.uniform(np.log(5e4), np.log(n_max), count))
+
+    def one(k):
+        dims = batch_dims(int(js[k]))
+        lr = zmean_observation(phantom((seed, k), dims), f)
+        n = int(min(round(ns[k]), lr.size))
+        p = lattice_init((seed, k, 1), lr, n, f, stride_xy=lattice_stride(lr.shape, n))
+        return p, lr, dims
+
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        return list(ex.map(one, range(count)))

@@ -86,3 +86,23 @@ def test_batch_sizes_and_checks():
             gs.gs_workspace_size_batch(bad, o, 10)
         assert e.value.code == gs.GS_ERR_INVALID_ARG
     assert gs.gs_fit_scratch_bytes_batch(gs.Batch([], [])) == 0
+
+
+def test_forward_only_workspace():
+    g = gs.Grid(64, 64, 32)
+    full = gs.gs_workspace_size(5000, g, gs.Opts(), 200000)
+    fwd = gs.gs_workspace_size(5000, g, gs.Opts(forward_only=True), 200000)
+    assert full - fwd >= 200000 * 48
+    bad = gs.gs_opts_t(8, 8, 4, 3.0, 1e-8, 2)  # unknown flag bit
+    out = ctypes.c_size_t(0)
+    rc = gs._lib.gs_workspace_size(10, ctypes.byref(g.c()), ctypes.byref(bad), 10, ctypes.byref(out))
+    assert rc == gs.GS_ERR_INVALID_ARG and "flags" in gs.gs_last_error()
+
+
+def test_binding_exposes_the_conveniences():
+    """The binding's public classes and helpers are all there (no GPU needed to look them up)."""
+    for name in ("Grid", "Opts", "Gaussians", "Batch", "Bins", "Grads", "Adam", "FitState", "FitBuffers",
+                 "FitOpts", "render", "render_batch", "backward", "plan_bins", "plan_bins_batch", "concat",
+                 "gs_fit_step", "gs_fit_step_batch", "gs_render_bwd_batch", "gs_count_pairs_batch"):
+        assert hasattr(gs, name), name
+    from paper_2603_09621_amd import autograd, autotune, graph, serve  # noqa: F401  (import cleanly)

@@ -106,6 +106,13 @@ def test_batch_render_and_gradient_equal_single(bx):
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     gs.gs_count_pairs_batch(gall, batch, opts, bins, cnt)
     assert int(cnt.item()) == sum(s[4] for s in singles)
+    # the same batch reading every scan's own (resident) tensors instead of the concatenated set
+    own = gs.Batch.of_sets([gs.Gaussians.from_numpy(p) for p, _ in scans], batch.grids)
+    I2, W2, bins2 = gs.render_batch(None, own, opts)
+    gs.gs_status(bins2)
+    assert torch.equal(I2, I) and torch.equal(W2, W)
+    with pytest.raises(gs.GSError):
+        gs.gs_bin_batch(gall, own, opts, bins2)  # both a concatenated set and per-scan sets
     gI = torch.cat([s[2].reshape(-1) for s in singles])
     grads = gs.Grads.empty(gall.n, relax=True)
     gs.gs_render_bwd_batch(gall, batch, opts, bins, I, W, gI, grads)
