@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-scan comparison")
+    ap.add_argument("--no-graph", action="store_true", help="skip timing the fit step replayed from a HIP graph")
     ap.add_argument("--batch-steps", type=int, default=20, help="timed steps of the batched comparison")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals for the request-loop section (0: skip)")
@@ -257,6 +258,25 @@ def main():
                 "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic_from_profiles(dom, f"fit {dims[0]}x{dims[1]}x{dims[2]} n={args.n} bx={args.bx}")}
 
+    # the same steps replayed from a HIP graph (one captured fit step per replay)
+    ms_graph = None
+    if not args.no_graph:
+        from paper_2603_09621_amd import graph
+
+        fg = graph.FitGraph(st, obs, gs.Batch([g.n], [grid]), fo, bins, buf, steps=1)
+        fg.replay()
+        torch.cuda.synchronize()
+        ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ga.record(stream)
+        for _ in range(args.steps):
+            fg.replay()
+        gb.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = ga.elapsed_time(gb) / args.steps
+        if gs.gs_status(bins, raise_on_error=False)["rc"] != 0:
+            ms_graph = None
+        del fg
+
     if args.copy_probe_mib > 0:
         nbytes = args.copy_probe_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -303,7 +323,7 @@ def main():
                                      log=lambda m: print("[bench]", m, file=sys.stderr, flush=True))
 
     out = {
-        "metric": "Gaussian-voxel evals/s (fwd+bwd)",
+        "metric": "Gaussian\u2013voxel evals/s (fwd+bwd), fit iters/s vs plain; p50/p99 render latency",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -319,6 +339,7 @@ def main():
                                f"of 4, {args.n} Gaussians on the LR lattice, L1 + Adam",
                    "global_batch": 1, "brick": [fo.opts.bx, fo.opts.by, fo.opts.bz]},
         "fit_iters_per_s": 1.0 / t_step,
+        "ms_per_step_hip_graph": ms_graph,
         "useful_pairs_per_step": U_step,
         "wall_s_timed": wall,
         "loss_end": loss_end,

@@ -131,7 +131,9 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
   L.brick_off = take(sizeof(uint32_t) * (size_t)(nbricks + 1));
   L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
   const int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
-  L.scan_tmp = take(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
+  // scan scratch: tile totals of the count scan, later the radix digit totals
+  L.scan_tmp = take(std::max(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1),
+                             sizeof(uint32_t) * (size_t)kRadix));
   L.partials = take(partials ? sizeof(float) * 12 * (size_t)cap : 0);
   L.total = o;
   // pass p writes keys to keys_alt when p is even, key_brick when odd

@@ -287,30 +287,61 @@ hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s) {
 
 // ------------------------------------------------------------------------------------------------
 // Emit: the j-th key of Gaussian i is written at slot off[i] + j, with its scan's global brick id.
+// A block's Gaussians own a contiguous slot range; when it fits, the block assembles its keys in
+// LDS and writes the range out with consecutive threads on consecutive slots.
 
-__global__ void k_emit(const ScanTable T, float cutoff, const EvalRec *__restrict__ er,
-                       const CullRec *__restrict__ cr, const uint32_t *__restrict__ off, int64_t cap,
-                       const DevStatus *st, uint32_t *__restrict__ key_brick, uint32_t *__restrict__ key_gid) {
+constexpr int kEmitThreads = 256;
+constexpr int kEmitStage = 4096;  // keys staged per block (32 KB of LDS)
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit(const ScanTable T, float cutoff,
+                                                       const EvalRec *__restrict__ er,
+                                                       const CullRec *__restrict__ cr,
+                                                       const uint32_t *__restrict__ off, int64_t cap,
+                                                       const DevStatus *st, uint32_t *__restrict__ key_brick,
+                                                       uint32_t *__restrict__ key_gid) {
+  __shared__ uint32_t sbrick[kEmitStage], sgid[kEmitStage];
   if (st->overflow) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= T.n_total) return;
-  const ScanDesc &sd = T.s[T.of_gauss(i)];
-  const uint32_t base = off[i], b0 = (uint32_t)sd.b0;
-  enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
-    const int64_t slot = (int64_t)base + j;
-    if (slot < cap) {
-      key_brick[slot] = b0 + brick;
-      key_gid[slot] = (uint32_t)i;
+  const int64_t n = T.n_total;
+  const int64_t g_first = (int64_t)blockIdx.x * kEmitThreads;
+  const int64_t g_end = min(g_first + (int64_t)kEmitThreads, n);
+  const int64_t i = g_first + threadIdx.x;
+  const uint32_t blk0 = off[g_first], blk1 = off[g_end];
+  const bool staged = blk1 - blk0 <= (uint32_t)kEmitStage;
+  if (i < n) {
+    const ScanDesc &sd = T.s[T.of_gauss(i)];
+    const uint32_t base = off[i], b0 = (uint32_t)sd.b0;
+    if (staged) {
+      enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
+        sbrick[base - blk0 + j] = b0 + brick;
+        sgid[base - blk0 + j] = (uint32_t)i;
+      });
+    } else {
+      enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
+        const int64_t slot = (int64_t)base + j;
+        if (slot < cap) {
+          key_brick[slot] = b0 + brick;
+          key_gid[slot] = (uint32_t)i;
+        }
+      });
     }
-  });
+  }
+  if (!staged) return;  // uniform per block
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kEmitThreads) {
+    const int64_t slot = (int64_t)blk0 + k;
+    if (slot < cap) {
+      key_brick[slot] = sbrick[k];
+      key_gid[slot] = sgid[k];
+    }
+  }
 }
 
 hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
   if (T.n_total == 0) return hipSuccess;
   char *b = (char *)ws;
-  int blocks = (int)((T.n_total + 255) / 256);
+  int blocks = (int)((T.n_total + kEmitThreads - 1) / kEmitThreads);
   prof_begin(s);
-  k_emit<<<blocks, 256, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+  k_emit<<<blocks, kEmitThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
                                 (const uint32_t *)(b + L.off), L.cap, (const DevStatus *)(b + L.status),
                                 (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid));
   prof_end(s, "emit");
@@ -319,7 +350,8 @@ hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayou
 
 // ------------------------------------------------------------------------------------------------
 // LSD radix sort of (brick id, slot) pairs, 8 bits per pass, stable.  Tiles of 4096 keys.
-//   hist:    per-tile digit counts, digit-major [256][tiles] (scanned into global offsets).
+//   hist:    per-tile digit counts, digit-major [256][tiles]; colscan: scanned along the tiles per
+//            digit, plus the digit totals.
 //   scatter: each wave ranks its 1024 consecutive keys in 16 rounds of 64 (rank among equal digits =
 //            wave ballots + a per-wave running count), the four waves' counts are combined into
 //            per-digit tile offsets, the tile is reordered by digit in LDS and written out in
@@ -348,11 +380,45 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
   hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
 }
 
+// Per digit (one block each): exclusive scan of the digit's tile counts along the tiles, in place,
+// and the digit's total.  The digits' own offsets (an exclusive scan of the 256 totals) are formed by
+// every scatter block from the totals.
+__global__ __launch_bounds__(kSortThreads) void k_radix_colscan(uint32_t *__restrict__ hist, int ntiles,
+                                                                 uint32_t *__restrict__ dtot) {
+  __shared__ uint32_t wsum[kSortThreads / 64];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < ntiles; c0 += kSortThreads) {
+    const int i = c0 + t;
+    const uint32_t v = i < ntiles ? row[i] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d, 64);
+      if (l >= d) incl += o;
+    }
+    if (l == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t off = carry, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kSortThreads / 64; ++k) {
+      off += k < w ? wsum[k] : 0u;
+      tot += wsum[k];
+    }
+    if (i < ntiles) row[i] = off + incl - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (t == 0) dtot[blockIdx.x] = carry;
+}
+
 template <bool LAST>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ key_gid, uint32_t *__restrict__ gout,
-    const DevStatus *st, int64_t cap, int shift, const uint32_t *__restrict__ offsets, int ntiles) {
+    const DevStatus *st, int64_t cap, int shift, const uint32_t *__restrict__ offsets, int ntiles,
+    const uint32_t *__restrict__ dtot) {
   __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];  // per-wave running counts, then per-wave offsets
   __shared__ uint32_t tdo[kRadix];                      // digit offsets within the tile
   __shared__ uint32_t goff[kRadix];                     // global offset of the tile's first key of each digit
@@ -364,7 +430,25 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   const int n_tile = (int)min((int64_t)kSortTile, K - base);
 #pragma unroll
   for (int v = 0; v < kSortThreads / 64; ++v) wcnt[v][t] = 0;
-  goff[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
+  {  // digit base = exclusive scan of the digit totals (one wave, 4 digits per lane)
+    if (t < 64) {
+      const uint32_t a0 = dtot[4 * t], a1 = dtot[4 * t + 1], a2 = dtot[4 * t + 2], a3 = dtot[4 * t + 3];
+      const uint32_t s4 = a0 + a1 + a2 + a3;
+      uint32_t incl = s4;
+#pragma unroll
+      for (int dd = 1; dd < 64; dd <<= 1) {
+        const uint32_t o = __shfl_up(incl, dd, 64);
+        if (l >= dd) incl += o;
+      }
+      const uint32_t ex = incl - s4;
+      tdo[4 * t] = ex;
+      tdo[4 * t + 1] = ex + a0;
+      tdo[4 * t + 2] = ex + a0 + a1;
+      tdo[4 * t + 3] = ex + a0 + a1 + a2;
+    }
+    __syncthreads();
+    goff[t] = tdo[t] + offsets[(int64_t)t * ntiles + blockIdx.x];
+  }
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
@@ -462,7 +546,7 @@ hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStrea
   uint32_t *ka = (uint32_t *)(b + L.key_brick), *kb = (uint32_t *)(b + L.keys_alt);
   uint32_t *va = (uint32_t *)(b + L.vals_a), *vb = (uint32_t *)(b + L.vals_b);
   uint32_t *hist = (uint32_t *)(b + L.hist);
-  uint64_t *tmp = (uint64_t *)(b + L.scan_tmp);
+  uint32_t *dtot = (uint32_t *)(b + L.scan_tmp);  // digit totals (the scan scratch is free here)
   const int nt = L.sort_blocks;
   hipError_t err = hipSuccess;
   if (nt > 0) {
@@ -474,16 +558,17 @@ hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStrea
       prof_begin(s);
       k_radix_hist<<<nt, kSortThreads, 0, s>>>(kin, st, L.cap, p * kRadixBits, hist, nt);
       prof_end(s, "radix_hist");
-      err = scan_u32(hist, (int64_t)kRadix * nt, tmp, -1, 0, st, s, "radix_scan");
-      if (err != hipSuccess) return err;
+      prof_begin(s);
+      k_radix_colscan<<<kRadix, kSortThreads, 0, s>>>(hist, nt, dtot);
+      prof_end(s, "radix_scan");
       prof_begin(s);
       if (last)
         k_radix_scatter<true><<<nt, kSortThreads, 0, s>>>(kin, vin, kout, vout, (const uint32_t *)(b + L.key_gid),
                                                           (uint32_t *)(b + L.list_gid), st, L.cap, p * kRadixBits,
-                                                          hist, nt);
+                                                          hist, nt, dtot);
       else
         k_radix_scatter<false><<<nt, kSortThreads, 0, s>>>(kin, vin, kout, vout, nullptr, nullptr, st, L.cap,
-                                                           p * kRadixBits, hist, nt);
+                                                           p * kRadixBits, hist, nt, dtot);
       prof_end(s, "radix_scatter");
       kin = kout;
       vin = vout;

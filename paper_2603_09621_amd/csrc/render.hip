@@ -13,12 +13,12 @@
 // so the result is bitwise deterministic.
 //
 // Backward: two waves per brick, one Gaussian per lane.  The brick's per-voxel factors
-// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; a first pass marks, per key, the
-// 4-voxel row segments its ellipsoid may touch, the keys are ordered by that count so that the lanes
-// of a wave run the same number of iterations, and each lane walks exactly its marked segments,
-// evaluates their 4 voxels unrolled and accumulates the moments sum(k), sum(k dx), sum(k dx^2) and
-// sum(c w) of k = dL/dw * w, folded with the row's (dy, dz) into the 11 brick-local sums of
-// (1, delta, delta delta^T) and dA.  The sums of each
+// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by their
+// number of rows in the brick so that the lanes of a wave run the same number of iterations; each
+// lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
+// maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and accumulates per
+// row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w, folded with the row's
+// (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.  The sums of each
 // (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel reduces each
 // Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
@@ -243,19 +243,10 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p0 = (sum c w, sum k, sum k dx, sum k dy), p1 = (sum k dz, sum k dx dx, sum k dy dy, sum k dz dz),
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
-//
-// Work unit: one 4-voxel segment of one brick row (a brick has 32 rows of BX voxels, BX / 4
-// segments each).  A first pass over a window of the brick's keys marks, per key, the units its
-// ellipsoid may touch: for each row of the key's voxel box, the exponent's maximum over each
-// segment (the row's quadratic at its vertex clamped to the segment) is compared with the cutoff
-// with a rounding allowance, so a unit holding a pair with d^2 <= 9 is never left out.  Keys are then
-// ordered by their unit count (an LDS counting sort; a key's result does not depend on where it
-// runs), and every lane walks exactly its key's marked units, so the lanes of a wave run similar
-// trip counts and no lane idles on untouched rows.  The per-pair predicate inside a unit is the same
-// as in the forward, so both take the same inclusion decisions.
 
 constexpr int kBwdThreads = 128;
-constexpr int kBwdWindow = 1024;  // keys ordered by work per pass over the brick list
+constexpr int kBwdWindow = 2048;  // keys ordered by work per pass over the brick list
+constexpr int kBwdBuckets = 34;   // rows per key in a brick: 0 .. 32 (bucket 0 = 32 rows)
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
 __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
@@ -290,16 +281,12 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
                                                      const float *__restrict__ gI, const float *__restrict__ obs,
                                                      float *__restrict__ loss_part, int64_t cap,
                                                      float4 *__restrict__ part) {
-  constexpr int RP = BX + 1;     // LDS row stride in voxels (pad: rows of a wave hit different banks)
-  constexpr int NS = BX / 4;     // segments per brick row
-  constexpr int NU = 32 * NS;    // units per brick
-  constexpr int NB = NU + 2;     // buckets: NU - (unit count), and one for invalid keys
+  constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
   if (st->overflow) return;
   __shared__ float2 sCI[32 * RP];
-  __shared__ uint32_t smask[NS][kBwdWindow];  // per key and segment column: bit = brick row lz * 8 + ly
   __shared__ uint16_t sorder[kBwdWindow];
   __shared__ uint8_t sbucket[kBwdWindow];
-  __shared__ uint32_t bcount[NB], bcursor[NB];
+  __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   const int64_t b = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_brick(b)];
   const BrickGrid &bg = sd.bg;
@@ -361,51 +348,26 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   const int xe = min(x0 + BX - 1, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
   for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
     const int L = (int)min((uint32_t)kBwdWindow, end - w0);
-    for (int k = t; k < NB; k += kBwdThreads) bcount[k] = 0u;
+    // order the window's keys by their number of rows in the brick, most first, so that the lanes of
+    // a wave run the same number of row iterations (each key's result is independent of where it
+    // runs, so the order does not change any result)
+    if (t < kBwdBuckets) bcount[t] = 0u;
     __syncthreads();
-    // pass 1: the units each key may touch
     for (int j = t; j < L; j += kBwdThreads) {
       const uint32_t gid = list_gid[w0 + j];
-      uint32_t m[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) m[s] = 0u;
-      int bk = NB - 1;
+      int bk = kBwdBuckets - 1;
       if (gid < T.n_total) {
-        const EvalRec R = er[gid];
         int xl, xh, yl, yh, zl, zh;
-        key_box(bg, R, cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
-        if (xl <= xh && yl <= yh && zl <= zh) {
-          const float mx = R.r0.x, a = R.r1.x, thr = R.r1.w;
-          const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
-          for (int iz = zl; iz <= zh; ++iz)
-            for (int iy = yl; iy <= yh; ++iy) {
-              float dy, dz, bq, cq;
-              row_coeffs(R, centre(bg.oy, bg.hy, iy), centre(bg.oz, bg.hz, iz), dy, dz, bq, cq);
-              const float xs = -bq * inv2a;
-              const float lim = thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq));
-              const uint32_t bit = 1u << ((iz - z0) * 8 + (iy - y0));
-#pragma unroll
-              for (int s = 0; s < NS; ++s) {
-                if (x0 + 4 * s > xh || x0 + 4 * s + 3 < xl) continue;
-                const float xc = fminf(fmaxf(xs, px[4 * s] - mx), px[4 * s + 3] - mx);
-                if (row_q(a, bq, cq, xc) >= lim) m[s] |= bit;
-              }
-            }
-          int cnt = 0;
-#pragma unroll
-          for (int s = 0; s < NS; ++s) cnt += __popc(m[s]);
-          bk = NU - cnt;
-        }
+        key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+        if (xl <= xh && yl <= yh && zl <= zh) bk = 32 - (yh - yl + 1) * (zh - zl + 1);
       }
-#pragma unroll
-      for (int s = 0; s < NS; ++s) smask[s][j] = m[s];
       sbucket[j] = (uint8_t)bk;
       atomicAdd(&bcount[bk], 1u);
     }
     __syncthreads();
     if (t == 0) {
       uint32_t run = 0;
-      for (int k = 0; k < NB; ++k) {
+      for (int k = 0; k < kBwdBuckets; ++k) {
         bcursor[k] = run;
         run += bcount[k];
       }
@@ -413,84 +375,68 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     __syncthreads();
     for (int j = t; j < L; j += kBwdThreads) sorder[atomicAdd(&bcursor[sbucket[j]], 1u)] = (uint16_t)j;
     __syncthreads();
-    // pass 2: each lane walks its key's units
     for (int c0 = w * 64; c0 < L; c0 += kBwdThreads) {
       const int p = c0 + l;
       if (p >= L) continue;
-      const int j = sorder[p];
-      const uint32_t k = w0 + j;
+      const uint32_t k = w0 + sorder[p];
       const uint32_t gid = list_gid[k];
       const uint32_t slot = list_slot[k];
       if (gid >= T.n_total || (int64_t)slot >= cap) continue;
       const EvalRec R = er[gid];
-      const float mx = R.r0.x, A = R.r0.w, a = R.r1.x, thr = R.r1.w;
-      uint32_t m[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) m[s] = smask[s][j];
+      const CullRec C = cr[gid];
+      const float mx = R.r0.x, A = R.r0.w;
+      const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
+      int xl, xh, yl, yh, zl, zh;
+      key_box(bg, R, C, cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-      while (true) {
-        // next unit: the lowest set bit of the first non-empty segment column
-        int s = -1;
-#pragma unroll
-        for (int q = NS - 1; q >= 0; --q)
-          if (m[q]) s = q;
-        if (s < 0) break;
-        uint32_t cur = 0u;
-#pragma unroll
-        for (int q = 0; q < NS; ++q)
-          if (q == s) cur = m[q];
-        const int bit = __builtin_ctz(cur);
-#pragma unroll
-        for (int q = 0; q < NS; ++q)
-          if (q == s) m[q] = cur & (cur - 1u);
-        float xs4[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          xs4[kk] = px[kk];
-#pragma unroll
-          for (int q = 1; q < NS; ++q)
-            if (q == s) xs4[kk] = px[4 * q + kk];
-        }
-        const int iy = y0 + (bit & 7), iz = z0 + (bit >> 3);
+      const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
+      const int ny_k = yh - yl + 1;
+      const int nrows = (xl <= xh && yl <= yh && zl <= zh) ? ny_k * (zh - zl + 1) : 0;
+      int iy = yl, iz = zl;
+      for (int r = 0; r < nrows; ++r) {
+        const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
         float dy, dz, bq, cq;
-        row_coeffs(R, centre(bg.oy, bg.hy, iy), centre(bg.oz, bg.hz, iz), dy, dz, bq, cq);
-        const float2 *ci = sCI + bit * RP + 4 * s;
-        float tA, m0, m1, m2;
+        row_coeffs(R, py, pz, dy, dz, bq, cq);
+        // the row's maximum of q is at dx* = -b / (2a); rows whose maximum is clearly below the
+        // cutoff hold no pair
+        const float xs = -bq * inv2a;
+        const float qmax = fmaf(0.5f * bq, xs, cq);
+        if (qmax >= thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) {
+          const int rb = ((iz - z0) * 8 + (iy - y0)) * RP;
+          float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const float dx = xs4[kk] - mx;
-          const float q = row_q(a, bq, cq, dx);
-          float wt = fast_exp2(q);
-          wt = q >= thr ? wt : 0.f;
-          const float2 c2 = ci[kk];
-          const float tt = c2.x * wt;
-          const float kap = (A - c2.y) * tt;
-          const float u = kap * dx;
-          if (kk == 0) {
-            tA = tt;
-            m0 = kap;
-            m1 = u;
-            m2 = u * dx;
-          } else {
+          for (int kk = 0; kk < BX; ++kk) {
+            const float dx = px[kk] - mx;
+            const float q = row_q(a, bq, cq, dx);
+            float wt = fast_exp2(q);
+            wt = q >= thr ? wt : 0.f;
+            const float2 ci = sCI[rb + kk];
+            const float tt = ci.x * wt;
+            const float kap = (A - ci.y) * tt;
             tA += tt;
             m0 += kap;
+            const float u = kap * dx;
             m1 += u;
             m2 = fmaf(u, dx, m2);
           }
+          sA += tA;
+          sk += m0;
+          skx += m1;
+          sky = fmaf(m0, dy, sky);
+          skz = fmaf(m0, dz, skz);
+          mxx += m2;
+          mxy = fmaf(m1, dy, mxy);
+          mxz = fmaf(m1, dz, mxz);
+          const float m0dy = m0 * dy;
+          myy = fmaf(m0dy, dy, myy);
+          myz = fmaf(m0dy, dz, myz);
+          mzz = fmaf(m0 * dz, dz, mzz);
         }
-        sA += tA;
-        sk += m0;
-        skx += m1;
-        sky = fmaf(m0, dy, sky);
-        skz = fmaf(m0, dz, skz);
-        mxx += m2;
-        mxy = fmaf(m1, dy, mxy);
-        mxz = fmaf(m1, dz, mxz);
-        const float m0dy = m0 * dy;
-        myy = fmaf(m0dy, dy, myy);
-        myz = fmaf(m0dy, dz, myz);
-        mzz = fmaf(m0 * dz, dz, mzz);
+        if (++iy > yh) {
+          iy = yl;
+          ++iz;
+        }
       }
       float4 *o = part + (int64_t)slot * 3;
       o[0] = make_float4(sA, sk, skx, sky);

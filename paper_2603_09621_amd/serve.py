@@ -121,12 +121,33 @@ class Server:
         self.headroom, self.fit_headroom = headroom, fit_headroom
         self.keep_results = keep_results
         self.device = torch.device(device)
-        self.rstream = torch.cuda.Stream(device=self.device)
-        self.fstream = torch.cuda.Stream(device=self.device)
+        self._streams = None
         self.keys: Dict[Tuple[int, float], int] = {}
         self.used = 0
         self.peak_used = 0
         self.done: List = []
+
+    @property
+    def rstream(self):
+        return self._stream(0)
+
+    @property
+    def fstream(self):
+        return self._stream(1)
+
+    def _stream(self, k):
+        if self._streams is None:  # created on first use (streams of default priority)
+            self._streams = (torch.cuda.Stream(device=self.device), torch.cuda.Stream(device=self.device))
+        return self._streams[k]
+
+    def admissible(self, r, busy: bool, renders_waiting: int, fits_active: int) -> bool:
+        """Admission rule for the queue head: a free slot of its kind and room in the HBM budget;
+        a request larger than the whole budget is admitted only when nothing else is admitted."""
+        if r.kind == "render" and renders_waiting >= 4 * self.max_batch:
+            return False
+        if r.kind == "fit" and fits_active >= self.max_fits:
+            return False
+        return not busy or self.used + r.footprint <= self.budget
 
     # ---- sizing ---------------------------------------------------------------------------------
 
@@ -268,11 +289,7 @@ class Server:
             while queue:
                 r = queue[0]
                 busy = bool(admitted_renders or fits or joining or rflight or fflight)
-                if r.kind == "render" and len(admitted_renders) >= 4 * self.max_batch:
-                    break
-                if r.kind == "fit" and len(fits) + len(joining) >= self.max_fits:
-                    break
-                if busy and self.used + r.footprint > self.budget:
+                if not self.admissible(r, busy, len(admitted_renders), len(fits) + len(joining)):
                     break
                 queue.popleft()
                 r.t_admit = now()

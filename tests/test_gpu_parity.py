@@ -310,3 +310,43 @@ def test_crowded_bricks_long_lists():
     ref = oracle.grad(p, grid, np64(I), np64(W), go.astype(np.float32).astype(np.float64))
     for k in ("mu", "amp"):
         assert_grad_close(gg[k], ref[k], f"crowded d_{k}")
+
+
+def test_fit_step_with_learnable_relaxation():
+    """The relaxation factor r as a fitted parameter (§3.1): one fit step with a nonzero learning
+    rate for r, against the oracle's FP64 step, for every parameter group including r."""
+    gs = gs_mod()
+    dims, zdown = (32, 24, 16), 4
+    hr = synth.phantom(71, dims)
+    lr_obs = synth.zmean_observation(hr, zdown)
+    p = synth.lattice_init(72, lr_obs, 700, f=zdown)
+    p["relax"] = np.random.default_rng(73).uniform(0.5, 1.0, p["amp"].shape[0]).astype(np.float32)
+    grid = oracle.Grid(*dims)
+    p = cases.condition(p, grid, seed=74, jitter=(0.5, 0.5, 1.0))
+    lr_obs = cases.condition_obs(p, grid, lr_obs, zdown)
+    say("fit step, learnable r", grid.shape, p["amp"].shape[0])
+    g = gs.Gaussians.from_numpy(p)
+    ggrid = to_grid(grid)
+    adam = gs.Adam(lr=(1e-2, 5e-3, 1e-3, 1e-2, 5e-3))
+    fo = gs.FitOpts(ggrid, zdown=zdown, adam=adam)
+    bins = gs.plan_bins(g, ggrid, fo.opts, headroom=1.5)
+    st = gs.FitState(g)
+    buf = gs.FitBuffers(g.n, ggrid, relax=True)
+    gs.gs_fit_step(st, torch.from_numpy(lr_obs).cuda(), fo, bins, buf)
+    gs.gs_status(bins)
+    lr = dict(zip(oracle.GROUPS, [float(np.float32(x)) for x in adam.lr]))
+    m0 = {k: np.zeros(np.shape(p[k])) for k in oracle.GROUPS}
+    L, newp, _, _, gr = oracle.fit_step(p, lr_obs, grid, m0, m0, 1, lr, f=zdown, beta1=float(np.float32(0.9)),
+                                        beta2=float(np.float32(0.999)), adam_eps=float(np.float32(1e-8)))
+    assert float(buf.loss.item()) == pytest.approx(L, rel=1e-5)
+    gg = {k: np64(v) for k, v in buf.grads.as_dict().items() if v is not None}
+    # the lattice Gaussians have sigma_x = sigma_y: the quaternion gradient's rotation about z is 0 by
+    # symmetry; a floor at 1e-7 of the other gradients' scale
+    floor = 1e-7 * max(float(np.sqrt(np.mean(gr[k] ** 2))) for k in ("mu", "log_scale", "amp"))
+    for k in oracle.GROUPS:
+        assert_grad_close(gg[k], gr[k], f"fit d_{k}", floor=floor)
+    for k in oracle.GROUPS:
+        got = np64(getattr(g, k))
+        big = np.abs(gr[k]) > max(1e-2 * np.sqrt(np.mean(gr[k] ** 2)), 1e3 * floor)
+        np.testing.assert_allclose(got[big], newp[k][big], rtol=1e-6, atol=1e-3 * lr[k], err_msg=k)
+    assert (np64(g.relax) > 0).all()
