@@ -87,9 +87,12 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
                                                  unsigned long long *__restrict__ pair_count) {
   constexpr int NT = 32 * BX, NW = BX / 2, NQX = BX / 4;
   if (st->overflow) return;
-  __shared__ EvalRec srec[NT];
+  // srec[NT] is an empty record (threshold +inf: never a pair) that pads the wave lists to a
+  // multiple of 4; the lists hold byte offsets into srec
+  __shared__ EvalRec srec[NT + 1];
   __shared__ uint8_t smask[NT];
-  __shared__ uint16_t wlist[NW][NT];
+  __shared__ uint16_t wlist[NW][NT + 4];
+  constexpr uint16_t kPad = (uint16_t)(NT * sizeof(EvalRec));
   __shared__ float4 sred[NW][4][16][2];
   __shared__ unsigned long long scount[NW];
 
@@ -111,6 +114,11 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
   const uint32_t start = brick_off[b], end = brick_off[b + 1];
   const uint64_t lt = lanemask_lt();
 
+  if (t == 0) {
+    srec[NT].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    srec[NT].r1 = make_float4(0.f, 0.f, 0.f, INFINITY);
+    srec[NT].r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   float Wa[4] = {0.f, 0.f, 0.f, 0.f}, Sa[4] = {0.f, 0.f, 0.f, 0.f};
   uint32_t npairs = 0;
   for (uint32_t c0 = start; c0 < end; c0 += NT) {
@@ -131,15 +139,14 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
     for (int j0 = 0; j0 < cnt; j0 += 64) {
       const bool has = (j0 + l < cnt) && ((smask[j0 + l] >> w) & 1);
       const uint64_t bal = __ballot(has);
-      if (has) wlist[w][nw + __popcll(bal & lt)] = (uint16_t)(j0 + l);
+      if (has) wlist[w][nw + __popcll(bal & lt)] = (uint16_t)((j0 + l) * sizeof(EvalRec));
       nw += __popcll(bal);
     }
+    if (l < 4) wlist[w][nw + l] = kPad;
     __syncthreads();
     for (int j0 = 0; j0 < nw; j0 += 4) {
-      const int j = j0 + grp;
-      const bool valid = j < nw;
-      const EvalRec R = srec[wlist[w][valid ? j : j0]];
-      const float thr = valid ? R.r1.w : INFINITY;
+      const EvalRec R = *reinterpret_cast<const EvalRec *>(reinterpret_cast<const char *>(srec) + wlist[w][j0 + grp]);
+      const float thr = R.r1.w;
       float dy, dz, bq, cq;
       row_coeffs(R, py, pz, dy, dz, bq, cq);
 #pragma unroll
