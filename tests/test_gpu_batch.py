@@ -80,7 +80,7 @@ def _scan(seed, dims, n, origin, spacing):
     return p, grid
 
 
-@pytest.mark.parametrize("bx", (8, 16))
+@pytest.mark.parametrize("bx", (4, 8, 16))
 def test_batch_render_and_gradient_equal_single(bx):
     gs = gs_mod()
     scans = [_scan(*s) for s in SCANS]
@@ -190,3 +190,55 @@ def test_batch_fit_steps_equal_single(zdown):
             a = st.m[c * gall.n + w * o[k]: c * gall.n + w * o[k + 1]]
             b = st1.m[c * n: c * n + w * n]
             assert torch.equal(a, b), f"scan {k} m group {gi}"
+
+
+def test_full_batch_of_tiny_and_empty_scans():
+    """The largest batch (16 scans): grids smaller than one brick, ragged grids, empty Gaussian sets;
+    two fit steps bitwise equal to the single-scan calls, and more than 16 scans rejected."""
+    gs = gs_mod()
+    rng = np.random.default_rng(241)
+    dims = [(3, 5, 4), (8, 8, 4), (13, 9, 8), (20, 17, 12), (5, 30, 4), (31, 6, 16), (9, 9, 8), (16, 16, 8),
+            (7, 11, 4), (24, 8, 8), (4, 4, 4), (17, 23, 12), (12, 12, 4), (6, 19, 8), (27, 14, 12), (10, 10, 20)]
+    data = []
+    for k, d in enumerate(dims):
+        hr = synth.phantom((241, k), d)
+        lr = synth.zmean_observation(hr, 4)
+        n = 0 if k in (3, 10) else int(min(lr.size, rng.integers(5, 60)))
+        p = synth.lattice_init((242, k), lr, n, f=4, stride_xy=1) if n else {
+            "mu": np.zeros((0, 3), np.float32), "log_scale": np.zeros((0, 3), np.float32),
+            "quat": np.zeros((0, 4), np.float32), "amp": np.zeros(0, np.float32), "relax": np.zeros(0, np.float32)}
+        data.append((p, lr, d))
+    say("16-scan batch", [p["amp"].shape[0] for p, _, _ in data])
+    singles = []
+    for p, lr, d in data:
+        g = gs.Gaussians.from_numpy(p)
+        grid = gs.Grid(*d)
+        fo = gs.FitOpts(grid)
+        bins = gs.plan_bins(g, grid, fo.opts, headroom=2.0) if g.n else gs.Bins(0, grid, fo.opts, 1024)
+        st = gs.FitState(g)
+        buf = gs.FitBuffers(g.n, grid, relax=True)
+        obs = torch.from_numpy(lr).cuda()
+        for _ in range(2):
+            gs.gs_fit_step(st, obs, fo, bins, buf)
+        gs.gs_status(bins)
+        singles.append((g, float(buf.loss.item())))
+    batch = gs.Batch([p["amp"].shape[0] for p, _, _ in data], [gs.Grid(*d) for _, _, d in data])
+    gall = gs.concat([gs.Gaussians.from_numpy(p) for p, _, _ in data])
+    fo = gs.FitOpts(None)
+    bins = gs.plan_bins_batch(gall, batch, fo.opts, headroom=2.0)
+    st = gs.FitState(gall, nscans=16)
+    buf = gs.FitBuffers(gall.n, batch, relax=True, need_dL_dI=False)
+    obs = torch.from_numpy(np.concatenate([lr.reshape(-1) for _, lr, _ in data])).cuda()
+    for _ in range(2):
+        gs.gs_fit_step_batch(st, obs, batch, fo, bins, buf)
+    gs.gs_status(bins)
+    o = batch.g_offsets
+    losses = buf.loss.cpu().numpy()
+    for k, (g1, l1) in enumerate(singles):
+        for name in gs.GROUPS:
+            assert torch.equal(getattr(gall, name)[o[k]:o[k + 1]], getattr(g1, name)), f"scan {k} {name}"
+        assert losses[k] == np.float32(l1), f"scan {k} loss"
+    assert (st.step.cpu().numpy() == 2).all()
+    big = gs.Batch([1] * 17, [gs.Grid(4, 4, 4)] * 17)
+    with pytest.raises(gs.GSError):
+        gs.gs_workspace_size_batch(big, gs.Opts(), 10)
