@@ -12,7 +12,7 @@ Each useful pair is evaluated once in the forward and once in the backward.  The
 from replaying the same steps from a snapshot (the kernels are deterministic) with a counting pass
 after each step.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -167,7 +167,7 @@ def batch_section(args, dev):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -47,7 +47,7 @@ enum {
   GS_ERR_CAPACITY = -2,    /* more (brick, Gaussian) keys than the workspace's key capacity */
   GS_ERR_NONFINITE = -3,   /* NaN/Inf parameter, zero quaternion or relaxation factor <= 0 */
   GS_ERR_HIP = -4,         /* a HIP runtime call failed */
-  GS_ERR_UNSUPPORTED = -5  /* valid but not supported by this build (e.g. a brick shape) */
+  GS_ERR_UNSUPPORTED = -5  /* valid but not supported by this library (e.g. a brick shape) */
 };
 
 /* Gaussian set (§3.1): n Gaussians, structure of arrays, device pointers. */
@@ -71,7 +71,7 @@ typedef struct {
 #define GS_FLAG_FORWARD_ONLY 1u /* workspace without the backward's partial sums (48 B per key less);
                                    the backward and the fit reject such options */
 
-/* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4; this build also runs
+/* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4; the library also runs
  * 4x8x4 and 16x8x4, a choice that changes speed, never results); gs_brick_supported() tells.  cutoff: Mahalanobis truncation radius (3 = the 3-sigma
  * ellipsoid).  eps: denominator regulariser (>= 0). */
 typedef struct {
@@ -179,7 +179,7 @@ int gs_workspace_size_batch(const gs_batch_t *batch, const gs_opts_t *opts, int6
                             size_t *bytes /* host out */);
 size_t gs_fit_scratch_bytes_batch(const gs_batch_t *batch);
 
-/* 1 if the brick shape is supported by the kernels of this build, else 0. */
+/* 1 if the brick shape is supported by the kernels of this library, else 0. */
 int gs_brick_supported(int32_t bx, int32_t by, int32_t bz);
 
 /* ---- binning (§3.3: for each brick, the Gaussians whose 3-sigma ellipsoid meets it) --------- */
