@@ -106,3 +106,18 @@ def test_binding_exposes_the_conveniences():
                  "gs_fit_step", "gs_fit_step_batch", "gs_render_bwd_batch", "gs_count_pairs_batch"):
         assert hasattr(gs, name), name
     from paper_2603_09621_amd import autograd, autotune, graph, serve  # noqa: F401  (import cleanly)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """Importing the binding where libgs.so is absent raises ImportError (there is no fallback)."""
+    import shutil
+    import subprocess
+    import sys
+
+    pkg = tmp_path / "pkg_copy"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_2603_09621_amd", "gs.py"), pkg / "gs.py")
+    code = "import sys; sys.path.insert(0, %r); import gs" % str(pkg)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libgs.so is missing" in r.stderr
