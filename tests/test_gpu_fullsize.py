@@ -1,4 +1,5 @@
-"""Parity at the full sizes of the benchmark workloads (sampled or masked comparisons).
+"""Parity at the full sizes of the benchmark workloads (sampled or masked comparisons), in the
+launch configurations the benchmark times (fit step, batched fit step, batched forward-only render).
 
 Anisotropic backward-heavy workload (320x320x256, 2M Gaussians, log-scale std 0.8, axis ratio <= 8):
 inputs cannot be conditioned (the largest Gaussians always have pairs within the FP32/FP64 ambiguity
@@ -67,3 +68,116 @@ def test_fit_workload_full_size_sampled():
     assert_fwd_close(np64(I).reshape(-1)[vox], Io, "fit I")
     n_amb = int(oracle.ambiguous(p, grid, cases.BAND).sum())
     assert abs(int(cnt.item()) - oracle.count_pairs(p, grid)) <= n_amb
+
+
+def _fit_stagewise_check(gs, p, lr_obs, dims, I_t, W_t, grads, loss, what, nsel=64, seed=9):
+    """Stage-wise check of one fit step's loss and gradients at full size: the oracle takes the GPU's
+    I and W (FP32) and forms the loss and dL/dI itself; gradients of `nsel` sampled Gaussians without
+    ambiguous pairs are compared."""
+    grid = oracle.Grid(*dims)
+    I = np64(I_t).reshape(grid.shape)
+    W = np64(W_t).reshape(grid.shape)
+    L, gI = oracle.fit_l1_loss(I, lr_obs, 4)
+    assert loss == pytest.approx(L, rel=1e-5), what
+    per_g = oracle.ambiguous(p, grid, cases.BAND)
+    cand = np.flatnonzero(per_g == 0)
+    sel = np.sort(np.random.default_rng(seed).choice(cand, min(nsel, cand.size), replace=False))
+    ref = oracle.grad(p, grid, I, W, gI, sel=sel)
+    for k in ("mu", "log_scale", "quat", "amp", "relax"):
+        got = np64(getattr(grads, k)).reshape(ref[k].shape)
+        assert_grad_close(got[sel], ref[k][sel], f"{what} d_{k}",
+                          floor=1e-7 * float(np.sqrt(np.mean(ref["mu"][sel] ** 2))))
+
+
+def test_fit_step_full_size_stagewise():
+    """One gs_fit_step of the fit workload (256x256x128, 500k Gaussians) in the benchmark's launch
+    configuration: sampled forward voxels, the fused L1 loss and 64 sampled gradients."""
+    from paper_2603_09621_amd import gs
+
+    p, lr_obs, _ = synth.workload_fit()
+    dims = (256, 256, 128)
+    grid = gs.Grid(*dims)
+    g = gs.Gaussians.from_numpy(p)
+    fo = gs.FitOpts(grid)
+    bins = gs.plan_bins(g, grid, fo.opts, headroom=1.5)
+    st = gs.FitState(g)
+    buf = gs.FitBuffers(g.n, grid, relax=True)
+    say("fit step full size")
+    gs.gs_fit_step(st, torch.from_numpy(lr_obs).cuda(), fo, bins, buf)
+    gs.gs_status(bins)
+    og = oracle.Grid(*dims)
+    vox = np.sort(np.random.default_rng(10).choice(og.size, 3000, replace=False))
+    lo = oracle.render_points(p, og, vox, cutoff=float(np.sqrt(9.0 - cases.BAND)))
+    hi = oracle.render_points(p, og, vox, cutoff=float(np.sqrt(9.0 + cases.BAND)))
+    clean = (lo[0] == hi[0]) & (lo[1] == hi[1])
+    Io, Wo, _ = oracle.render_points(p, og, vox)
+    assert_fwd_close(np64(buf.I).reshape(-1)[vox][clean], Io[clean], "fit step I")
+    assert_fwd_close(np64(buf.W).reshape(-1)[vox][clean], Wo[clean], "fit step W")
+    _fit_stagewise_check(gs, p, lr_obs, dims, buf.I, buf.W, buf.grads, float(buf.loss.item()), "fit step")
+
+
+def test_batch_full_size_stagewise():
+    """One batched fit step of the 16-scan uneven batch (74M voxels, 4.9M Gaussians): every scan's
+    forward at sampled voxels and loss, and sampled gradients of the smallest and largest scan."""
+    from paper_2603_09621_amd import gs
+
+    scans = synth.workload_batch(seed=4)
+    batch = gs.Batch([q["amp"].shape[0] for q, _, _ in scans], [gs.Grid(*d) for _, _, d in scans])
+    g = gs.concat([gs.Gaussians.from_numpy(q) for q, _, _ in scans])
+    fo = gs.FitOpts(None)
+    bins = gs.plan_bins_batch(g, batch, fo.opts, headroom=1.5)
+    st = gs.FitState(g, nscans=len(batch))
+    buf = gs.FitBuffers(g.n, batch, relax=True, need_dL_dI=False)
+    obs = torch.from_numpy(np.concatenate([lr.reshape(-1) for _, lr, _ in scans])).cuda()
+    say("batch full size", g.n, batch.v_offsets[-1])
+    gs.gs_fit_step_batch(st, obs, batch, fo, bins, buf)
+    gs.gs_status(bins)
+    Is, Ws = batch.split(buf.I), batch.split(buf.W)
+    losses = buf.loss.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for k, (q, lr, d) in enumerate(scans):
+        og = oracle.Grid(*d)
+        vox = np.sort(rng.choice(og.size, 400, replace=False))
+        lo = oracle.render_points(q, og, vox, cutoff=float(np.sqrt(9.0 - cases.BAND)))
+        hi = oracle.render_points(q, og, vox, cutoff=float(np.sqrt(9.0 + cases.BAND)))
+        clean = (lo[0] == hi[0]) & (lo[1] == hi[1])
+        Io, _, _ = oracle.render_points(q, og, vox)
+        assert_fwd_close(np64(Is[k]).reshape(-1)[vox][clean], Io[clean], f"batch scan {k} I")
+        L, _ = oracle.fit_l1_loss(np64(Is[k]), lr, 4)
+        assert float(losses[k]) == pytest.approx(L, rel=1e-5), f"batch scan {k} loss"
+    sizes = [d[0] * d[1] * d[2] for _, _, d in scans]
+    o = batch.g_offsets
+    for k in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        q, lr, d = scans[k]
+        sub = gs.Grads(*(None if getattr(buf.grads, n) is None else getattr(buf.grads, n)[o[k]:o[k + 1]]
+                         for n in gs.GROUPS))
+        say(f"  batch scan {k} {d}: sampled gradients")
+        _fit_stagewise_check(gs, q, lr, d, Is[k], Ws[k], sub, float(losses[k]), f"batch scan {k}", nsel=32)
+
+
+def test_serving_set_full_size_render():
+    """The largest resident set of the request-loop workload rendered at scale 4 of its LR box through
+    the request loop's batched forward-only path (with a second set in the same batch), sampled
+    voxels vs the oracle."""
+    from paper_2603_09621_amd import gs
+
+    sets = synth.serving_sets(5, 32)
+    order = np.argsort([q["amp"].shape[0] for q, _ in sets])
+    picks = [sets[order[-1]], sets[order[0]]]
+    grids = [gs.Grid.at_scale(picks[0][1], 4.0), gs.Grid.at_scale(picks[1][1], 2.5)]
+    gsets = [gs.Gaussians.from_numpy(q) for q, _ in picks]
+    batch = gs.Batch.of_sets(gsets, grids)
+    opts = gs.Opts(forward_only=True)
+    say("serving set full size", [x.n for x in gsets], [gr.shape for gr in grids])
+    I, _, bins = gs.render_batch(None, batch, opts, want_w=False)
+    gs.gs_status(bins)
+    rng = np.random.default_rng(12)
+    for k, ((q, _), gr) in enumerate(zip(picks, grids)):
+        og = oracle.Grid(gr.nx, gr.ny, gr.nz, gr.origin, gr.spacing)
+        vox = np.sort(rng.choice(og.size, 1500, replace=False))
+        lo = oracle.render_points(q, og, vox, cutoff=float(np.sqrt(9.0 - cases.BAND)))
+        hi = oracle.render_points(q, og, vox, cutoff=float(np.sqrt(9.0 + cases.BAND)))
+        clean = (lo[0] == hi[0]) & (lo[1] == hi[1])
+        Io, _, _ = oracle.render_points(q, og, vox)
+        assert clean.mean() > 0.9
+        assert_fwd_close(np64(batch.split(I)[k]).reshape(-1)[vox][clean], Io[clean], f"serving set {k} I")
