@@ -72,8 +72,9 @@ typedef struct {
                                    the backward and the fit reject such options */
 
 /* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4; the library also runs
- * 4x8x4 and 16x8x4, a choice that changes speed, never results); gs_brick_supported() tells.  cutoff: Mahalanobis truncation radius (3 = the 3-sigma
- * ellipsoid).  eps: denominator regulariser (>= 0). */
+ * 4x8x4 and 16x8x4, a choice that changes speed and FP32 summation order only);
+ * gs_brick_supported() tells.  cutoff: Mahalanobis truncation radius (3 = the 3-sigma ellipsoid).
+ * eps: denominator regulariser (>= 0). */
 typedef struct {
   int32_t bx, by, bz;
   float cutoff;
@@ -84,7 +85,7 @@ typedef struct {
 /* Binning workspace: caller-owned device memory of gs_workspace_size() bytes for `key_capacity`
  * (brick, Gaussian) keys.  Holds the per-Gaussian records, the brick-sorted key lists, the brick
  * offsets, the backward's per-key partial sums and the status block.  One workspace serves one
- * Gaussian set and grid at a time. */
+ * Gaussian set and grid (or one batch of scans) at a time. */
 typedef struct {
   void *ws;
   size_t ws_bytes;
@@ -201,7 +202,8 @@ int gs_bin(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts
 
 /* Render I (and the per-voxel weight sum W, the cache the backward reads; may be NULL) on `grid`
  * from bins built by gs_bin with the same g, grid and opts.  I, W: device [nz][ny][nx].  Each
- * voxel sums its Gaussians in ascending index order (bitwise deterministic). */
+ * voxel's sums run over its Gaussians in ascending index order as four interleaved partial sums
+ * added in a fixed order (bitwise deterministic). */
 int gs_render_fwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
                   float *I, float *W, void *stream);
 
@@ -240,10 +242,10 @@ int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_ada
 
 /* One step of the per-scan zero-shot fit (§3.3 "end-to-end", Fig. 1): bin -> render -> z-mean ->
  * L1 vs lr_obs -> backward -> Adam.  lr_obs: device [hr.nz/zdown][hr.ny][hr.nx].  Writes I, W, the
- * gradients and the loss; updates the parameters, the moments and *step.  When zdown equals the
- * brick depth the loss is computed inside the backward kernel and the gradient reduction is fused
- * with Adam.  No host synchronisation; check gs_status() for capacity overflow (the step then leaves
- * the parameters and *step unchanged). */
+ * gradients and the loss; updates the parameters, the moments and *step.  The gradient reduction
+ * is fused with Adam; when zdown equals the brick depth the loss is also computed inside the
+ * backward kernel.  No host synchronisation; check gs_status() for capacity overflow (the step then
+ * leaves the parameters and *step unchanged). */
 int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
                 const gs_fit_buffers_t *buf, void *stream);
 
