@@ -130,9 +130,8 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
   L.list_slot = take(sizeof(uint32_t) * (size_t)cap);
   L.brick_off = take(sizeof(uint32_t) * (size_t)(nbricks + 1));
   L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
-  const int64_t scan_len = std::max<int64_t>(n + 1, (int64_t)kRadix * L.sort_blocks);
-  // scan scratch: tile totals of the count scan, later the radix digit totals
-  L.scan_tmp = take(std::max(sizeof(uint64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1),
+  // scan scratch: per-block key totals of the count scan, later the radix digit totals
+  L.scan_tmp = take(std::max(sizeof(uint64_t) * (size_t)((n + kPrepThreads - 1) / kPrepThreads + 1),
                              sizeof(uint32_t) * (size_t)kRadix));
   L.partials = take(partials ? sizeof(float) * 12 * (size_t)cap : 0);
   L.total = o;
@@ -266,8 +265,6 @@ static int check_common(const gs_gaussians_t *g, const gs_batch_t *bt, const gs_
   if (bins->key_capacity < 0 || bins->key_capacity > (int64_t)0x7FFFFF00)
     return fail(GS_ERR_INVALID_ARG, "key_capacity must be in [0, 2^31 - 256]");
   *L = make_layout(T->n_total, T->nbricks_total, bins->key_capacity, !(opts->flags & GS_FLAG_FORWARD_ONLY));
-  if ((int64_t)kRadix * L->sort_blocks > (int64_t)kScanTile * 8192 || T->n_total + 1 > (int64_t)kScanTile * 8192)
-    return fail(GS_ERR_INVALID_ARG, "key capacity or n beyond the scan limit");
   if (bins->ws_bytes < L->total)
     return fail(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes given, %zu needed", bins->ws_bytes, L->total);
   return GS_OK;

@@ -129,41 +129,53 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
 }
 
 // Fused prep + count: records of Gaussian i (of the concatenated numbering; its parameters are
-// entry i - g0 of its scan's arrays) and its key count cnt[i].  Thread n_total writes cnt[n_total] = 0
-// (the scan's total slot).
-__global__ void k_prep_count(const ScanTable T, float cutoff, EvalRec *__restrict__ er, CullRec *__restrict__ cr,
-                             uint32_t *__restrict__ cnt, DevStatus *st) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = T.n_total;
-  if (i > n) return;
-  if (i == n) {
-    cnt[n] = 0u;
-    return;
+// entry i - g0 of its scan's arrays), its key count cnt[i] and, per block of kPrepThreads
+// Gaussians, the block's key total bsum[block] (the first level of the count scan).
+__global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, float cutoff,
+                                                             EvalRec *__restrict__ er, CullRec *__restrict__ cr,
+                                                             uint32_t *__restrict__ cnt, uint64_t *__restrict__ bsum,
+                                                             DevStatus *st) {
+  __shared__ uint64_t wsum[kPrepThreads / 64];
+  const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
+  uint32_t c = 0;
+  if (i < T.n_total) {
+    const ScanDesc &sd = T.s[T.of_gauss(i)];
+    EvalRec e;
+    CullRec r;
+    make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, r, st);
+    er[i] = e;
+    cr[i] = r;
+    c = enumerate_bricks(sd.bg, e, r, cutoff, [](uint32_t, uint32_t) {});
+    cnt[i] = c;
   }
-  const ScanDesc &sd = T.s[T.of_gauss(i)];
-  EvalRec e;
-  CullRec c;
-  make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, c, st);
-  er[i] = e;
-  cr[i] = c;
-  cnt[i] = enumerate_bricks(sd.bg, e, c, cutoff, [](uint32_t, uint32_t) {});
+  uint64_t v = c;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+  if (lane_id() == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tot = 0;
+    for (int w = 0; w < kPrepThreads / 64; ++w) tot += wsum[w];
+    bsum[blockIdx.x] = tot;
+  }
 }
 
 hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
-  int blocks = (int)((T.n_total + 1 + 255) / 256);
+  const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
+  if (blocks == 0) return hipSuccess;
   prof_begin(s);
-  k_prep_count<<<blocks, 256, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
-                                      (uint32_t *)(b + L.off), (DevStatus *)(b + L.status));
+  k_prep_count<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
+                                               (uint32_t *)(b + L.off), (uint64_t *)(b + L.scan_tmp),
+                                               (DevStatus *)(b + L.status));
   prof_end(s, "prep_count");
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
-// Exclusive scan of a uint32 array (length on the host).  Three launches: per-tile totals, a
-// one-block scan of the tile totals (64-bit), and the per-tile scan.  Each wave scans 16 consecutive
-// chunks of 64 elements with a running carry.  If key_idx >= 0, entry key_idx of the result is the
-// key count: it is stored (64-bit) in the status block with the overflow flag.
+// Second level of the count scan: one block turns the per-block key totals into exclusive block
+// offsets (64-bit, in place), stores the key count K in the status block with the overflow flag
+// (K > capacity) and writes off[n] = K.  Each thread scans a contiguous segment of the totals.
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 #pragma unroll
@@ -183,133 +195,87 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t len,
-                                                               uint64_t *__restrict__ bsum) {
-  __shared__ uint64_t ws[kScanThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanTile;
-  uint64_t acc = 0;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    int64_t idx = base + (int64_t)j * kScanThreads + threadIdx.x;
-    if (idx < len) acc += in[idx];
-  }
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
-  if (lane_id() == 0) ws[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) t += ws[w];
-    bsum[blockIdx.x] = t;
-  }
-}
+constexpr int kBlockScanThreads = 1024;
 
-// One block of 1024 threads scans nb <= 8192 tile totals in place (exclusive).
-__global__ __launch_bounds__(1024) void k_scan_bsums(uint64_t *__restrict__ bsum, int nb) {
-  __shared__ uint64_t wsum[16];
-  constexpr int PER = 8;
-  int t = threadIdx.x;
-  uint64_t v[PER];
+__global__ __launch_bounds__(kBlockScanThreads) void k_scan_blocks(uint64_t *__restrict__ bsum, int64_t nb,
+                                                                    int64_t n, int64_t cap,
+                                                                    uint32_t *__restrict__ off, DevStatus *st) {
+  __shared__ uint64_t wsum[kBlockScanThreads / 64];
+  const int t = threadIdx.x;
+  const int64_t per = (nb + kBlockScanThreads - 1) / kBlockScanThreads;
+  const int64_t s0 = min((int64_t)t * per, nb), s1 = min(s0 + per, nb);
   uint64_t local = 0;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    int idx = t * PER + j;
-    v[j] = idx < nb ? bsum[idx] : 0;
-    local += v[j];
-  }
-  uint64_t incl = wave_incl_scan64(local);
+  for (int64_t k = s0; k < s1; ++k) local += bsum[k];
+  const uint64_t incl = wave_incl_scan64(local);
   if (lane_id() == 63) wsum[t >> 6] = incl;
   __syncthreads();
-  uint64_t woff = 0;
-  for (int w = 0; w < (t >> 6); ++w) woff += wsum[w];
+  uint64_t woff = 0, total = 0;
+  for (int w = 0; w < kBlockScanThreads / 64; ++w) {
+    woff += w < (t >> 6) ? wsum[w] : 0;
+    total += wsum[w];
+  }
   uint64_t run = woff + incl - local;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    int idx = t * PER + j;
-    if (idx < nb) bsum[idx] = run;
-    run += v[j];
+  for (int64_t k = s0; k < s1; ++k) {
+    const uint64_t v = bsum[k];
+    bsum[k] = run;
+    run += v;
   }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t *__restrict__ in,
-                                                              uint32_t *__restrict__ out, int64_t len,
-                                                              const uint64_t *__restrict__ bsum_ex, int64_t key_idx,
-                                                              int64_t cap, DevStatus *st) {
-  __shared__ uint32_t ws[kScanThreads / 64];
-  const int w = threadIdx.x >> 6, l = lane_id();
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * (64 * kScanItems);
-  uint32_t pref[kScanItems];
-  uint32_t carry = 0;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    int64_t idx = base + j * 64 + l;
-    uint32_t v = idx < len ? in[idx] : 0u;
-    uint32_t incl = wave_incl_scan(v);
-    pref[j] = carry + incl - v;
-    carry += __shfl(incl, 63, 64);
+  if (t == 0) {
+    st->n_keys = (int64_t)total;
+    st->overflow = (int64_t)total > cap ? 1 : 0;
+    off[n] = (int64_t)total > cap ? (uint32_t)cap : (uint32_t)total;
   }
-  if (l == 0) ws[w] = carry;
-  __syncthreads();
-  uint32_t off = 0;
-  for (int v = 0; v < w; ++v) off += ws[v];
-  const uint64_t bex = bsum_ex[blockIdx.x];
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    int64_t idx = base + j * 64 + l;
-    if (idx < len) {
-      const uint64_t e64 = bex + (uint64_t)(pref[j] + off);
-      out[idx] = (uint32_t)e64;
-      if (idx == key_idx) {
-        st->n_keys = (int64_t)e64;
-        st->overflow = (int64_t)e64 > cap ? 1 : 0;
-      }
-    }
-  }
-}
-
-static hipError_t scan_u32(uint32_t *data, int64_t len, uint64_t *tmp, int64_t key_idx, int64_t cap, DevStatus *st,
-                           hipStream_t s, const char *name) {
-  const int nb = (int)((len + kScanTile - 1) / kScanTile);
-  if (nb == 0) return hipSuccess;
-  prof_begin(s);
-  k_scan_reduce<<<nb, kScanThreads, 0, s>>>(data, len, tmp);
-  k_scan_bsums<<<1, 1024, 0, s>>>(tmp, nb);
-  k_scan_apply<<<nb, kScanThreads, 0, s>>>(data, data, len, tmp, key_idx, cap, st);
-  prof_end(s, name);
-  return hipGetLastError();
 }
 
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
-  return scan_u32((uint32_t *)(b + L.off), L.n + 1, (uint64_t *)(b + L.scan_tmp), L.n, L.cap,
-                  (DevStatus *)(b + L.status), s, "scan_counts");
+  const int64_t nb = (L.n + kPrepThreads - 1) / kPrepThreads;
+  prof_begin(s);
+  k_scan_blocks<<<1, kBlockScanThreads, 0, s>>>((uint64_t *)(b + L.scan_tmp), nb, L.n, L.cap,
+                                               (uint32_t *)(b + L.off), (DevStatus *)(b + L.status));
+  prof_end(s, "scan_counts");
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
-// Emit: the j-th key of Gaussian i is written at slot off[i] + j, with its scan's global brick id.
-// A block's Gaussians own a contiguous slot range; when it fits, the block assembles its keys in
-// LDS and writes the range out with consecutive threads on consecutive slots.
+// Emit: the j-th key of Gaussian i is written at slot off[i] + j, with its scan's global brick id
+// (the last level of the count scan is done here: off[i] becomes the Gaussian's first slot).  A
+// block's Gaussians own a contiguous slot range; when it fits, the block assembles its keys in LDS
+// and writes the range out with consecutive threads on consecutive slots.
 
-constexpr int kEmitThreads = 256;
 constexpr int kEmitStage = 4096;  // keys staged per block (32 KB of LDS)
 
-__global__ __launch_bounds__(kEmitThreads) void k_emit(const ScanTable T, float cutoff,
+__global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float cutoff,
                                                        const EvalRec *__restrict__ er,
-                                                       const CullRec *__restrict__ cr,
-                                                       const uint32_t *__restrict__ off, int64_t cap,
+                                                       const CullRec *__restrict__ cr, uint32_t *__restrict__ off,
+                                                       const uint64_t *__restrict__ bex, int64_t cap,
                                                        const DevStatus *st, uint32_t *__restrict__ key_brick,
                                                        uint32_t *__restrict__ key_gid) {
   __shared__ uint32_t sbrick[kEmitStage], sgid[kEmitStage];
+  __shared__ uint32_t wtot[kPrepThreads / 64];
   if (st->overflow) return;
   const int64_t n = T.n_total;
-  const int64_t g_first = (int64_t)blockIdx.x * kEmitThreads;
-  const int64_t g_end = min(g_first + (int64_t)kEmitThreads, n);
-  const int64_t i = g_first + threadIdx.x;
-  const uint32_t blk0 = off[g_first], blk1 = off[g_end];
-  const bool staged = blk1 - blk0 <= (uint32_t)kEmitStage;
+  const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
+  // off[i] holds the key count of Gaussian i; turn it into its first slot: the block's offset plus
+  // the exclusive scan of the counts within the block
+  const uint32_t c = i < n ? off[i] : 0u;
+  const uint32_t incl = wave_incl_scan(c);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) wtot[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0, btot = 0;
+#pragma unroll
+  for (int k = 0; k < kPrepThreads / 64; ++k) {
+    woff += k < w ? wtot[k] : 0u;
+    btot += wtot[k];
+  }
+  const uint32_t blk0 = (uint32_t)bex[blockIdx.x], blk1 = blk0 + btot;
+  const uint32_t base = blk0 + woff + incl - c;
+  if (i < n) off[i] = base;
+  const bool staged = btot <= (uint32_t)kEmitStage;
   if (i < n) {
     const ScanDesc &sd = T.s[T.of_gauss(i)];
-    const uint32_t base = off[i], b0 = (uint32_t)sd.b0;
+    const uint32_t b0 = (uint32_t)sd.b0;
     if (staged) {
       enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
         sbrick[base - blk0 + j] = b0 + brick;
@@ -327,7 +293,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const ScanTable T, float 
   }
   if (!staged) return;  // uniform per block
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kEmitThreads) {
+  for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kPrepThreads) {
     const int64_t slot = (int64_t)blk0 + k;
     if (slot < cap) {
       key_brick[slot] = sbrick[k];
@@ -339,11 +305,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const ScanTable T, float 
 hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
   if (T.n_total == 0) return hipSuccess;
   char *b = (char *)ws;
-  int blocks = (int)((T.n_total + kEmitThreads - 1) / kEmitThreads);
+  const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
   prof_begin(s);
-  k_emit<<<blocks, kEmitThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-                                (const uint32_t *)(b + L.off), L.cap, (const DevStatus *)(b + L.status),
-                                (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid));
+  k_emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+                                         (uint32_t *)(b + L.off), (const uint64_t *)(b + L.scan_tmp), L.cap,
+                                         (const DevStatus *)(b + L.status), (uint32_t *)(b + L.key_brick),
+                                         (uint32_t *)(b + L.key_gid));
   prof_end(s, "emit");
   return hipGetLastError();
 }

@@ -92,14 +92,13 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-// Scan tiling (exclusive scan of uint32 arrays).
-constexpr int kScanThreads = 512;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;
+// Gaussians per prep / emit block: the first level of the key-count scan.
+constexpr int kPrepThreads = 256;
 
 // Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
-//   off: uint32 [n + 1]: key counts per Gaussian, after the scan the first key slot of each Gaussian
-//        (keys are numbered Gaussian-major) and off[n] = the key count.
+//   off: uint32 [n + 1]: key counts per Gaussian, after the emit the first key slot of each
+//        Gaussian (keys are numbered Gaussian-major); off[n] = the key count.
+//   scan_tmp: per-block key totals of the count scan (uint64), later the radix digit totals.
 //   key_brick, key_gid: uint32 [cap] keys in slot order; keys_alt, vals_a, vals_b: radix ping-pong.
 //   list_gid, list_slot: uint32 [cap] the keys sorted by brick: Gaussian index and key slot.
 //   brick_off: uint32 [B + 1] brick list offsets.  partials: 48 B per key slot (backward; absent in a
