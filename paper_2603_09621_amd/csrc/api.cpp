@@ -320,7 +320,6 @@ size_t gs_loss_scratch_bytes(int64_t nvox) { return sizeof(float) * (size_t)std:
 static int bin_front(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
                      const WsLayout &L, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_reset(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "reset");
   if ((e = launch_prep_count(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
   if ((e = launch_scan_counts(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "scan_counts");
   return GS_OK;

@@ -16,29 +16,15 @@
 
 namespace gs {
 
-__global__ void k_reset(DevStatus *st) {
-  if (threadIdx.x == 0) {
-    st->n_keys = 0;
-    st->overflow = 0;
-    st->nonfinite = 0;
-  }
-}
-
-hipError_t launch_reset(void *ws, const WsLayout &L, hipStream_t s) {
-  prof_begin(s);
-  k_reset<<<1, 64, 0, s>>>((DevStatus *)((char *)ws + L.status));
-  prof_end(s, "reset");
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------------------------------------
 // Prep: (mu, s, q, A, r) -> evaluation and culling records (§3.1 parameters; §3.2 weight).  The
 // records are built by a device function shared by the fused prep + count kernel.
 
-__device__ __forceinline__ void make_records(int64_t i, const float *__restrict__ mu, const float *__restrict__ ls,
+// Returns false (and an empty record that yields no keys and no pairs) for a non-finite parameter,
+// a zero quaternion or r <= 0.
+__device__ __forceinline__ bool make_records(int64_t i, const float *__restrict__ mu, const float *__restrict__ ls,
                                              const float *__restrict__ quat, const float *__restrict__ amp,
-                                             const float *__restrict__ relax, float cutoff, EvalRec &e, CullRec &cr,
-                                             DevStatus *st) {
+                                             const float *__restrict__ relax, float cutoff, EvalRec &e, CullRec &cr) {
   float mx = mu[3 * i], my = mu[3 * i + 1], mz = mu[3 * i + 2];
   float s0 = ls[3 * i], s1 = ls[3 * i + 1], s2 = ls[3 * i + 2];
   float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
@@ -48,10 +34,9 @@ __device__ __forceinline__ void make_records(int64_t i, const float *__restrict_
   bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(s0) && isfinite(s1) && isfinite(s2) &&
             isfinite(qn2) && qn2 > 0.f && isfinite(A) && isfinite(r) && r > 0.f;
   if (!ok) {
-    atomicOr(&st->nonfinite, 1);
     e = EvalRec{make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
     cr = CullRec{make_float4(1, 1, 1, 0), make_float4(0, 0, 0, 0)};
-    return;
+    return false;
   }
   float qn = sqrtf(qn2);
   float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
@@ -74,6 +59,7 @@ __device__ __forceinline__ void make_records(int64_t i, const float *__restrict_
   e.r1 = make_float4(k * P[0][0], 2.f * k * P[0][1], 2.f * k * P[0][2], k * cutoff * cutoff + l2r);
   e.r2 = make_float4(k * P[1][1], 2.f * k * P[1][2], k * P[2][2], l2r);
   cr = CullRec{make_float4(S[0][0], S[1][1], S[2][2], S[0][1]), make_float4(S[0][2], S[1][2], 1.f, 0.f)};
+  return true;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -130,19 +116,22 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
 
 // Fused prep + count: records of Gaussian i (of the concatenated numbering; its parameters are
 // entry i - g0 of its scan's arrays), its key count cnt[i] and, per block of kPrepThreads
-// Gaussians, the block's key total bsum[block] (the first level of the count scan).
+// Gaussians, the block's key total bsum[block] (the first level of the count scan), with bit 63
+// set if the block holds an invalid Gaussian.
 __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, float cutoff,
                                                              EvalRec *__restrict__ er, CullRec *__restrict__ cr,
-                                                             uint32_t *__restrict__ cnt, uint64_t *__restrict__ bsum,
-                                                             DevStatus *st) {
+                                                             uint32_t *__restrict__ cnt, uint64_t *__restrict__ bsum) {
   __shared__ uint64_t wsum[kPrepThreads / 64];
+  __shared__ int sbad;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
   uint32_t c = 0;
   if (i < T.n_total) {
     const ScanDesc &sd = T.s[T.of_gauss(i)];
     EvalRec e;
     CullRec r;
-    make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, r, st);
+    if (!make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, r)) sbad = 1;
     er[i] = e;
     cr[i] = r;
     c = enumerate_bricks(sd.bg, e, r, cutoff, [](uint32_t, uint32_t) {});
@@ -156,7 +145,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, 
   if (threadIdx.x == 0) {
     uint64_t tot = 0;
     for (int w = 0; w < kPrepThreads / 64; ++w) tot += wsum[w];
-    bsum[blockIdx.x] = tot;
+    bsum[blockIdx.x] = tot | (sbad ? kBadBlock : 0ull);
   }
 }
 
@@ -166,16 +155,16 @@ hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const W
   if (blocks == 0) return hipSuccess;
   prof_begin(s);
   k_prep_count<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
-                                               (uint32_t *)(b + L.off), (uint64_t *)(b + L.scan_tmp),
-                                               (DevStatus *)(b + L.status));
+                                               (uint32_t *)(b + L.off), (uint64_t *)(b + L.scan_tmp));
   prof_end(s, "prep_count");
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
 // Second level of the count scan: one block turns the per-block key totals into exclusive block
-// offsets (64-bit, in place), stores the key count K in the status block with the overflow flag
-// (K > capacity) and writes off[n] = K.  Each thread scans a contiguous segment of the totals.
+// offsets (64-bit, in place) and writes the whole status block: the key count K, the overflow flag
+// (K > capacity) and the non-finite flag (any block flagged); and off[n] = K.  Each thread scans a
+// contiguous segment of the totals.
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 #pragma unroll
@@ -205,7 +194,13 @@ __global__ __launch_bounds__(kBlockScanThreads) void k_scan_blocks(uint64_t *__r
   const int64_t per = (nb + kBlockScanThreads - 1) / kBlockScanThreads;
   const int64_t s0 = min((int64_t)t * per, nb), s1 = min(s0 + per, nb);
   uint64_t local = 0;
-  for (int64_t k = s0; k < s1; ++k) local += bsum[k];
+  int bad = 0;
+  for (int64_t k = s0; k < s1; ++k) {
+    const uint64_t v = bsum[k];
+    bad |= (v & kBadBlock) ? 1 : 0;
+    local += v & ~kBadBlock;
+  }
+  bad = __syncthreads_or(bad);
   const uint64_t incl = wave_incl_scan64(local);
   if (lane_id() == 63) wsum[t >> 6] = incl;
   __syncthreads();
@@ -216,13 +211,14 @@ __global__ __launch_bounds__(kBlockScanThreads) void k_scan_blocks(uint64_t *__r
   }
   uint64_t run = woff + incl - local;
   for (int64_t k = s0; k < s1; ++k) {
-    const uint64_t v = bsum[k];
+    const uint64_t v = bsum[k] & ~kBadBlock;
     bsum[k] = run;
     run += v;
   }
   if (t == 0) {
     st->n_keys = (int64_t)total;
     st->overflow = (int64_t)total > cap ? 1 : 0;
+    st->nonfinite = bad;
     off[n] = (int64_t)total > cap ? (uint32_t)cap : (uint32_t)total;
   }
 }

@@ -92,8 +92,11 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-// Gaussians per prep / emit block: the first level of the key-count scan.
+// Gaussians per prep / emit block: the first level of the key-count scan.  A block's key total
+// carries kBadBlock when the block holds an invalid Gaussian (non-finite parameter, zero quaternion
+// or r <= 0).
 constexpr int kPrepThreads = 256;
+constexpr uint64_t kBadBlock = 1ull << 63;
 
 // Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
 //   off: uint32 [n + 1]: key counts per Gaussian, after the emit the first key slot of each
@@ -122,7 +125,6 @@ void prof_end(hipStream_t s, const char *name);
 
 // Kernel launchers (bin.hip, render.hip, reduce.hip, fit.hip).  Return hipGetLastError() of the
 // launches.  `g` / `st` hold the concatenated Gaussians of all scans of T.
-hipError_t launch_reset(void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
