@@ -120,10 +120,13 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
 // set if the block holds an invalid Gaussian.
 __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, float cutoff,
                                                              EvalRec *__restrict__ er, CullRec *__restrict__ cr,
-                                                             uint32_t *__restrict__ cnt, uint64_t *__restrict__ bsum) {
+                                                             uint32_t *__restrict__ cnt, uint64_t *__restrict__ bsum,
+                                                             uint32_t *__restrict__ hist, int64_t hist_len) {
   __shared__ uint64_t wsum[kPrepThreads / 64];
   __shared__ int sbad;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
+  // the first radix pass's histogram is accumulated by the emit kernel: clear it here
+  for (int64_t k = i; k < hist_len; k += (int64_t)gridDim.x * kPrepThreads) hist[k] = 0u;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   uint32_t c = 0;
@@ -155,7 +158,8 @@ hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const W
   if (blocks == 0) return hipSuccess;
   prof_begin(s);
   k_prep_count<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
-                                               (uint32_t *)(b + L.off), (uint64_t *)(b + L.scan_tmp));
+                                               (uint32_t *)(b + L.off), (uint64_t *)(b + L.scan_tmp),
+                                               (uint32_t *)(b + L.hist), (int64_t)kRadix * L.sort_blocks);
   prof_end(s, "prep_count");
   return hipGetLastError();
 }
@@ -246,9 +250,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
                                                        const CullRec *__restrict__ cr, uint32_t *__restrict__ off,
                                                        const uint64_t *__restrict__ bex, int64_t cap,
                                                        const DevStatus *st, uint32_t *__restrict__ key_brick,
-                                                       uint32_t *__restrict__ key_gid) {
+                                                       uint32_t *__restrict__ key_gid, uint32_t *__restrict__ hist,
+                                                       int ntiles) {
   __shared__ uint32_t sbrick[kEmitStage], sgid[kEmitStage];
   __shared__ uint32_t wtot[kPrepThreads / 64];
+  __shared__ uint32_t tcnt[2][kRadix];  // digit counts of the (at most two) sort tiles the range meets
   if (st->overflow) return;
   const int64_t n = T.n_total;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
@@ -283,18 +289,30 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
         if (slot < cap) {
           key_brick[slot] = b0 + brick;
           key_gid[slot] = (uint32_t)i;
+          atomicAdd(&hist[(int64_t)((b0 + brick) & (kRadix - 1)) * ntiles + slot / kSortTile], 1u);
         }
       });
     }
   }
   if (!staged) return;  // uniform per block
+  tcnt[0][threadIdx.x] = 0u;
+  tcnt[1][threadIdx.x] = 0u;
   __syncthreads();
+  const uint32_t tile0 = blk0 / kSortTile;
   for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kPrepThreads) {
     const int64_t slot = (int64_t)blk0 + k;
     if (slot < cap) {
-      key_brick[slot] = sbrick[k];
+      const uint32_t key = sbrick[k];
+      key_brick[slot] = key;
       key_gid[slot] = sgid[k];
+      atomicAdd(&tcnt[(uint32_t)(slot / kSortTile) - tile0][key & (kRadix - 1)], 1u);
     }
+  }
+  __syncthreads();
+  // integer sums: the histogram does not depend on the order of the additions
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t c = tcnt[q][threadIdx.x];
+    if (c) atomicAdd(&hist[(int64_t)threadIdx.x * ntiles + tile0 + q], c);
   }
 }
 
@@ -306,15 +324,15 @@ hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayou
   k_emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
                                          (uint32_t *)(b + L.off), (const uint64_t *)(b + L.scan_tmp), L.cap,
                                          (const DevStatus *)(b + L.status), (uint32_t *)(b + L.key_brick),
-                                         (uint32_t *)(b + L.key_gid));
+                                         (uint32_t *)(b + L.key_gid), (uint32_t *)(b + L.hist), L.sort_blocks);
   prof_end(s, "emit");
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
 // LSD radix sort of (brick id, slot) pairs, 8 bits per pass, stable.  Tiles of 4096 keys.
-//   hist:    per-tile digit counts, digit-major [256][tiles]; colscan: scanned along the tiles per
-//            digit, plus the digit totals.
+//   hist:    per-tile digit counts, digit-major [256][tiles] (for the first pass accumulated by the
+//            emit kernel); colscan: scanned along the tiles per digit, plus the digit totals.
 //   scatter: each wave ranks its 1024 consecutive keys in 16 rounds of 64 (rank among equal digits =
 //            wave ballots + a per-wave running count), the four waves' counts are combined into
 //            per-digit tile offsets, the tile is reordered by digit in LDS and written out in
@@ -518,9 +536,11 @@ hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStrea
       const bool last = p == L.sort_passes - 1;
       uint32_t *kout = (p & 1) ? ka : kb;
       uint32_t *vout = last ? (uint32_t *)(b + L.list_slot) : ((p & 1) ? vb : va);
-      prof_begin(s);
-      k_radix_hist<<<nt, kSortThreads, 0, s>>>(kin, st, L.cap, p * kRadixBits, hist, nt);
-      prof_end(s, "radix_hist");
+      if (p > 0) {  // the first pass's histogram was accumulated while the keys were emitted
+        prof_begin(s);
+        k_radix_hist<<<nt, kSortThreads, 0, s>>>(kin, st, L.cap, p * kRadixBits, hist, nt);
+        prof_end(s, "radix_hist");
+      }
       prof_begin(s);
       k_radix_colscan<<<kRadix, kSortThreads, 0, s>>>(hist, nt, dtot);
       prof_end(s, "radix_scan");
