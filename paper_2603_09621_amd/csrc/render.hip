@@ -12,7 +12,7 @@
 // S, denominator W).  The four groups' partial sums of a voxel are added in a fixed order at the end,
 // so the result is bitwise deterministic.
 //
-// Backward: two waves per brick, one Gaussian per lane.  The brick's per-voxel factors
+// Backward: one wave per brick, one Gaussian per lane.  The brick's per-voxel factors
 // c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by their
 // number of rows in the brick so that the lanes of a wave run the same number of iterations; each
 // lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
@@ -251,8 +251,8 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
-constexpr int kBwdThreads = 128;
-constexpr int kBwdWindow = 2048;  // keys ordered by work per pass over the brick list
+constexpr int kBwdThreads = 64;  // one wave per brick
+constexpr int kBwdWindow = 512;  // keys ordered by work per pass over the brick list
 constexpr int kBwdBuckets = 34;   // rows per key in a brick: 0 .. 32 (bucket 0 = 32 rows)
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
@@ -302,10 +302,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const uint32_t start = brick_off[b], end = brick_off[b + 1];
   if (FIT) {
-    // BX * 8 columns of 4 voxels, one per thread
+    // BX * 8 columns of 4 voxels, one per thread and pass
     float absd = 0.f;
-    if (t < BX * 8) {
-      const int lx = t % BX, ly = t / BX;
+    for (int col = t; col < BX * 8; col += kBwdThreads) {
+      const int lx = col % BX, ly = col / BX;
       const int gx = x0 + lx, gy = y0 + ly;
       float c4[4] = {0.f, 0.f, 0.f, 0.f}, i4[4] = {0.f, 0.f, 0.f, 0.f};
       if (gx < bg.nx && gy < bg.ny) {
@@ -316,22 +316,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
         const float lr = (((i4[0] + i4[1]) + i4[2]) + i4[3]) * 0.25f;
         const float d = lr - obs[sd.o0 + ((int64_t)(z0 >> 2) * bg.ny + gy) * bg.nx + gx];
         const float sg = d > 0.f ? sd.gscale : (d < 0.f ? -sd.gscale : 0.f);
-        absd = fabsf(d);
+        absd += fabsf(d);
 #pragma unroll
         for (int z = 0; z < 4; ++z) c4[z] = sg / (Wv[g0 + z * plane] + eps);
       }
 #pragma unroll
       for (int z = 0; z < 4; ++z) sCI[(z * 8 + ly) * RP + lx] = make_float2(c4[z], i4[z]);
     }
-    // the brick's loss sum: wave 0 reduces the first 64 columns, wave 1 the rest (if any); the two
-    // halves are added by thread 0 in a fixed order
+    // the brick's loss sum: each thread's columns in order, then a fixed-order wave reduction
     float wsum = absd;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) wsum += __shfl_down(wsum, d, 64);
-    __shared__ float swsum[2];
-    if (l == 0) swsum[w] = wsum;
     __syncthreads();
-    if (t == 0) loss_part[b] = swsum[0] + swsum[1];
+    if (t == 0) loss_part[b] = wsum;
   } else {
     if (start == end) return;
     // per voxel of the brick: c = dL/dI / (W + eps) and I; zero outside the grid, so that voxels
