@@ -341,6 +341,7 @@ def main():
         "fit_iters_per_s": 1.0 / t_step,
         "ms_per_step_hip_graph": ms_graph,
         "useful_pairs_per_step": U_step,
+        "keys_last_step": status["n_keys"],
         "wall_s_timed": wall,
         "loss_end": loss_end,
         "replay_identical": replay_same,
