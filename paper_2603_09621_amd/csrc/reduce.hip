@@ -71,23 +71,21 @@ __device__ __forceinline__ void block_partial_sums(int64_t i0, int64_t n, const 
 
 // Gradient of Gaussian i from its summed partials (a0, a1, a2) and its raw parameters.
 // g[0..2] = dmu, g[3..5] = dlog_scale, g[6..9] = dquat, g[10] = dA, g[11] = dr (r = 1 if relax NULL).
-__device__ __forceinline__ void gauss_grad(int64_t i, const float *__restrict__ quat, const float *__restrict__ ls,
-                                           const float *__restrict__ relax, float4 a0, float4 a1, float4 a2,
-                                           float g[12]) {
+__device__ __forceinline__ void gauss_grad_v(float qw, float qx, float qy, float qz, float s0, float s1, float s2,
+                                             float r, float4 a0, float4 a1, float4 a2, float g[12]) {
   const float sA = a0.x, sk = a0.y;
   const float kd[3] = {a0.z, a0.w, a1.x};
   // G = dL/dP = -1/2 M (symmetric)
   const float G[3][3] = {{-0.5f * a1.y, -0.5f * a2.x, -0.5f * a2.y},
                          {-0.5f * a2.x, -0.5f * a1.z, -0.5f * a2.z},
                          {-0.5f * a2.y, -0.5f * a2.z, -0.5f * a1.w}};
-  const float qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2], qz = quat[4 * i + 3];
   float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   if (!(qn > 0.f) || !isfinite(qn)) qn = 1.f;
   const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
   const float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
                          {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
                          {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-  const float D[3] = {expf(-2.f * ls[3 * i]), expf(-2.f * ls[3 * i + 1]), expf(-2.f * ls[3 * i + 2])};
+  const float D[3] = {expf(-2.f * s0), expf(-2.f * s1), expf(-2.f * s2)};
   float P[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -123,7 +121,16 @@ __device__ __forceinline__ void gauss_grad(int64_t i, const float *__restrict__ 
   g[8] = (gy - dot * y) / qn;
   g[9] = (gz - dot * z) / qn;
   g[10] = sA;
-  g[11] = relax ? sk / relax[i] : sk;
+  g[11] = sk / r;
+}
+
+// Gradient of Gaussian i from its summed partials and its raw parameters in global memory
+// (r = 1 when relax is NULL).
+__device__ __forceinline__ void gauss_grad(int64_t i, const float *__restrict__ quat, const float *__restrict__ ls,
+                                           const float *__restrict__ relax, float4 a0, float4 a1, float4 a2,
+                                           float g[12]) {
+  gauss_grad_v(quat[4 * i], quat[4 * i + 1], quat[4 * i + 2], quat[4 * i + 3], ls[3 * i], ls[3 * i + 1],
+               ls[3 * i + 2], relax ? relax[i] : 1.f, a0, a1, a2, g);
 }
 
 __global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const float *__restrict__ ls,
@@ -187,33 +194,71 @@ __global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ 
   if (st->overflow) return;
   __shared__ float4 sp[3 * kRedChunk];
   const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
+  // the Gaussian's parameters and moments do not depend on the partial sums: their loads are issued
+  // first, so that they overlap the partials' loads.  Entry e of the 12 is (group, component) in the
+  // order mu 3, log_scale 3, quat 4, amp, relax; its moment index is moff[e] (group layout).
+  const int ng = relax ? 12 : 11;
+  auto moff = [&](int e) -> int64_t {
+    return e < 3 ? 3 * i + e : e < 6 ? 3 * n + 3 * i + (e - 3) : e < 10 ? 6 * n + 4 * i + (e - 6)
+                                                                     : (e == 10 ? 10 * n + i : 11 * n + i);
+  };
+  float pv[12], mv[12], vv[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    pv[e] = 1.f;
+    mv[e] = 0.f;
+    vv[e] = 0.f;
+  }
+  if (i < n) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pv[a] = mu[3 * i + a];
+      pv[3 + a] = ls[3 * i + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pv[6 + a] = quat[4 * i + a];
+    pv[10] = amp[i];
+    if (relax) pv[11] = relax[i];
+#pragma unroll
+    for (int e = 0; e < 12; ++e)
+      if (e < ng) {
+        mv[e] = m[moff(e)];
+        vv[e] = v[moff(e)];
+      }
+  }
   float4 a0, a1, a2;
   block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
   if (i >= n) return;
   float g[12];
-  gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
+  gauss_grad_v(pv[6], pv[7], pv[8], pv[9], pv[3], pv[4], pv[5], pv[11], a0, a1, a2, g);
   const float t = (float)(step[T.of_gauss(i)] + 1);
   const float bc1 = -expm1f(t * h.lnb1), bc2 = -expm1f(t * h.lnb2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     d_mu[3 * i + a] = g[a];
     d_ls[3 * i + a] = g[3 + a];
-    adam_one(mu[3 * i + a], g[a], m[3 * i + a], v[3 * i + a], h.lr[0], h.b1, h.b2, h.eps, bc1, bc2);
-    adam_one(ls[3 * i + a], g[3 + a], m[3 * n + 3 * i + a], v[3 * n + 3 * i + a], h.lr[1], h.b1, h.b2, h.eps, bc1,
-             bc2);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    d_quat[4 * i + a] = g[6 + a];
-    adam_one(quat[4 * i + a], g[6 + a], m[6 * n + 4 * i + a], v[6 * n + 4 * i + a], h.lr[2], h.b1, h.b2, h.eps, bc1,
-             bc2);
-  }
+  for (int a = 0; a < 4; ++a) d_quat[4 * i + a] = g[6 + a];
   d_amp[i] = g[10];
-  adam_one(amp[i], g[10], m[10 * n + i], v[10 * n + i], h.lr[3], h.b1, h.b2, h.eps, bc1, bc2);
-  if (relax) {
-    if (d_relax) d_relax[i] = g[11];
-    adam_one(relax[i], g[11], m[11 * n + i], v[11 * n + i], h.lr[4], h.b1, h.b2, h.eps, bc1, bc2);
+  if (relax && d_relax) d_relax[i] = g[11];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    if (e >= ng) continue;
+    const int grp = e < 3 ? 0 : e < 6 ? 1 : e < 10 ? 2 : e == 10 ? 3 : 4;
+    adam_one(pv[e], g[e], mv[e], vv[e], h.lr[grp], h.b1, h.b2, h.eps, bc1, bc2);
+    m[moff(e)] = mv[e];
+    v[moff(e)] = vv[e];
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mu[3 * i + a] = pv[a];
+    ls[3 * i + a] = pv[3 + a];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) quat[4 * i + a] = pv[6 + a];
+  amp[i] = pv[10];
+  if (relax) relax[i] = pv[11];
 }
 
 // Fit-step epilogue, one block per scan: loss[s] = (sum of the scan's per-brick partial sums, fixed
