@@ -293,6 +293,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   __shared__ float2 sCI[32 * RP];
   __shared__ uint16_t sorder[kBwdWindow];
   __shared__ uint8_t sbucket[kBwdWindow];
+  __shared__ uint16_t sbox[kBwdWindow];  // key's row box in the brick: yl, yh (3 bits), zl, zh (2 bits), empty
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   const int64_t b = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_brick(b)];
@@ -360,12 +361,17 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     for (int j = t; j < L; j += kBwdThreads) {
       const uint32_t gid = list_gid[w0 + j];
       int bk = kBwdBuckets - 1;
+      uint16_t box = 1u << 10;  // empty
       if (gid < T.n_total) {
         int xl, xh, yl, yh, zl, zh;
         key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
-        if (xl <= xh && yl <= yh && zl <= zh) bk = 32 - (yh - yl + 1) * (zh - zl + 1);
+        if (xl <= xh && yl <= yh && zl <= zh) {
+          bk = 32 - (yh - yl + 1) * (zh - zl + 1);
+          box = (uint16_t)((yl - y0) | ((yh - y0) << 3) | ((zl - z0) << 6) | ((zh - z0) << 8));
+        }
       }
       sbucket[j] = (uint8_t)bk;
+      sbox[j] = box;
       atomicAdd(&bcount[bk], 1u);
     }
     __syncthreads();
@@ -382,21 +388,22 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     for (int c0 = w * 64; c0 < L; c0 += kBwdThreads) {
       const int p = c0 + l;
       if (p >= L) continue;
-      const uint32_t k = w0 + sorder[p];
+      const int jj = sorder[p];
+      const uint32_t k = w0 + jj;
       const uint32_t gid = list_gid[k];
       const uint32_t slot = list_slot[k];
       if (gid >= T.n_total || (int64_t)slot >= cap) continue;
       const EvalRec R = er[gid];
-      const CullRec C = cr[gid];
       const float mx = R.r0.x, A = R.r0.w;
       const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
-      int xl, xh, yl, yh, zl, zh;
-      key_box(bg, R, C, cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+      const uint32_t box = sbox[jj];
+      const int yl = y0 + (box & 7), yh = y0 + ((box >> 3) & 7), zl = z0 + ((box >> 6) & 3),
+                zh = z0 + ((box >> 8) & 3);
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
       const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
       const int ny_k = yh - yl + 1;
-      const int nrows = (xl <= xh && yl <= yh && zl <= zh) ? ny_k * (zh - zl + 1) : 0;
+      const int nrows = (box >> 10) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
       for (int r = 0; r < nrows; ++r) {
         const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
