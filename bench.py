@@ -198,7 +198,7 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    gs.gs_status(bins)
+    keys_warm = gs.gs_status(bins)["n_keys"]
     torch.cuda.synchronize()
     snap = {k: getattr(g, k).clone() for k in gs.GROUPS if getattr(g, k) is not None}
     snap_m, snap_v, snap_step = st.m.clone(), st.v.clone(), st.step.clone()
@@ -341,6 +341,7 @@ def main():
         "fit_iters_per_s": 1.0 / t_step,
         "ms_per_step_hip_graph": ms_graph,
         "useful_pairs_per_step": U_step,
+        "keys_last_warmup_step": keys_warm,
         "keys_last_step": status["n_keys"],
         "wall_s_timed": wall,
         "loss_end": loss_end,
