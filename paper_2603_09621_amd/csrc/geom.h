@@ -15,27 +15,45 @@ __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) -
 // Sigma2 = [[saa, sab], [sab, sbb]]) restricted to the slab b in [lo_b, hi_b] (world units).
 // For fixed offset d_b the a-offsets span (sab / sbb) d_b +- sqrt((c^2 - d_b^2 / sbb) (saa - sab^2 / sbb));
 // the upper end is concave in d_b with its maximum at d_b* = c sab / sqrt(saa), so over an interval
-// it peaks at d_b* clamped to the interval (likewise for the lower end at -d_b*).  Returns false if
-// the slab misses the ellipsoid.  Bounds are widened by `tol` (world units), which covers the
-// hardware reciprocal and square-root approximations used here (these ranges only cull).
+// it peaks at d_b* clamped to the interval (likewise for the lower end at -d_b*).  The slab misses
+// the ellipsoid if the clamped interval is empty.  Bounds are widened by `tol` (world units), which
+// covers the hardware reciprocal and square-root approximations used here (these ranges only cull).
+//
+// SlabAxes holds the slab-independent part for one (a, b) pair, so that several slabs of the same
+// pair share it; slab_extent is branch-free and returns whether the slab meets the ellipsoid
+// (amin/amax are meaningless otherwise).
+struct SlabAxes {
+  float isbb, eb, slope, schur, dstar;
+};
+
+__device__ __forceinline__ SlabAxes slab_axes(float saa, float sbb, float sab, float c) {
+  SlabAxes k;
+  k.isbb = __builtin_amdgcn_rcpf(sbb);
+  k.eb = c * __builtin_amdgcn_sqrtf(sbb);
+  k.slope = sab * k.isbb;
+  k.schur = fmaxf(saa - sab * k.slope, 0.f);
+  k.dstar = c * sab * __builtin_amdgcn_rsqf(saa);
+  return k;
+}
+
+__device__ __forceinline__ bool slab_extent(const SlabAxes &k, float ma, float mb, float c, float lo_b, float hi_b,
+                                            float tol, float &amin, float &amax) {
+  const float d0 = fmaxf(lo_b - mb, -k.eb - tol);
+  const float d1 = fminf(hi_b - mb, k.eb + tol);
+  const float dm = fminf(fmaxf(k.dstar, d0), d1);
+  const float dn = fminf(fmaxf(-k.dstar, d0), d1);
+  const float c2 = c * c;
+  const float hm = __builtin_amdgcn_sqrtf(fmaxf(c2 - dm * dm * k.isbb, 0.f) * k.schur);
+  const float hn = __builtin_amdgcn_sqrtf(fmaxf(c2 - dn * dn * k.isbb, 0.f) * k.schur);
+  amax = ma + k.slope * dm + hm + tol;
+  amin = ma + k.slope * dn - hn - tol;
+  return d0 <= d1;
+}
+
 __device__ __forceinline__ bool extent_in_slab(float ma, float mb, float saa, float sbb, float sab, float c, float lo_b,
                                                float hi_b, float tol, float &amin, float &amax) {
-  const float isbb = __builtin_amdgcn_rcpf(sbb);
-  const float eb = c * __builtin_amdgcn_sqrtf(sbb);
-  const float d0 = fmaxf(lo_b - mb, -eb - tol);
-  const float d1 = fminf(hi_b - mb, eb + tol);
-  if (d0 > d1) return false;
-  const float slope = sab * isbb;
-  const float schur = fmaxf(saa - sab * slope, 0.f);
-  const float dstar = c * sab * __builtin_amdgcn_rsqf(saa);
-  const float dm = fminf(fmaxf(dstar, d0), d1);
-  const float dn = fminf(fmaxf(-dstar, d0), d1);
-  const float c2 = c * c;
-  const float hm = __builtin_amdgcn_sqrtf(fmaxf(c2 - dm * dm * isbb, 0.f) * schur);
-  const float hn = __builtin_amdgcn_sqrtf(fmaxf(c2 - dn * dn * isbb, 0.f) * schur);
-  amax = ma + slope * dm + hm + tol;
-  amin = ma + slope * dn - hn - tol;
-  return true;
+  const SlabAxes k = slab_axes(saa, sbb, sab, c);
+  return slab_extent(k, ma, mb, c, lo_b, hi_b, tol, amin, amax);
 }
 
 // World range [lo, hi] -> inclusive voxel index range on an axis of n voxels (origin o, inverse

@@ -3,14 +3,15 @@
 // Bricks are BX x 8 x 4 voxels (BX in {4, 8, 16}; the paper uses 8 x 8 x 4).  Every launch covers
 // the bricks of all scans of a scan table (one workgroup per brick).
 //
-// Forward: BX/2 waves per brick; each wave owns a 4x4x4 quarter of the brick.  The brick's Gaussian
-// list is staged through LDS in chunks; while staging, each Gaussian is tested against the quarters
-// and every wave compacts the indices of the Gaussians that may touch its quarter.  A wave keeps four
-// Gaussians in flight: lanes 16g..16g+15 (group g) take list entries g, g+4, g+8, ...; each lane owns
-// one voxel row of 4 voxels along x, sets up the row's quadratic once per Gaussian and evaluates the 4
-// voxels by Horner's rule, the inclusive cutoff test, one exp2 and the two accumulations (numerator
-// S, denominator W).  The four groups' partial sums of a voxel are added in a fixed order at the end,
-// so the result is bitwise deterministic.
+// Forward: BX/2 waves per brick; each wave owns a 4x4x4 quarter of the brick, split into four
+// 4x2x2 cells.  The brick's Gaussian list is staged through LDS in chunks; while staging, each
+// Gaussian is tested against every cell and each wave compacts, per cell of its quarter, the
+// Gaussians that may touch the cell.  A 16-lane group works on one cell and keeps four Gaussians in
+// flight: lanes 4j..4j+3 of the group take entries j, j+4, j+8, ... of the cell's list; each lane owns
+// one voxel row of 4 voxels along x, sets up the row's quadratic once per Gaussian and evaluates the
+// 4 voxels by Horner's rule, the inclusive cutoff test, one exp2 and the two accumulations
+// (numerator S, denominator W).  The four slots' partial sums of a voxel are added in a fixed order
+// at the end, so the result is bitwise deterministic.
 //
 // Backward: one wave per brick, one Gaussian per lane.  The brick's per-voxel factors
 // c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by their
@@ -30,42 +31,58 @@
 
 namespace gs {
 
-// Conservative test of one Gaussian against the quarters of a BX x 8 x 4 brick (quarter index
-// sx + (BX/4) sy).  Uses the ellipsoid's x/y extents inside the brick's z-slab and inside each
-// quarter column's x- or y-slab.
+// v of the lane N places along inside the lane's 16-lane DPP row (rotation).
+template <int N>
+__device__ __forceinline__ float dpp_row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xF, 0xF, false));
+}
+
+// Conservative test of one Gaussian against the 4x2x2-voxel cells of a BX x 8 x 4 brick.  Bit
+// 4 q + c of the result is cell c = cy + 2 cz (cy, cz in {0, 1}) of quarter q = sx + (BX/4) sy, the
+// cell spanning x in [x0 + 4 sx, +3], y in [y0 + 4 sy + 2 cy, +1], z in [z0 + 2 cz, +1].  Per z-pair
+// slab the ellipsoid's x- and y-extents are taken (exact for the slab); a cell passes if a voxel
+// centre of its x-range lies in the x-extent and a voxel centre of its y-range in the y-extent of its
+// z-slab.  A voxel centre within the ellipsoid lies in the extents of the slab that contains it, so
+// a cell holding a pair with d^2 <= 9 always passes.  (Adding the x-y coupling, i.e. the y-extent
+// inside each x-slab, culls a few more cells but costs more than it saves.)
 template <int BX>
-__device__ __forceinline__ uint32_t quarter_mask(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
-                                                 int x0, int y0, int z0) {
+__device__ __forceinline__ uint32_t cell_mask(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
+                                              int x0, int y0, int z0) {
   constexpr int NQX = BX / 4;
   if (c.c1.z == 0.f) return 0u;
   const float mx = e.r0.x, my = e.r0.y, mz = e.r0.z;
-  const float sxx = c.c0.x, syy = c.c0.y, szz = c.c0.z, sxy = c.c0.w, sxz = c.c1.x, syz = c.c1.y;
+  const float sxx = c.c0.x, syy = c.c0.y, szz = c.c0.z, sxz = c.c1.x, syz = c.c1.y;
+  const SlabAxes kxz = slab_axes(sxx, szz, sxz, cutoff), kyz = slab_axes(syy, szz, syz, cutoff);
   const float tx = extent_tol(mx, cutoff * __builtin_amdgcn_sqrtf(sxx), bg.hx),
               ty = extent_tol(my, cutoff * __builtin_amdgcn_sqrtf(syy), bg.hy);
-  const float Z0 = centre(bg.oz, bg.hz, z0), Z1 = centre(bg.oz, bg.hz, z0 + 3);
-  float xzl, xzh, yzl, yzh;
-  if (!extent_in_slab(mx, mz, sxx, szz, sxz, cutoff, Z0, Z1, tx, xzl, xzh)) return 0u;
-  if (!extent_in_slab(my, mz, syy, szz, syz, cutoff, Z0, Z1, ty, yzl, yzh)) return 0u;
-  float Y0[2], Y1[2], xyl[2], xyh[2];
-  bool okxy[2];
+  // x index range and y extent inside each z-pair slab
+  int ixl[2], ixh[2];
+  float yzl[2], yzh[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    Y0[h] = centre(bg.oy, bg.hy, y0 + 4 * h);
-    Y1[h] = centre(bg.oy, bg.hy, y0 + 4 * h + 3);
-    okxy[h] = extent_in_slab(mx, my, sxx, syy, sxy, cutoff, Y0[h], Y1[h], tx, xyl[h], xyh[h]);
+    const float Z0 = centre(bg.oz, bg.hz, z0 + 2 * h), Z1 = centre(bg.oz, bg.hz, z0 + 2 * h + 1);
+    float xl, xh;
+    const bool ok = slab_extent(kxz, mx, mz, cutoff, Z0, Z1, tx, xl, xh) &
+                    slab_extent(kyz, my, mz, cutoff, Z0, Z1, ty, yzl[h], yzh[h]);
+    world_to_index(xl, xh, bg.ox, bg.ihx, bg.nx, ixl[h], ixh[h]);
+    if (!ok) {
+      ixl[h] = 1;
+      ixh[h] = 0;
+    }
   }
   uint32_t m = 0;
 #pragma unroll
-  for (int sx = 0; sx < NQX; ++sx) {
-    const float X0 = centre(bg.ox, bg.hx, x0 + 4 * sx), X1 = centre(bg.ox, bg.hx, x0 + 4 * sx + 3);
-    float yxl, yxh;
-    if (!extent_in_slab(my, mx, syy, sxx, sxy, cutoff, X0, X1, ty, yxl, yxh)) continue;
-    const float yl = fmaxf(yzl, yxl), yh = fminf(yzh, yxh);
+  for (int h = 0; h < 2; ++h) {
+    int iyl, iyh;
+    world_to_index(yzl[h], yzh[h], bg.oy, bg.ihy, bg.ny, iyl, iyh);
+    const int pl = max(iyl - y0, 0) >> 1, ph = min(iyh - y0, 7) >> 1;
+    const uint32_t pm0 = (iyl <= iyh && pl <= ph) ? (2u << ph) - (1u << pl) : 0u;
 #pragma unroll
-    for (int sy = 0; sy < 2; ++sy) {
-      if (!okxy[sy]) continue;
-      const float xl = fmaxf(xzl, xyl[sy]), xh = fminf(xzh, xyh[sy]);
-      if (xl <= X1 && xh >= X0 && yl <= Y1[sy] && yh >= Y0[sy]) m |= 1u << (sx + NQX * sy);
+    for (int sx = 0; sx < NQX; ++sx) {
+      const int xa = x0 + 4 * sx;
+      const bool xin = ixl[h] <= ixh[h] && ixl[h] <= xa + 3 && ixh[h] >= xa;
+      const uint32_t pm = xin ? pm0 : 0u;
+      m |= ((pm & 3u) << (4 * sx + 2 * h)) | ((pm >> 2) << (4 * (sx + NQX) + 2 * h));
     }
   }
   return m;
@@ -87,13 +104,12 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
                                                  unsigned long long *__restrict__ pair_count) {
   constexpr int NT = 32 * BX, NW = BX / 2, NQX = BX / 4;
   if (st->overflow) return;
-  // srec[NT] is an empty record (threshold +inf: never a pair) that pads the wave lists to a
-  // multiple of 4; the lists hold byte offsets into srec
+  // srec[NT] is an empty record (threshold +inf: never a pair) that pads the cell lists; the lists
+  // hold byte offsets into srec
   __shared__ EvalRec srec[NT + 1];
-  __shared__ uint8_t smask[NT];
-  __shared__ uint16_t wlist[NW][NT + 4];
+  __shared__ uint32_t smask[NT];
+  __shared__ uint16_t wlist[NW][4][NT + 4];
   constexpr uint16_t kPad = (uint16_t)(NT * sizeof(EvalRec));
-  __shared__ float4 sred[NW][4][16][2];
   __shared__ unsigned long long scount[NW];
 
   const int64_t b = blockIdx.x;
@@ -101,11 +117,13 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
   const BrickGrid &bg = sd.bg;
   int x0, y0, z0;
   brick_coords(bg, b - sd.b0, x0, y0, z0);
+  // wave w owns quarter w; its lane l = 16 g + 4 j + r works on cell g of the quarter (cy = g & 1,
+  // cz = g >> 1), Gaussian slot j of the four in flight, and row r of the cell (ry = r & 1, rz = r >> 1)
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int grp = l >> 4, row = l & 15;
+  const int grp = l >> 4, sub = (l >> 2) & 3, r = l & 3;
   const int qx0 = x0 + (w % NQX) * 4;
-  const int iy = y0 + (w / NQX) * 4 + (row & 3);
-  const int iz = z0 + (row >> 2);
+  const int iy = y0 + (w / NQX) * 4 + 2 * (grp & 1) + (r & 1);
+  const int iz = z0 + 2 * (grp >> 1) + (r >> 1);
   const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
   float px[4];
 #pragma unroll
@@ -129,23 +147,34 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
         const EvalRec e = er[gid];
         const CullRec c = cr[gid];
         srec[t] = e;
-        smask[t] = (uint8_t)quarter_mask<BX>(bg, e, c, cutoff, x0, y0, z0);
+        smask[t] = cell_mask<BX>(bg, e, c, cutoff, x0, y0, z0);
       } else {
-        smask[t] = 0;
+        smask[t] = 0u;
       }
     }
     __syncthreads();
-    int nw = 0;
+    // the wave's four cell lists, compacted in list order
+    int n[4] = {0, 0, 0, 0};
     for (int j0 = 0; j0 < cnt; j0 += 64) {
-      const bool has = (j0 + l < cnt) && ((smask[j0 + l] >> w) & 1);
-      const uint64_t bal = __ballot(has);
-      if (has) wlist[w][nw + __popcll(bal & lt)] = (uint16_t)((j0 + l) * sizeof(EvalRec));
-      nw += __popcll(bal);
+      const int j = j0 + l;
+      const uint32_t qm = j < cnt ? (smask[j] >> (4 * w)) & 15u : 0u;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const bool has = (qm >> g) & 1u;
+        const uint64_t bal = __ballot(has);
+        if (has) wlist[w][g][n[g] + __popcll(bal & lt)] = (uint16_t)(j * sizeof(EvalRec));
+        n[g] += __popcll(bal);
+      }
     }
-    if (l < 4) wlist[w][nw + l] = kPad;
+    // every list padded with the empty record to the longest one, rounded up to a multiple of 4
+    const int n4 = (max(max(n[0], n[1]), max(n[2], n[3])) + 3) & ~3;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      for (int k = n[g] + l; k < n4; k += 64) wlist[w][g][k] = kPad;
     __syncthreads();
-    for (int j0 = 0; j0 < nw; j0 += 4) {
-      const EvalRec R = *reinterpret_cast<const EvalRec *>(reinterpret_cast<const char *>(srec) + wlist[w][j0 + grp]);
+    const uint16_t *mylist = wlist[w][grp];
+    for (int j0 = 0; j0 < n4; j0 += 4) {
+      const EvalRec R = *reinterpret_cast<const EvalRec *>(reinterpret_cast<const char *>(srec) + mylist[j0 + sub]);
       const float thr = R.r1.w;
       float dy, dz, bq, cq;
       row_coeffs(R, py, pz, dy, dz, bq, cq);
@@ -178,31 +207,25 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
     }
     return;
   }
-  sred[w][grp][row][0] = make_float4(Wa[0], Wa[1], Wa[2], Wa[3]);
-  sred[w][grp][row][1] = make_float4(Sa[0], Sa[1], Sa[2], Sa[3]);
-  __syncthreads();
-  if (grp == 0 && rowin) {
-    float4 Wt = sred[w][0][row][0], St = sred[w][0][row][1];
+  // the four slots' partial sums of each voxel of a row: rotations by 4 and then 8 lanes inside the
+  // group's 16-lane DPP row add the slots in a fixed order per lane; lane j of the row then produces
+  // voxel j (every voxel always comes from the same lane and the same order)
 #pragma unroll
-    for (int g2 = 1; g2 < 4; ++g2) {
-      const float4 a = sred[w][g2][row][0], s2 = sred[w][g2][row][1];
-      Wt.x += a.x; Wt.y += a.y; Wt.z += a.z; Wt.w += a.w;
-      St.x += s2.x; St.y += s2.y; St.z += s2.z; St.w += s2.w;
-    }
-    const float4 It = make_float4(St.x / (Wt.x + eps), St.y / (Wt.y + eps), St.z / (Wt.z + eps), St.w / (Wt.w + eps));
-    const int64_t v0 = sd.v0 + ((int64_t)iz * bg.ny + iy) * bg.nx + qx0;
-    if ((bg.nx & 3) == 0 && (sd.v0 & 3) == 0 && qx0 + 3 < bg.nx) {
-      *reinterpret_cast<float4 *>(I + v0) = It;
-      if (W) *reinterpret_cast<float4 *>(W + v0) = Wt;
-    } else {
-      const float iv[4] = {It.x, It.y, It.z, It.w}, wv[4] = {Wt.x, Wt.y, Wt.z, Wt.w};
+  for (int k = 0; k < 4; ++k) {
+    Wa[k] += dpp_row_ror<4>(Wa[k]);
+    Sa[k] += dpp_row_ror<4>(Sa[k]);
+  }
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (qx0 + k < bg.nx) {
-          I[v0 + k] = iv[k];
-          if (W) W[v0 + k] = wv[k];
-        }
-    }
+  for (int k = 0; k < 4; ++k) {
+    Wa[k] += dpp_row_ror<8>(Wa[k]);
+    Sa[k] += dpp_row_ror<8>(Sa[k]);
+  }
+  const float Wv = sub == 0 ? Wa[0] : (sub == 1 ? Wa[1] : (sub == 2 ? Wa[2] : Wa[3]));
+  const float Sv = sub == 0 ? Sa[0] : (sub == 1 ? Sa[1] : (sub == 2 ? Sa[2] : Sa[3]));
+  if (rowin && qx0 + sub < bg.nx) {
+    const int64_t v = sd.v0 + ((int64_t)iz * bg.ny + iy) * bg.nx + qx0 + sub;
+    I[v] = Sv / (Wv + eps);
+    if (W) W[v] = Wv;
   }
 }
 
