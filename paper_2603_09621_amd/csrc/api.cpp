@@ -186,7 +186,7 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
   if ((rc = check_opts(opts))) return rc;
   std::memset(T, 0, sizeof *T);
   T->ns = bt->ns;
-  int64_t g0 = 0, b0 = 0, v0 = 0, o0 = 0;
+  int64_t g0 = 0, b0 = 0, p0 = 0, v0 = 0, o0 = 0;
   for (int k = 0; k < bt->ns; ++k) {
     const gs_grid_t *gr = &bt->grid[k];
     if ((rc = check_grid(gr))) return rc;
@@ -198,6 +198,7 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
     sd.g0 = g0;
     sd.n = bt->n[k];
     sd.b0 = b0;
+    sd.p0 = p0;
     sd.v0 = v0;
     sd.o0 = o0;
     const int64_t nvox = (int64_t)gr->nx * gr->ny * gr->nz;
@@ -209,10 +210,12 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
     }
     g0 += bt->n[k];
     b0 += sd.bg.nbricks;
+    p0 += (sd.bg.nbricks + 1) / 2;
     v0 += nvox;
   }
   T->n_total = g0;
   T->nbricks_total = b0;
+  T->npairs_total = p0;
   if (g0 >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "total Gaussian count must be < 2^31");
   if (b0 >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
   if (v0 > ((int64_t)1 << 40)) return fail(GS_ERR_INVALID_ARG, "batch volumes too large");

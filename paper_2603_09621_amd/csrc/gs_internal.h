@@ -60,6 +60,7 @@ struct ScanDesc {
   const float *mu, *ls, *quat, *amp, *relax;
   int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated numbering
   int64_t b0;     // first (global) brick of the scan
+  int64_t p0;     // first (global) brick pair of the scan (the backward takes two bricks per wave)
   int64_t v0;     // first voxel of the scan's volume in the concatenated volumes
   int64_t o0;     // first LR voxel of the scan's observation in the concatenated observations
   float gscale;   // fit loss: dL/dI magnitude 1 / (zdown * nLR)
@@ -68,7 +69,7 @@ struct ScanDesc {
 
 struct ScanTable {
   int32_t ns;
-  int64_t n_total, nbricks_total;
+  int64_t n_total, nbricks_total, npairs_total;
   ScanDesc s[kMaxScans];
   __host__ __device__ __forceinline__ int of_gauss(int64_t i) const {
     int k = 0;
@@ -78,6 +79,11 @@ struct ScanTable {
   __host__ __device__ __forceinline__ int of_brick(int64_t b) const {
     int k = 0;
     while (k + 1 < ns && b >= s[k + 1].b0) ++k;
+    return k;
+  }
+  __host__ __device__ __forceinline__ int of_pair(int64_t q) const {
+    int k = 0;
+    while (k + 1 < ns && q >= s[k + 1].p0) ++k;
     return k;
   }
 };

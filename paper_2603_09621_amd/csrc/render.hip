@@ -13,15 +13,16 @@
 // (numerator S, denominator W).  The four slots' partial sums of a voxel are added in a fixed order
 // at the end, so the result is bitwise deterministic.
 //
-// Backward: one wave per brick, one Gaussian per lane.  The brick's per-voxel factors
-// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the brick's keys are ordered by their
-// number of rows in the brick so that the lanes of a wave run the same number of iterations; each
-// lane walks the rows of its Gaussian's box inside the brick in one flat loop, skips rows whose
-// maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and accumulates per
-// row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w, folded with the row's
-// (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.  The sums of each
-// (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel reduces each
-// Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
+// Backward: one wave per pair of neighbouring bricks, one Gaussian (key) per lane.  The bricks'
+// per-voxel factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of both
+// bricks are ordered together by their number of rows in their brick so that the lanes of a wave run
+// similar numbers of iterations (a pair gives the ordering twice as many keys to balance as one
+// brick); each lane walks the rows of its Gaussian's box inside its brick in one flat loop, skips
+// rows whose maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and
+// accumulates per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
+// folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.
+// The sums of each (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel
+// reduces each Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -274,9 +275,10 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
-constexpr int kBwdThreads = 64;  // one wave per brick
-constexpr int kBwdWindow = 512;  // keys ordered by work per pass over the brick list
-constexpr int kBwdBuckets = 34;   // rows per key in a brick: 0 .. 32 (bucket 0 = 32 rows)
+constexpr int kBwdThreads = 64;  // one wave per pair of bricks
+constexpr int kBwdBricks = 2;    // bricks b, b + 1 of a scan per wave: one ordering over both lists
+constexpr int kBwdWindow = 512;  // keys ordered by work per pass over the pair's lists
+constexpr int kBwdBuckets = 34;  // rows per key in its brick: 32 .. 0 (bucket 0 = 32 rows), then empty
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
 __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
@@ -302,29 +304,12 @@ __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, c
 // order), dL/dI = sign(LR - obs) * gscale on the column's 4 voxels, and the brick's sum of |LR - obs|
 // goes to loss_part[brick] (also for bricks without Gaussians).  Otherwise dL/dI is read from gI.
 template <int BX, bool FIT>
-__global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cutoff, float eps,
-                                                     const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
-                                                     const uint32_t *__restrict__ list_gid,
-                                                     const uint32_t *__restrict__ list_slot,
-                                                     const uint32_t *__restrict__ brick_off, const DevStatus *st,
-                                                     const float *__restrict__ Iv, const float *__restrict__ Wv,
-                                                     const float *__restrict__ gI, const float *__restrict__ obs,
-                                                     float *__restrict__ loss_part, int64_t cap,
-                                                     float4 *__restrict__ part) {
-  constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
-  if (st->overflow) return;
-  __shared__ float2 sCI[32 * RP];
-  __shared__ uint16_t sorder[kBwdWindow];
-  __shared__ uint8_t sbucket[kBwdWindow];
-  __shared__ uint16_t sbox[kBwdWindow];  // key's row box in the brick: yl, yh (3 bits), zl, zh (2 bits), empty
-  __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
-  const int64_t b = blockIdx.x;
-  const ScanDesc &sd = T.s[T.of_brick(b)];
+__device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0, int y0, int z0, int t,
+                                          const float *__restrict__ Iv, const float *__restrict__ Wv,
+                                          const float *__restrict__ gI, const float *__restrict__ obs, float eps,
+                                          float *__restrict__ loss_part, float2 *sCI) {
+  constexpr int RP = BX + 1;
   const BrickGrid &bg = sd.bg;
-  int x0, y0, z0;
-  brick_coords(bg, b - sd.b0, x0, y0, z0);
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const uint32_t start = brick_off[b], end = brick_off[b + 1];
   if (FIT) {
     // BX * 8 columns of 4 voxels, one per thread and pass
     float absd = 0.f;
@@ -351,10 +336,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     float wsum = absd;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) wsum += __shfl_down(wsum, d, 64);
-    __syncthreads();
     if (t == 0) loss_part[b] = wsum;
   } else {
-    if (start == end) return;
     // per voxel of the brick: c = dL/dI / (W + eps) and I; zero outside the grid, so that voxels
     // beyond the grid's edge contribute nothing
     for (int v = t; v < BX * 32; v += kBwdThreads) {
@@ -369,28 +352,73 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       sCI[(lz * 8 + ly) * RP + lx] = make_float2(c, iv);
     }
   }
+}
+
+template <int BX, bool FIT>
+__global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cutoff, float eps,
+                                                     const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
+                                                     const uint32_t *__restrict__ list_gid,
+                                                     const uint32_t *__restrict__ list_slot,
+                                                     const uint32_t *__restrict__ brick_off, const DevStatus *st,
+                                                     const float *__restrict__ Iv, const float *__restrict__ Wv,
+                                                     const float *__restrict__ gI, const float *__restrict__ obs,
+                                                     float *__restrict__ loss_part, int64_t cap,
+                                                     float4 *__restrict__ part) {
+  constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
+  // LDS voxels per brick, padded so that the same row of the two bricks falls into different banks
+  // (keys of similar boxes in both bricks read the same row index at the same time)
+  constexpr int BV = 32 * RP + 8;
+  if (st->overflow) return;
+  __shared__ float2 sCI[kBwdBricks * BV];
+  __shared__ uint16_t sorder[kBwdWindow];
+  __shared__ uint8_t sbucket[kBwdWindow];
+  // key's row box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the pair (bit 10),
+  // empty (bit 11)
+  __shared__ uint16_t sbox[kBwdWindow];
+  __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
+  const int64_t q = blockIdx.x;
+  const ScanDesc &sd = T.s[T.of_pair(q)];
+  const BrickGrid &bg = sd.bg;
+  const int64_t lb = 2 * (q - sd.p0);  // the pair's first brick, scan-local
+  const int nbk = bg.nbricks - lb >= 2 ? 2 : 1;
+  const int64_t b = sd.b0 + lb;
+  int x0[2], y0[2], z0[2];
+  brick_coords(bg, lb, x0[0], y0[0], z0[0]);
+  brick_coords(bg, lb + nbk - 1, x0[1], y0[1], z0[1]);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const uint32_t start = brick_off[b], mid = brick_off[b + 1], end = brick_off[b + nbk];
+  if (FIT || start != end) {
+    bwd_stage<BX, FIT>(sd, b, x0[0], y0[0], z0[0], t, Iv, Wv, gI, obs, eps, loss_part, sCI);
+    if (nbk == 2) bwd_stage<BX, FIT>(sd, b + 1, x0[1], y0[1], z0[1], t, Iv, Wv, gI, obs, eps, loss_part, sCI + BV);
+  }
+  __syncthreads();
   if (start == end) return;
-  float px[BX];
+  int xe[2], ye[2], ze[2];
 #pragma unroll
-  for (int k = 0; k < BX; ++k) px[k] = centre(bg.ox, bg.hx, x0 + k);
-  const int xe = min(x0 + BX - 1, bg.nx - 1), ye = min(y0 + 7, bg.ny - 1), ze = min(z0 + 3, bg.nz - 1);
+  for (int j = 0; j < 2; ++j) {
+    xe[j] = min(x0[j] + BX - 1, bg.nx - 1);
+    ye[j] = min(y0[j] + 7, bg.ny - 1);
+    ze[j] = min(z0[j] + 3, bg.nz - 1);
+  }
   for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
     const int L = (int)min((uint32_t)kBwdWindow, end - w0);
-    // order the window's keys by their number of rows in the brick, most first, so that the lanes of
-    // a wave run the same number of row iterations (each key's result is independent of where it
-    // runs, so the order does not change any result)
+    // order the window's keys (of both bricks) by their number of rows in their brick, most first,
+    // so that the lanes of a wave run the same number of row iterations (each key's result is
+    // independent of where it runs, so the order does not change any result)
     if (t < kBwdBuckets) bcount[t] = 0u;
     __syncthreads();
     for (int j = t; j < L; j += kBwdThreads) {
       const uint32_t gid = list_gid[w0 + j];
-      int bk = kBwdBuckets - 1;
-      uint16_t box = 1u << 10;  // empty
+      const int kb = w0 + j >= mid ? 1 : 0;
+      int bk = 33;
+      uint16_t box = (uint16_t)((1u << 11) | (kb << 10));  // empty
       if (gid < T.n_total) {
         int xl, xh, yl, yh, zl, zh;
-        key_box(bg, er[gid], cr[gid], cutoff, x0, y0, z0, xe, ye, ze, xl, xh, yl, yh, zl, zh);
+        key_box(bg, er[gid], cr[gid], cutoff, x0[kb], y0[kb], z0[kb], xe[kb], ye[kb], ze[kb], xl, xh, yl, yh, zl, zh);
         if (xl <= xh && yl <= yh && zl <= zh) {
           bk = 32 - (yh - yl + 1) * (zh - zl + 1);
-          box = (uint16_t)((yl - y0) | ((yh - y0) << 3) | ((zl - z0) << 6) | ((zh - z0) << 8));
+          box = (uint16_t)((yl - y0[kb]) | ((yh - y0[kb]) << 3) | ((zl - z0[kb]) << 6) | ((zh - z0[kb]) << 8) |
+                           (kb << 10));
         }
       }
       sbucket[j] = (uint8_t)bk;
@@ -420,13 +448,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       const float mx = R.r0.x, A = R.r0.w;
       const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
       const uint32_t box = sbox[jj];
-      const int yl = y0 + (box & 7), yh = y0 + ((box >> 3) & 7), zl = z0 + ((box >> 6) & 3),
-                zh = z0 + ((box >> 8) & 3);
+      const int kb = (box >> 10) & 1;
+      const int bx0 = kb ? x0[1] : x0[0], by0 = kb ? y0[1] : y0[0], bz0 = kb ? z0[1] : z0[0];
+      const float2 *sC = sCI + kb * BV;
+      const int yl = by0 + (box & 7), yh = by0 + ((box >> 3) & 7), zl = bz0 + ((box >> 6) & 3),
+                zh = bz0 + ((box >> 8) & 3);
+      float px[BX];
+#pragma unroll
+      for (int kk = 0; kk < BX; ++kk) px[kk] = centre(bg.ox, bg.hx, bx0 + kk);
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
       const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
       const int ny_k = yh - yl + 1;
-      const int nrows = (box >> 10) ? 0 : ny_k * (zh - zl + 1);
+      const int nrows = (box >> 11) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
       for (int r = 0; r < nrows; ++r) {
         const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
@@ -437,15 +471,15 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
         const float xs = -bq * inv2a;
         const float qmax = fmaf(0.5f * bq, xs, cq);
         if (qmax >= thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) {
-          const int rb = ((iz - z0) * 8 + (iy - y0)) * RP;
+          const int rb = ((iz - bz0) * 8 + (iy - by0)) * RP;
           float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
           for (int kk = 0; kk < BX; ++kk) {
             const float dx = px[kk] - mx;
-            const float q = row_q(a, bq, cq, dx);
-            float wt = fast_exp2(q);
-            wt = q >= thr ? wt : 0.f;
-            const float2 ci = sCI[rb + kk];
+            const float qv = row_q(a, bq, cq, dx);
+            float wt = fast_exp2(qv);
+            wt = qv >= thr ? wt : 0.f;
+            const float2 ci = sC[rb + kk];
             const float tt = ci.x * wt;
             const float kap = (A - ci.y) * tt;
             tA += tt;
@@ -486,7 +520,7 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
                                const float *I, const float *W, const float *gI, const float *obs, float *loss_part,
                                hipStream_t s) {
   char *b = (char *)ws;
-  const unsigned nb = (unsigned)T.nbricks_total;
+  const unsigned nb = (unsigned)T.npairs_total;  // one wave per pair of bricks
   if (nb == 0) return hipSuccess;
   const EvalRec *er = (const EvalRec *)(b + L.evalrec);
   const CullRec *cr = (const CullRec *)(b + L.cullrec);
