@@ -210,12 +210,12 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
     }
     g0 += bt->n[k];
     b0 += sd.bg.nbricks;
-    p0 += (sd.bg.nbricks + 1) / 2;
+    p0 += (sd.bg.nbricks + kBwdBricks - 1) / kBwdBricks;
     v0 += nvox;
   }
   T->n_total = g0;
   T->nbricks_total = b0;
-  T->npairs_total = p0;
+  T->ngroups_total = p0;
   if (g0 >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "total Gaussian count must be < 2^31");
   if (b0 >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARG, "too many bricks");
   if (v0 > ((int64_t)1 << 40)) return fail(GS_ERR_INVALID_ARG, "batch volumes too large");

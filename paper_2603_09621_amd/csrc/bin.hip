@@ -83,13 +83,16 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
   world_to_index(my - ey - ty, my + ey + ty, bg.oy, bg.ihy, bg.ny, yl, yh);
   world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.ihz, bg.nz, zl, zh);
   if (xl > xh || yl > yh || zl > zh) return 0;
+  // the slab-independent part of the three projections, shared by all slabs
+  const SlabAxes kyz = slab_axes(syy, szz, syz, cutoff), kxz = slab_axes(sxx, szz, sxz, cutoff),
+                 kxy = slab_axes(sxx, syy, sxy, cutoff);
   uint32_t count = 0;
   for (int kz = zl / bg.bz; kz <= zh / bg.bz; ++kz) {
     int za = max(zl, kz * bg.bz), zb = min(zh, kz * bg.bz + bg.bz - 1);
     const float Z0 = centre(bg.oz, bg.hz, za), Z1 = centre(bg.oz, bg.hz, zb);
     float ylo, yhi, xzlo, xzhi;
-    if (!extent_in_slab(my, mz, syy, szz, syz, cutoff, Z0, Z1, ty, ylo, yhi)) continue;
-    if (!extent_in_slab(mx, mz, sxx, szz, sxz, cutoff, Z0, Z1, tx, xzlo, xzhi)) continue;
+    if (!slab_extent(kyz, my, mz, cutoff, Z0, Z1, ty, ylo, yhi)) continue;
+    if (!slab_extent(kxz, mx, mz, cutoff, Z0, Z1, tx, xzlo, xzhi)) continue;
     int yl2, yh2;
     world_to_index(ylo, yhi, bg.oy, bg.ihy, bg.ny, yl2, yh2);
     yl2 = max(yl2, yl);
@@ -99,7 +102,7 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
       int ya = max(yl2, ky * bg.by), yb = min(yh2, ky * bg.by + bg.by - 1);
       const float Y0 = centre(bg.oy, bg.hy, ya), Y1 = centre(bg.oy, bg.hy, yb);
       float xylo, xyhi;
-      if (!extent_in_slab(mx, my, sxx, syy, sxy, cutoff, Y0, Y1, tx, xylo, xyhi)) continue;
+      if (!slab_extent(kxy, mx, my, cutoff, Y0, Y1, tx, xylo, xyhi)) continue;
       int xl2, xh2;
       world_to_index(fmaxf(xzlo, xylo), fminf(xzhi, xyhi), bg.ox, bg.ihx, bg.nx, xl2, xh2);
       xl2 = max(xl2, xl);

@@ -53,6 +53,9 @@ struct BrickGrid {
 // small table passed by value as a kernel argument.  A single scan is the one-entry table.
 constexpr int kMaxScans = 16;
 
+// Bricks per backward wave: consecutive bricks of a scan whose keys are ordered together.
+constexpr int kBwdBricks = 2;
+
 struct ScanDesc {
   BrickGrid bg;
   // the scan's own Gaussian parameters (n entries each; relax may be NULL); for a concatenated set
@@ -60,7 +63,7 @@ struct ScanDesc {
   const float *mu, *ls, *quat, *amp, *relax;
   int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated numbering
   int64_t b0;     // first (global) brick of the scan
-  int64_t p0;     // first (global) brick pair of the scan (the backward takes two bricks per wave)
+  int64_t p0;     // first (global) brick group of the scan (the backward takes kBwdBricks bricks per wave)
   int64_t v0;     // first voxel of the scan's volume in the concatenated volumes
   int64_t o0;     // first LR voxel of the scan's observation in the concatenated observations
   float gscale;   // fit loss: dL/dI magnitude 1 / (zdown * nLR)
@@ -69,7 +72,7 @@ struct ScanDesc {
 
 struct ScanTable {
   int32_t ns;
-  int64_t n_total, nbricks_total, npairs_total;
+  int64_t n_total, nbricks_total, ngroups_total;
   ScanDesc s[kMaxScans];
   __host__ __device__ __forceinline__ int of_gauss(int64_t i) const {
     int k = 0;
@@ -81,7 +84,7 @@ struct ScanTable {
     while (k + 1 < ns && b >= s[k + 1].b0) ++k;
     return k;
   }
-  __host__ __device__ __forceinline__ int of_pair(int64_t q) const {
+  __host__ __device__ __forceinline__ int of_group(int64_t q) const {
     int k = 0;
     while (k + 1 < ns && q >= s[k + 1].p0) ++k;
     return k;

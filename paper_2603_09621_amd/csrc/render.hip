@@ -275,9 +275,8 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
-constexpr int kBwdThreads = 64;  // one wave per pair of bricks
-constexpr int kBwdBricks = 2;    // bricks b, b + 1 of a scan per wave: one ordering over both lists
-constexpr int kBwdWindow = 512;  // keys ordered by work per pass over the pair's lists
+constexpr int kBwdThreads = 64;  // one wave per group of kBwdBricks consecutive bricks
+constexpr int kBwdWindow = 512;  // keys ordered by work per pass over the group's lists
 constexpr int kBwdBuckets = 34;  // rows per key in its brick: 32 .. 0 (bucket 0 = 32 rows), then empty
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
@@ -365,60 +364,87 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
                                                      float *__restrict__ loss_part, int64_t cap,
                                                      float4 *__restrict__ part) {
   constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
-  // LDS voxels per brick, padded so that the same row of the two bricks falls into different banks
-  // (keys of similar boxes in both bricks read the same row index at the same time)
-  constexpr int BV = 32 * RP + 8;
+  // LDS voxels per brick, padded so that the same row of different bricks falls into different banks
+  // (keys of similar boxes in the bricks read the same row index at the same time)
+  constexpr int BV = 32 * RP + 4;
+  constexpr int G = kBwdBricks;
   if (st->overflow) return;
-  __shared__ float2 sCI[kBwdBricks * BV];
+  __shared__ float2 sCI[G * BV];
   __shared__ uint16_t sorder[kBwdWindow];
   __shared__ uint8_t sbucket[kBwdWindow];
-  // key's row box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the pair (bit 10),
-  // empty (bit 11)
+  // key's row box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the group
+  // (bits 10-11), empty (bit 12)
   __shared__ uint16_t sbox[kBwdWindow];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
+  __shared__ int sorg[G][3];  // brick origins (voxel indices)
   const int64_t q = blockIdx.x;
-  const ScanDesc &sd = T.s[T.of_pair(q)];
+  const ScanDesc &sd = T.s[T.of_group(q)];
   const BrickGrid &bg = sd.bg;
-  const int64_t lb = 2 * (q - sd.p0);  // the pair's first brick, scan-local
-  const int nbk = bg.nbricks - lb >= 2 ? 2 : 1;
+  const int64_t lb = G * (q - sd.p0);  // the group's first brick, scan-local
+  const int nbk = (int)min((int64_t)G, bg.nbricks - lb);
   const int64_t b = sd.b0 + lb;
-  int x0[2], y0[2], z0[2];
-  brick_coords(bg, lb, x0[0], y0[0], z0[0]);
-  brick_coords(bg, lb + nbk - 1, x0[1], y0[1], z0[1]);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const uint32_t start = brick_off[b], mid = brick_off[b + 1], end = brick_off[b + nbk];
+  int x0[G], y0[G], z0[G];
+  uint32_t boff[G + 1];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    brick_coords(bg, lb + min(j, nbk - 1), x0[j], y0[j], z0[j]);
+    boff[j] = brick_off[b + min(j, nbk)];
+  }
+  boff[G] = brick_off[b + nbk];
+  if (t < G) {
+    sorg[t][0] = x0[t];
+    sorg[t][1] = y0[t];
+    sorg[t][2] = z0[t];
+  }
+  const uint32_t start = boff[0], end = boff[G];
   if (FIT || start != end) {
-    bwd_stage<BX, FIT>(sd, b, x0[0], y0[0], z0[0], t, Iv, Wv, gI, obs, eps, loss_part, sCI);
-    if (nbk == 2) bwd_stage<BX, FIT>(sd, b + 1, x0[1], y0[1], z0[1], t, Iv, Wv, gI, obs, eps, loss_part, sCI + BV);
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < nbk)
+        bwd_stage<BX, FIT>(sd, b + j, x0[j], y0[j], z0[j], t, Iv, Wv, gI, obs, eps, loss_part, sCI + j * BV);
   }
   __syncthreads();
   if (start == end) return;
-  int xe[2], ye[2], ze[2];
+  int xe[G], ye[G], ze[G];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < G; ++j) {
     xe[j] = min(x0[j] + BX - 1, bg.nx - 1);
     ye[j] = min(y0[j] + 7, bg.ny - 1);
     ze[j] = min(z0[j] + 3, bg.nz - 1);
   }
   for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
     const int L = (int)min((uint32_t)kBwdWindow, end - w0);
-    // order the window's keys (of both bricks) by their number of rows in their brick, most first,
-    // so that the lanes of a wave run the same number of row iterations (each key's result is
-    // independent of where it runs, so the order does not change any result)
+    // order the window's keys (of all bricks of the group) by their number of rows in their brick,
+    // most first, so that the lanes of a wave run similar numbers of row iterations (each key's
+    // result is independent of where it runs, so the order does not change any result)
     if (t < kBwdBuckets) bcount[t] = 0u;
     __syncthreads();
     for (int j = t; j < L; j += kBwdThreads) {
-      const uint32_t gid = list_gid[w0 + j];
-      const int kb = w0 + j >= mid ? 1 : 0;
-      int bk = 33;
-      uint16_t box = (uint16_t)((1u << 11) | (kb << 10));  // empty
+      const uint32_t k = w0 + j;
+      const uint32_t gid = list_gid[k];
+      int kb = 0;
+#pragma unroll
+      for (int g = 1; g < G; ++g) kb += k >= boff[g] ? 1 : 0;
+      int xb = x0[0], yb = y0[0], zb = z0[0], xeb = xe[0], yeb = ye[0], zeb = ze[0];
+#pragma unroll
+      for (int g = 1; g < G; ++g)
+        if (kb == g) {
+          xb = x0[g];
+          yb = y0[g];
+          zb = z0[g];
+          xeb = xe[g];
+          yeb = ye[g];
+          zeb = ze[g];
+        }
+      int bk = kBwdBuckets - 1;
+      uint16_t box = (uint16_t)((1u << 12) | (kb << 10));  // empty
       if (gid < T.n_total) {
         int xl, xh, yl, yh, zl, zh;
-        key_box(bg, er[gid], cr[gid], cutoff, x0[kb], y0[kb], z0[kb], xe[kb], ye[kb], ze[kb], xl, xh, yl, yh, zl, zh);
+        key_box(bg, er[gid], cr[gid], cutoff, xb, yb, zb, xeb, yeb, zeb, xl, xh, yl, yh, zl, zh);
         if (xl <= xh && yl <= yh && zl <= zh) {
           bk = 32 - (yh - yl + 1) * (zh - zl + 1);
-          box = (uint16_t)((yl - y0[kb]) | ((yh - y0[kb]) << 3) | ((zl - z0[kb]) << 6) | ((zh - z0[kb]) << 8) |
-                           (kb << 10));
+          box = (uint16_t)((yl - yb) | ((yh - yb) << 3) | ((zl - zb) << 6) | ((zh - zb) << 8) | (kb << 10));
         }
       }
       sbucket[j] = (uint8_t)bk;
@@ -448,8 +474,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       const float mx = R.r0.x, A = R.r0.w;
       const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
       const uint32_t box = sbox[jj];
-      const int kb = (box >> 10) & 1;
-      const int bx0 = kb ? x0[1] : x0[0], by0 = kb ? y0[1] : y0[0], bz0 = kb ? z0[1] : z0[0];
+      const int kb = (box >> 10) & 3;
+      const int bx0 = sorg[kb][0], by0 = sorg[kb][1], bz0 = sorg[kb][2];
       const float2 *sC = sCI + kb * BV;
       const int yl = by0 + (box & 7), yh = by0 + ((box >> 3) & 7), zl = bz0 + ((box >> 6) & 3),
                 zh = bz0 + ((box >> 8) & 3);
@@ -460,7 +486,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
       const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
       const int ny_k = yh - yl + 1;
-      const int nrows = (box >> 11) ? 0 : ny_k * (zh - zl + 1);
+      const int nrows = (box >> 12) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
       for (int r = 0; r < nrows; ++r) {
         const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
@@ -520,7 +546,7 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
                                const float *I, const float *W, const float *gI, const float *obs, float *loss_part,
                                hipStream_t s) {
   char *b = (char *)ws;
-  const unsigned nb = (unsigned)T.npairs_total;  // one wave per pair of bricks
+  const unsigned nb = (unsigned)T.ngroups_total;  // one wave per group of bricks
   if (nb == 0) return hipSuccess;
   const EvalRec *er = (const EvalRec *)(b + L.evalrec);
   const CullRec *cr = (const CullRec *)(b + L.cullrec);
