@@ -485,6 +485,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
       const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
+      const float thr_lo = thr - 1e-5f * (1.f + fabsf(thr));  // the row test's allowance, key part
       const int ny_k = yh - yl + 1;
       const int nrows = (box >> 12) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
@@ -496,9 +497,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
         // cutoff hold no pair
         const float xs = -bq * inv2a;
         const float qmax = fmaf(0.5f * bq, xs, cq);
-        if (qmax >= thr - 1e-5f * (1.f + fabsf(thr) + fabsf(cq))) {
+        if (qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo)) {
           const int rb = ((iz - bz0) * 8 + (iy - by0)) * RP;
-          float tA = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+          float tA, m0, m1, m2;
 #pragma unroll
           for (int kk = 0; kk < BX; ++kk) {
             const float dx = px[kk] - mx;
@@ -508,11 +509,18 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
             const float2 ci = sC[rb + kk];
             const float tt = ci.x * wt;
             const float kap = (A - ci.y) * tt;
-            tA += tt;
-            m0 += kap;
             const float u = kap * dx;
-            m1 += u;
-            m2 = fmaf(u, dx, m2);
+            if (kk == 0) {  // the row's sums start from the first voxel's terms
+              tA = tt;
+              m0 = kap;
+              m1 = u;
+              m2 = u * dx;
+            } else {
+              tA += tt;
+              m0 += kap;
+              m1 += u;
+              m2 = fmaf(u, dx, m2);
+            }
           }
           sA += tA;
           sk += m0;
