@@ -377,6 +377,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   __shared__ uint16_t sbox[kBwdWindow];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   __shared__ int sorg[G][3];  // brick origins (voxel indices)
+  __shared__ float spy[G][8], spz[G][4];  // voxel-centre coordinates of the bricks' rows and slices
   const int64_t q = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_group(q)];
   const BrickGrid &bg = sd.bg;
@@ -396,6 +397,17 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     sorg[t][0] = x0[t];
     sorg[t][1] = y0[t];
     sorg[t][2] = z0[t];
+  }
+  if (t < 8 * G) {
+    int yb = y0[0], zb = z0[0];
+#pragma unroll
+    for (int j = 1; j < G; ++j)
+      if (t / 8 == j) {
+        yb = y0[j];
+        zb = z0[j];
+      }
+    spy[t / 8][t % 8] = centre(bg.oy, bg.hy, yb + t % 8);
+    if (t % 8 < 4) spz[t / 8][t % 8] = centre(bg.oz, bg.hz, zb + t % 8);
   }
   const uint32_t start = boff[0], end = boff[G];
   if (FIT || start != end) {
@@ -475,30 +487,30 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
       const uint32_t box = sbox[jj];
       const int kb = (box >> 10) & 3;
-      const int bx0 = sorg[kb][0], by0 = sorg[kb][1], bz0 = sorg[kb][2];
+      const int bx0 = sorg[kb][0];
       const float2 *sC = sCI + kb * BV;
-      const int yl = by0 + (box & 7), yh = by0 + ((box >> 3) & 7), zl = bz0 + ((box >> 6) & 3),
-                zh = bz0 + ((box >> 8) & 3);
+      const float *sPy = spy[kb], *sPz = spz[kb];
+      // the box in brick-local rows and slices
+      const int yl = box & 7, yh = (box >> 3) & 7, zl = (box >> 6) & 3, zh = (box >> 8) & 3;
       float px[BX];
 #pragma unroll
       for (int kk = 0; kk < BX; ++kk) px[kk] = centre(bg.ox, bg.hx, bx0 + kk);
       float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
       float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-      const float inv2a = 0.5f * __builtin_amdgcn_rcpf(a);
+      const float inv4a = 0.25f * __builtin_amdgcn_rcpf(a);
       const float thr_lo = thr - 1e-5f * (1.f + fabsf(thr));  // the row test's allowance, key part
       const int ny_k = yh - yl + 1;
       const int nrows = (box >> 12) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
       for (int r = 0; r < nrows; ++r) {
-        const float py = centre(bg.oy, bg.hy, iy), pz = centre(bg.oz, bg.hz, iz);
+        const float py = sPy[iy], pz = sPz[iz];
         float dy, dz, bq, cq;
         row_coeffs(R, py, pz, dy, dz, bq, cq);
-        // the row's maximum of q is at dx* = -b / (2a); rows whose maximum is clearly below the
-        // cutoff hold no pair
-        const float xs = -bq * inv2a;
-        const float qmax = fmaf(0.5f * bq, xs, cq);
+        // the row's maximum of q (at dx* = -b / (2a)) is c - b^2 / (4a); rows whose maximum is
+        // clearly below the cutoff hold no pair
+        const float qmax = fmaf(-(bq * bq), inv4a, cq);
         if (qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo)) {
-          const int rb = ((iz - bz0) * 8 + (iy - by0)) * RP;
+          const int rb = (iz * 8 + iy) * RP;
           float tA, m0, m1, m2;
 #pragma unroll
           for (int kk = 0; kk < BX; ++kk) {
