@@ -81,9 +81,15 @@ bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg
   bg->nx = grid->nx;
   bg->ny = grid->ny;
   bg->nz = grid->nz;
-  bg->bx = opts->bx;
-  bg->by = opts->by;
-  bg->bz = opts->bz;
+  auto ilog2 = [](int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+  };
+  bg->lbx = ilog2(opts->bx);
+  bg->lby = ilog2(opts->by);
+  bg->lbz = ilog2(opts->bz);
+  if ((1 << bg->lbx) != opts->bx || (1 << bg->lby) != opts->by || (1 << bg->lbz) != opts->bz) return false;
   bg->nbx = (grid->nx + opts->bx - 1) / opts->bx;
   bg->nby = (grid->ny + opts->by - 1) / opts->by;
   bg->nbz = (grid->nz + opts->bz - 1) / opts->bz;

@@ -87,8 +87,9 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
   const SlabAxes kyz = slab_axes(syy, szz, syz, cutoff), kxz = slab_axes(sxx, szz, sxz, cutoff),
                  kxy = slab_axes(sxx, syy, sxy, cutoff);
   uint32_t count = 0;
-  for (int kz = zl / bg.bz; kz <= zh / bg.bz; ++kz) {
-    int za = max(zl, kz * bg.bz), zb = min(zh, kz * bg.bz + bg.bz - 1);
+  // index ranges are non-negative, so shifts divide by the (power-of-two) brick shape
+  for (int kz = zl >> bg.lbz; kz <= zh >> bg.lbz; ++kz) {
+    int za = max(zl, kz << bg.lbz), zb = min(zh, ((kz + 1) << bg.lbz) - 1);
     const float Z0 = centre(bg.oz, bg.hz, za), Z1 = centre(bg.oz, bg.hz, zb);
     float ylo, yhi, xzlo, xzhi;
     if (!slab_extent(kyz, my, mz, cutoff, Z0, Z1, ty, ylo, yhi)) continue;
@@ -98,8 +99,8 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
     yl2 = max(yl2, yl);
     yh2 = min(yh2, yh);
     if (yl2 > yh2) continue;
-    for (int ky = yl2 / bg.by; ky <= yh2 / bg.by; ++ky) {
-      int ya = max(yl2, ky * bg.by), yb = min(yh2, ky * bg.by + bg.by - 1);
+    for (int ky = yl2 >> bg.lby; ky <= yh2 >> bg.lby; ++ky) {
+      int ya = max(yl2, ky << bg.lby), yb = min(yh2, ((ky + 1) << bg.lby) - 1);
       const float Y0 = centre(bg.oy, bg.hy, ya), Y1 = centre(bg.oy, bg.hy, yb);
       float xylo, xyhi;
       if (!slab_extent(kxy, mx, my, cutoff, Y0, Y1, tx, xylo, xyhi)) continue;
@@ -108,7 +109,7 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
       xl2 = max(xl2, xl);
       xh2 = min(xh2, xh);
       if (xl2 > xh2) continue;
-      const int kx0 = xl2 / bg.bx, kx1 = xh2 / bg.bx;
+      const int kx0 = xl2 >> bg.lbx, kx1 = xh2 >> bg.lbx;
       const uint32_t row = (uint32_t)((kz * bg.nby + ky) * bg.nbx);
       for (int kx = kx0; kx <= kx1; ++kx) visit(row + (uint32_t)kx, count + (uint32_t)(kx - kx0));
       count += (uint32_t)(kx1 - kx0 + 1);

@@ -40,7 +40,7 @@ struct DevStatus {
 // Brick grid geometry of one scan.  Brick shape (bx, 8, 4) with bx in {4, 8, 16}.
 struct BrickGrid {
   int nx, ny, nz;    // voxels
-  int bx, by, bz;    // brick shape
+  int lbx, lby, lbz; // log2 of the brick shape (bricks are powers of two on every axis)
   int nbx, nby, nbz; // bricks per axis
   int64_t nbricks;
   float ox, oy, oz;  // origin

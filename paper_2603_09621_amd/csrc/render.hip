@@ -91,7 +91,7 @@ __device__ __forceinline__ uint32_t cell_mask(const BrickGrid &bg, const EvalRec
 
 __device__ __forceinline__ void brick_coords(const BrickGrid &bg, int64_t lb, int &x0, int &y0, int &z0) {
   const int kx = (int)(lb % bg.nbx), ky = (int)((lb / bg.nbx) % bg.nby), kz = (int)(lb / ((int64_t)bg.nbx * bg.nby));
-  x0 = kx * bg.bx;
+  x0 = kx << bg.lbx;
   y0 = ky * 8;
   z0 = kz * 4;
 }
