@@ -1,7 +1,8 @@
 // Forward and backward rasterizer kernels (§3.2 Eq. (rendering), §3.3).
 //
 // Bricks are BX x 8 x 4 voxels (BX in {4, 8, 16}; the paper uses 8 x 8 x 4).  Every launch covers
-// the bricks of all scans of a scan table (one workgroup per brick).
+// the bricks of all scans of a scan table (the forward: one workgroup per brick; the backward: one
+// per group of kBwdBricks consecutive bricks of a scan).
 //
 // Forward: BX/2 waves per brick; each wave owns a 4x4x4 quarter of the brick, split into four
 // 4x2x2 cells.  The brick's Gaussian list is staged through LDS in chunks; while staging, each
@@ -13,11 +14,11 @@
 // (numerator S, denominator W).  The four slots' partial sums of a voxel are added in a fixed order
 // at the end, so the result is bitwise deterministic.
 //
-// Backward: one wave per pair of neighbouring bricks, one Gaussian (key) per lane.  The bricks'
-// per-voxel factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of both
-// bricks are ordered together by their number of rows in their brick so that the lanes of a wave run
-// similar numbers of iterations (a pair gives the ordering twice as many keys to balance as one
-// brick); each lane walks the rows of its Gaussian's box inside its brick in one flat loop, skips
+// Backward: one wave per group of kBwdBricks (two) consecutive bricks, one Gaussian (key) per lane.
+// The bricks' per-voxel factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of
+// the group's bricks are ordered together by their number of rows in their brick so that the lanes of
+// a wave run similar numbers of iterations (two bricks give the ordering twice as many keys to
+// balance as one); each lane walks the rows of its Gaussian's box inside its brick in one flat loop, skips
 // rows whose maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and
 // accumulates per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
 // folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.
