@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=20, help="timed steps of the batched comparison")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals for the request-loop section (0: skip)")
+    ap.add_argument("--aniso-steps", type=int, default=5,
+                    help="timed render+gradient steps of the anisotropic 2M-Gaussian workload (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain device-to-device copy of this many MiB (a known-size "
                          "kernel against which profiler byte counters are calibrated)")
@@ -161,6 +163,63 @@ def batch_section(args, dev):
         "hip_graph": True,
         "bitwise_equal_to_plain": bool(equal),
         "ms_per_batched_step_eager": ms_eager / K,
+    }
+
+
+def aniso_section(args, dev):
+    """Render + gradient of the anisotropic workload (320x320x256, 2M Gaussians, log-scale std 0.8,
+    axis ratio <= 8, random rotations, MSE against a U(0,1) target): one step = bin, forward, MSE loss
+    and dL/dI, backward with the reduction to per-Gaussian gradients (no optimiser step)."""
+    import torch
+
+    from paper_2603_09621_amd import gs, synth
+
+    t0 = time.time()
+    p, T_np = synth.workload_aniso()
+    dims = (320, 320, 256)
+    print(f"[bench] anisotropic workload in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    grid = gs.Grid(*dims)
+    opts = gs.Opts(bx=args.bx)
+    g = gs.Gaussians.from_numpy(p, device=dev)
+    T = torch.from_numpy(T_np).to(dev)
+    bins = gs.plan_bins(g, grid, opts, headroom=1.1)
+    I = torch.empty(grid.shape, dtype=torch.float32, device=dev)
+    W = torch.empty_like(I)
+    gI = torch.empty_like(I)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    scratch = torch.empty(gs.gs_loss_scratch_bytes(I.numel()), dtype=torch.uint8, device=dev)
+    grads = gs.Grads.empty(g.n, relax=g.relax is not None, device=dev)
+
+    def step():
+        gs.gs_bin(g, grid, opts, bins)
+        gs.gs_render_fwd(g, grid, opts, bins, I, W)
+        gs.gs_loss_mse(I, T, gI, loss, scratch)
+        gs.gs_render_bwd(g, grid, opts, bins, I, W, gI, grads)
+
+    for _ in range(2):
+        step()
+    st = gs.gs_status(bins)
+    pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    gs.gs_count_pairs(g, grid, opts, bins, pairs)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.aniso_steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.aniso_steps
+    U = int(pairs.item())
+    return {
+        "workload": f"anisotropic render + gradient: HR {dims[0]}x{dims[1]}x{dims[2]}, {g.n} Gaussians (log-scale "
+                    f"std 0.8, axis ratio <= 8, random rotations), MSE vs U(0,1) target; bin + forward + loss + "
+                    f"backward + reduction per step",
+        "brick": [opts.bx, opts.by, opts.bz],
+        "steps": args.aniso_steps,
+        "ms_per_step": ms,
+        "keys": st["n_keys"],
+        "useful_pairs": U,
+        "evals_per_s": U / (ms * 1e-3),  # useful pairs per second, as the headline value
     }
 
 
@@ -309,9 +368,16 @@ def main():
                          f"{dims[0]}x{dims[1]}x{dims[2]} / {args.n}-Gaussian workload, "
                          f"{pairs0} useful pairs per step, {cpu_s:.2f} s per step"}
 
+    aniso = None
+    if args.aniso_steps > 0:
+        del bins, st, buf, g
+        torch.cuda.empty_cache()
+        aniso = aniso_section(args, dev)
+        torch.cuda.empty_cache()
+
     batched = None
     if not args.no_batch:
-        del bins, st, buf, g, snap, final
+        del snap, final
         torch.cuda.empty_cache()
         batched = batch_section(args, dev)
     serving = None
@@ -349,6 +415,7 @@ def main():
         "kernels_avg_ms": {k: round(v["avg_ms"], 5) for k, v in sorted(kern.items())},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "anisotropic": aniso,
         "batched": batched,
         "serving": serving,
     }
