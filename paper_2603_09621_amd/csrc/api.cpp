@@ -127,6 +127,7 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
   L.evalrec = take(sizeof(EvalRec) * (size_t)n);
   L.cullrec = take(sizeof(CullRec) * (size_t)n);
   L.off = take(sizeof(uint32_t) * (size_t)(n + 1));
+  L.runs = take(sizeof(uint32_t) * kRuns * (size_t)n);
   L.key_brick = take(sizeof(uint32_t) * (size_t)cap);
   L.key_gid = take(sizeof(uint32_t) * (size_t)cap);
   L.keys_alt = take(sizeof(uint32_t) * (size_t)cap);

@@ -66,8 +66,8 @@ __device__ __forceinline__ bool make_records(int64_t i, const float *__restrict_
 // Key generation.  For one Gaussian: its axis-aligned 3-sigma voxel box; for each brick z-slab the
 // y-extent of the ellipsoid inside that slab; for each brick row the x-extent inside the row's y-slab
 // intersected with the x-extent inside the z-slab.  Every brick whose voxel centres fall in these
-// conservative ranges receives a key.  The count pass and the emit pass run the same enumeration
-// (visit(brick, j) is called for the j-th key of the Gaussian).
+// conservative ranges receives a key.  The keys come in runs of consecutive bricks along x (one run
+// per brick row): visit(first brick, length, index of the run's first key among the Gaussian's keys).
 
 template <class Visit>
 __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
@@ -111,20 +111,27 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
       if (xl2 > xh2) continue;
       const int kx0 = xl2 >> bg.lbx, kx1 = xh2 >> bg.lbx;
       const uint32_t row = (uint32_t)((kz * bg.nby + ky) * bg.nbx);
-      for (int kx = kx0; kx <= kx1; ++kx) visit(row + (uint32_t)kx, count + (uint32_t)(kx - kx0));
+      visit(row + (uint32_t)kx0, (uint32_t)(kx1 - kx0 + 1), count);
       count += (uint32_t)(kx1 - kx0 + 1);
     }
   }
   return count;
 }
 
+// Run cache: the count pass records each Gaussian's runs (up to kRuns of them, each a 32-bit word
+// (first scan-local brick << 4) | (length - 1) for runs of at most 16 bricks starting below 2^28 - 1),
+// ended by kRunEnd; a Gaussian whose runs do not fit is marked kRunRedo and the emit pass enumerates
+// it again.  The emit pass then expands the recorded runs instead of repeating the enumeration.
+constexpr uint32_t kRunEnd = 0xFFFFFFFFu, kRunRedo = 0xFFFFFFFEu;
+
 // Fused prep + count: records of Gaussian i (of the concatenated numbering; its parameters are
-// entry i - g0 of its scan's arrays), its key count cnt[i] and, per block of kPrepThreads
-// Gaussians, the block's key total bsum[block] (the first level of the count scan), with bit 63
-// set if the block holds an invalid Gaussian.
+// entry i - g0 of its scan's arrays), its key count cnt[i], its run cache entry and, per block of
+// kPrepThreads Gaussians, the block's key total bsum[block] (the first level of the count scan),
+// with bit 63 set if the block holds an invalid Gaussian.
 __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, float cutoff,
                                                              EvalRec *__restrict__ er, CullRec *__restrict__ cr,
-                                                             uint32_t *__restrict__ cnt, uint64_t *__restrict__ bsum,
+                                                             uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
+                                                             uint64_t *__restrict__ bsum,
                                                              uint32_t *__restrict__ hist, int64_t hist_len) {
   __shared__ uint64_t wsum[kPrepThreads / 64];
   __shared__ int sbad;
@@ -141,7 +148,27 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, 
     if (!make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, r)) sbad = 1;
     er[i] = e;
     cr[i] = r;
-    c = enumerate_bricks(sd.bg, e, r, cutoff, [](uint32_t, uint32_t) {});
+    // the runs are kept in registers (run k goes to rr[k] by selects: the index is not a constant)
+    // and written as two 16-byte stores
+    uint32_t rr[kRuns];
+#pragma unroll
+    for (int k = 0; k < kRuns; ++k) rr[k] = kRunEnd;
+    int nr = 0;
+    bool redo = false;
+    c = enumerate_bricks(sd.bg, e, r, cutoff, [&](uint32_t first, uint32_t len, uint32_t) {
+      if (nr < kRuns && len <= 16u && first < 0x0FFFFFFFu) {
+        const uint32_t word = (first << 4) | (len - 1u);
+#pragma unroll
+        for (int k = 0; k < kRuns; ++k) rr[k] = nr == k ? word : rr[k];
+        ++nr;
+      } else {
+        redo = true;
+      }
+    });
+    if (redo) rr[0] = kRunRedo;
+    uint4 *rc = reinterpret_cast<uint4 *>(runs + (int64_t)kRuns * i);
+    rc[0] = make_uint4(rr[0], rr[1], rr[2], rr[3]);
+    rc[1] = make_uint4(rr[4], rr[5], rr[6], rr[7]);
     cnt[i] = c;
   }
   uint64_t v = c;
@@ -162,7 +189,8 @@ hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const W
   if (blocks == 0) return hipSuccess;
   prof_begin(s);
   k_prep_count<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
-                                               (uint32_t *)(b + L.off), (uint64_t *)(b + L.scan_tmp),
+                                               (uint32_t *)(b + L.off), (uint32_t *)(b + L.runs),
+                                               (uint64_t *)(b + L.scan_tmp),
                                                (uint32_t *)(b + L.hist), (int64_t)kRadix * L.sort_blocks);
   prof_end(s, "prep_count");
   return hipGetLastError();
@@ -251,7 +279,8 @@ constexpr int kEmitStage = 4096;  // keys staged per block (32 KB of LDS)
 
 __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float cutoff,
                                                        const EvalRec *__restrict__ er,
-                                                       const CullRec *__restrict__ cr, uint32_t *__restrict__ off,
+                                                       const CullRec *__restrict__ cr,
+                                                       const uint32_t *__restrict__ runs, uint32_t *__restrict__ off,
                                                        const uint64_t *__restrict__ bex, int64_t cap,
                                                        const DevStatus *st, uint32_t *__restrict__ key_brick,
                                                        uint32_t *__restrict__ key_gid, uint32_t *__restrict__ hist,
@@ -282,18 +311,40 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
   if (i < n) {
     const ScanDesc &sd = T.s[T.of_gauss(i)];
     const uint32_t b0 = (uint32_t)sd.b0;
+    // the Gaussian's runs: from the run cache, or enumerated again if they did not fit there
+    auto for_runs = [&](auto &&visit) {
+      const uint4 *rc = reinterpret_cast<const uint4 *>(runs + (int64_t)kRuns * i);
+      const uint4 ra = rc[0], rb = rc[1];
+      const uint32_t rr[kRuns] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+      if (rr[0] == kRunRedo) {
+        enumerate_bricks(sd.bg, er[i], cr[i], cutoff, visit);
+      } else {
+        uint32_t j = 0;
+#pragma unroll
+        for (int k = 0; k < kRuns; ++k) {
+          if (rr[k] == kRunEnd) break;
+          const uint32_t len = (rr[k] & 15u) + 1u;
+          visit(rr[k] >> 4, len, j);
+          j += len;
+        }
+      }
+    };
     if (staged) {
-      enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
-        sbrick[base - blk0 + j] = b0 + brick;
-        sgid[base - blk0 + j] = (uint32_t)i;
+      for_runs([&](uint32_t first, uint32_t len, uint32_t j0) {
+        for (uint32_t q = 0; q < len; ++q) {
+          sbrick[base - blk0 + j0 + q] = b0 + first + q;
+          sgid[base - blk0 + j0 + q] = (uint32_t)i;
+        }
       });
     } else {
-      enumerate_bricks(sd.bg, er[i], cr[i], cutoff, [&](uint32_t brick, uint32_t j) {
-        const int64_t slot = (int64_t)base + j;
-        if (slot < cap) {
-          key_brick[slot] = b0 + brick;
-          key_gid[slot] = (uint32_t)i;
-          atomicAdd(&hist[(int64_t)((b0 + brick) & (kRadix - 1)) * ntiles + slot / kSortTile], 1u);
+      for_runs([&](uint32_t first, uint32_t len, uint32_t j0) {
+        for (uint32_t q = 0; q < len; ++q) {
+          const int64_t slot = (int64_t)base + j0 + q;
+          if (slot < cap) {
+            key_brick[slot] = b0 + first + q;
+            key_gid[slot] = (uint32_t)i;
+            atomicAdd(&hist[(int64_t)((b0 + first + q) & (kRadix - 1)) * ntiles + slot / kSortTile], 1u);
+          }
         }
       });
     }
@@ -326,7 +377,7 @@ hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayou
   const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
   prof_begin(s);
   k_emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-                                         (uint32_t *)(b + L.off), (const uint64_t *)(b + L.scan_tmp), L.cap,
+                                         (const uint32_t *)(b + L.runs), (uint32_t *)(b + L.off), (const uint64_t *)(b + L.scan_tmp), L.cap,
                                          (const DevStatus *)(b + L.status), (uint32_t *)(b + L.key_brick),
                                          (uint32_t *)(b + L.key_gid), (uint32_t *)(b + L.hist), L.sort_blocks);
   prof_end(s, "emit");

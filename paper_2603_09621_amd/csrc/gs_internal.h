@@ -105,6 +105,7 @@ constexpr int kRadix = 1 << kRadixBits;
 // carries kBadBlock when the block holds an invalid Gaussian (non-finite parameter, zero quaternion
 // or r <= 0).
 constexpr int kPrepThreads = 256;
+constexpr int kRuns = 8;  // brick runs cached per Gaussian between the count and the emit pass
 constexpr uint64_t kBadBlock = 1ull << 63;
 
 // Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
@@ -119,7 +120,7 @@ struct WsLayout {
   int64_t n = 0, cap = 0, nbricks = 0;
   int sort_blocks = 0;  // tiles per radix pass (covers cap keys)
   int sort_passes = 0;  // ceil(bits(nbricks) / 8), at least 1
-  size_t status = 0, evalrec = 0, cullrec = 0, off = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
+  size_t status = 0, evalrec = 0, cullrec = 0, off = 0, runs = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
          vals_b = 0, list_gid = 0, list_slot = 0, brick_off = 0, hist = 0, scan_tmp = 0, partials = 0, total = 0;
   size_t sorted_keys = 0;  // where the brick ids end up after the last pass
 };
