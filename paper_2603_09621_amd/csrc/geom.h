@@ -38,15 +38,16 @@ __device__ __forceinline__ SlabAxes slab_axes(float saa, float sbb, float sab, f
 
 __device__ __forceinline__ bool slab_extent(const SlabAxes &k, float ma, float mb, float c, float lo_b, float hi_b,
                                             float tol, float &amin, float &amax) {
-  const float d0 = fmaxf(lo_b - mb, -k.eb - tol);
-  const float d1 = fminf(hi_b - mb, k.eb + tol);
+  const float ebt = k.eb + tol;
+  const float d0 = fmaxf(lo_b - mb, -ebt);
+  const float d1 = fminf(hi_b - mb, ebt);
   const float dm = fminf(fmaxf(k.dstar, d0), d1);
   const float dn = fminf(fmaxf(-k.dstar, d0), d1);
   const float c2 = c * c;
-  const float hm = __builtin_amdgcn_sqrtf(fmaxf(c2 - dm * dm * k.isbb, 0.f) * k.schur);
-  const float hn = __builtin_amdgcn_sqrtf(fmaxf(c2 - dn * dn * k.isbb, 0.f) * k.schur);
-  amax = ma + k.slope * dm + hm + tol;
-  amin = ma + k.slope * dn - hn - tol;
+  const float hm = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-dm * k.isbb, dm, c2), 0.f) * k.schur);
+  const float hn = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-dn * k.isbb, dn, c2), 0.f) * k.schur);
+  amax = fmaf(k.slope, dm, ma) + (hm + tol);
+  amin = fmaf(k.slope, dn, ma) - (hn + tol);
   return d0 <= d1;
 }
 
