@@ -350,3 +350,33 @@ def test_fit_step_with_learnable_relaxation():
         big = np.abs(gr[k]) > max(1e-2 * np.sqrt(np.mean(gr[k] ** 2)), 1e3 * floor)
         np.testing.assert_allclose(got[big], newp[k][big], rtol=1e-6, atol=1e-3 * lr[k], err_msg=k)
     assert (np64(g.relax) > 0).all()
+
+
+def test_long_brick_runs_are_enumerated_again():
+    """Gaussians elongated along x over many bricks (runs longer than the 16 bricks a run-cache word
+    holds) and Gaussians with more than 8 brick rows: the emit pass enumerates them again.  Keys,
+    useful pairs and the forward must match the oracle as for any other input."""
+    dims = (160, 24, 16)
+    grid = oracle.Grid(*dims)
+    n = 24
+    rng = np.random.default_rng(41)
+    p = synth.gaussians_uniform(41, n, dims, ls_std=0.1)
+    ls = np.log(np.stack([rng.uniform(15.0, 25.0, n), rng.uniform(0.8, 1.2, n), rng.uniform(0.8, 1.2, n)], 1))
+    ls[: n // 2, 1:] = np.log(3.0)  # half of them also span many brick rows
+    p["log_scale"] = ls.astype(np.float32)
+    p["quat"] = np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1))
+    p = cases.condition(p, grid, seed=43)
+    say("long runs", grid.shape, n)
+    gs = gs_mod()
+    for bx in (4, 8):
+        g = gs.Gaussians.from_numpy(p)
+        ggrid = to_grid(grid)
+        opts = gs.Opts(bx=bx)
+        I, W, bins = gs.render(g, ggrid, opts)
+        gs.gs_status(bins)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gs.gs_count_pairs(g, ggrid, opts, bins, cnt)
+        assert int(cnt.item()) == oracle.count_pairs(p, grid)
+        Io, Wo, _ = oracle.render(p, grid)
+        assert_fwd_close(np64(W), Wo, f"long runs W bx={bx}")
+        assert_fwd_close(np64(I), Io, f"long runs I bx={bx}")
