@@ -584,7 +584,6 @@ hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStrea
   uint32_t *hist = (uint32_t *)(b + L.hist);
   uint32_t *dtot = (uint32_t *)(b + L.scan_tmp);  // digit totals (the scan scratch is free here)
   const int nt = L.sort_blocks;
-  hipError_t err = hipSuccess;
   if (nt > 0) {
     const uint32_t *kin = ka, *vin = nullptr;
     for (int p = 0; p < L.sort_passes; ++p) {

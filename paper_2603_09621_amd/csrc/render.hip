@@ -64,8 +64,9 @@ __device__ __forceinline__ uint32_t cell_mask(const BrickGrid &bg, const EvalRec
   for (int h = 0; h < 2; ++h) {
     const float Z0 = centre(bg.oz, bg.hz, z0 + 2 * h), Z1 = centre(bg.oz, bg.hz, z0 + 2 * h + 1);
     float xl, xh;
-    const bool ok = slab_extent(kxz, mx, mz, cutoff, Z0, Z1, tx, xl, xh) &
-                    slab_extent(kyz, my, mz, cutoff, Z0, Z1, ty, yzl[h], yzh[h]);
+    const bool okx = slab_extent(kxz, mx, mz, cutoff, Z0, Z1, tx, xl, xh);
+    const bool oky = slab_extent(kyz, my, mz, cutoff, Z0, Z1, ty, yzl[h], yzh[h]);
+    const bool ok = okx && oky;
     world_to_index(xl, xh, bg.ox, bg.ihx, bg.nx, ixl[h], ixh[h]);
     if (!ok) {
       ixl[h] = 1;
