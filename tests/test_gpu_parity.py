@@ -24,12 +24,15 @@ CASES = {
     "aniso": (102, (40, 36, 20), 400, 0.8, 8.0),
     "dense": (103, (24, 24, 16), 1500, 0.3, None),
     "big_sigma": (104, (48, 40, 24), 40, 0.5, None),
+    "tiny_sigma": (105, (30, 22, 14), 400, 0.3, 4.0),
 }
+
+LS_MEAN = {"big_sigma": math.log(4.0), "tiny_sigma": math.log(0.35)}
 
 
 def _case(name):
     seed, dims, n, std, ratio = CASES[name]
-    kw = {"ls_mean": math.log(4.0)} if name == "big_sigma" else {}
+    kw = {"ls_mean": LS_MEAN[name]} if name in LS_MEAN else {}
     p, grid = cases.small_case(seed, dims=dims, n=n, ls_std=std, max_ratio=ratio, **kw)
     p["relax"] = np.random.default_rng(seed).uniform(0.3, 1.0, n).astype(np.float32)
     return p, grid
