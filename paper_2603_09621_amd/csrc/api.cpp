@@ -327,11 +327,12 @@ int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, i
 
 size_t gs_loss_scratch_bytes(int64_t nvox) { return sizeof(float) * (size_t)std::max(1, loss_blocks(nvox)); }
 
+// step: the fit's per-scan step counters (advanced by the count scan), or NULL outside a fit step
 static int bin_front(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
-                     const WsLayout &L, hipStream_t s) {
+                     const WsLayout &L, hipStream_t s, int32_t *step = nullptr) {
   hipError_t e;
   if ((e = launch_prep_count(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
-  if ((e = launch_scan_counts(bins->ws, L, s)) != hipSuccess) return hip_fail(e, "scan_counts");
+  if ((e = launch_scan_counts(bins->ws, L, step, T.ns, s)) != hipSuccess) return hip_fail(e, "scan_counts");
   return GS_OK;
 }
 
@@ -360,9 +361,9 @@ int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t
 }
 
 static int bin_all(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
-                   const WsLayout &L, hipStream_t s) {
+                   const WsLayout &L, hipStream_t s, int32_t *step = nullptr) {
   int rc;
-  if ((rc = bin_front(g, T, opts, bins, L, s))) return rc;
+  if ((rc = bin_front(g, T, opts, bins, L, s, step))) return rc;
   hipError_t e;
   if ((e = launch_emit(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
   if ((e = launch_sort(T, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
@@ -524,7 +525,7 @@ int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_ba
   if (!fused && !buf->dL_dI)
     return fail(GS_ERR_INVALID_ARG, "dL_dI is required when zdown differs from the brick depth");
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = bin_all(&g, T, &fo->opts, bins, L, s))) return rc;
+  if ((rc = bin_all(&g, T, &fo->opts, bins, L, s, st->step))) return rc;
   const gs_opts_t &o = fo->opts;
   hipError_t e = launch_fwd(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, s);
   if (e != hipSuccess) return hip_fail(e, "render_fwd");

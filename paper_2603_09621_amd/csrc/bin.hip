@@ -222,9 +222,12 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
 
 constexpr int kBlockScanThreads = 1024;
 
+// step (fit steps only, else NULL): the scans' Adam step counters advance here, before the step's
+// Adam update reads them, unless the keys overflowed the capacity (then the step changes nothing).
 __global__ __launch_bounds__(kBlockScanThreads) void k_scan_blocks(uint64_t *__restrict__ bsum, int64_t nb,
                                                                     int64_t n, int64_t cap,
-                                                                    uint32_t *__restrict__ off, DevStatus *st) {
+                                                                    uint32_t *__restrict__ off, DevStatus *st,
+                                                                    int32_t *__restrict__ step, int ns) {
   __shared__ uint64_t wsum[kBlockScanThreads / 64];
   const int t = threadIdx.x;
   const int64_t per = (nb + kBlockScanThreads - 1) / kBlockScanThreads;
@@ -257,14 +260,15 @@ __global__ __launch_bounds__(kBlockScanThreads) void k_scan_blocks(uint64_t *__r
     st->nonfinite = bad;
     off[n] = (int64_t)total > cap ? (uint32_t)cap : (uint32_t)total;
   }
+  if (step && t < ns && (int64_t)total <= cap) step[t] += 1;
 }
 
-hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s) {
+hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns, hipStream_t s) {
   char *b = (char *)ws;
   const int64_t nb = (L.n + kPrepThreads - 1) / kPrepThreads;
   prof_begin(s);
   k_scan_blocks<<<1, kBlockScanThreads, 0, s>>>((uint64_t *)(b + L.scan_tmp), nb, L.n, L.cap,
-                                               (uint32_t *)(b + L.off), (DevStatus *)(b + L.status));
+                                               (uint32_t *)(b + L.off), (DevStatus *)(b + L.status), step, ns);
   prof_end(s, "scan_counts");
   return hipGetLastError();
 }

@@ -136,7 +136,7 @@ void prof_end(hipStream_t s, const char *name);
 // Kernel launchers (bin.hip, render.hip, reduce.hip, fit.hip).  Return hipGetLastError() of the
 // launches.  `g` / `st` hold the concatenated Gaussians of all scans of T.
 hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
-hipError_t launch_scan_counts(void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns, hipStream_t s);
 hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_fwd(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,

@@ -185,13 +185,50 @@ __device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, 
   if (lr != 0.f) p -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
 }
 
+// Fit loss of every scan of T: loss[s] = (sum of its bricks' loss parts, fixed order) * lscale, by
+// one block of kRedThreads threads.
+__device__ void fit_loss_sum(const ScanTable &T, const float *__restrict__ loss_part, float *__restrict__ loss) {
+  __shared__ float sh[kRedThreads / 64];
+  const int t = threadIdx.x;
+  for (int k = 0; k < T.ns; ++k) {
+    const ScanDesc &sd = T.s[k];
+    const float *lp = loss_part + sd.b0;
+    const int64_t nb = sd.bg.nbricks;
+    float acc = 0.f;
+    for (int64_t j0 = t; j0 < nb; j0 += 8 * kRedThreads) {
+      float w8[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t jj = j0 + (int64_t)j * kRedThreads;
+        w8[j] = jj < nb ? lp[jj] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += w8[j];
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
+    if ((t & 63) == 0) sh[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      float tot = 0.f;
+      for (int w = 0; w < kRedThreads / 64; ++w) tot += sh[w];
+      loss[k] = tot * sd.lscale;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ mu, float *__restrict__ ls, float *__restrict__ quat,
                               float *__restrict__ amp, float *__restrict__ relax, const uint32_t *__restrict__ off,
                               const float4 *__restrict__ part, const DevStatus *st, float *__restrict__ d_mu,
                               float *__restrict__ d_ls, float *__restrict__ d_quat, float *__restrict__ d_amp,
                               float *__restrict__ d_relax, float *__restrict__ m, float *__restrict__ v,
-                              const int32_t *__restrict__ step, AdamArgs h) {
+                              const int32_t *__restrict__ step, AdamArgs h, const float *__restrict__ loss_part,
+                              float *__restrict__ loss) {
   if (st->overflow) return;
+  // block 0 also sums the fit loss of every scan (the per-brick loss parts come from the backward):
+  // bricks t, t + 256, ... per thread in order, then a fixed-order block reduction
+  if (blockIdx.x == 0 && loss_part) fit_loss_sum(T, loss_part, loss);
   __shared__ float4 sp[3 * kRedChunk];
   const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
   // the Gaussian's parameters and moments do not depend on the partial sums: their loads are issued
@@ -231,7 +268,7 @@ __global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ 
   if (i >= n) return;
   float g[12];
   gauss_grad_v(pv[6], pv[7], pv[8], pv[9], pv[3], pv[4], pv[5], pv[11], a0, a1, a2, g);
-  const float t = (float)(step[T.of_gauss(i)] + 1);
+  const float t = (float)step[T.of_gauss(i)];  // advanced by this step's binning
   const float bc1 = -expm1f(t * h.lnb1), bc2 = -expm1f(t * h.lnb2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -261,30 +298,27 @@ __global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ 
   if (relax) relax[i] = pv[11];
 }
 
-// Fit-step epilogue, one block per scan: loss[s] = (sum of the scan's per-brick partial sums, fixed
-// order) * lscale (skipped when loss_part is NULL: the loss was computed by the loss kernel) and the
-// scan's step counter advances.  Thread t adds bricks t, t + 1024, ... in order, 8 loads in flight.
+// Fit loss without Gaussians (the fused reduction computes it otherwise), one block per scan:
+// loss[s] = (sum of the scan's per-brick loss parts, fixed order) * lscale.  Thread t adds bricks
+// t, t + 1024, ... in order, 8 loads in flight.
 constexpr int kFinThreads = 1024;
 
 __global__ __launch_bounds__(kFinThreads) void k_fit_finalize(const ScanTable T, const float *__restrict__ loss_part,
-                                                              float *__restrict__ loss, int32_t *__restrict__ step,
-                                                              const DevStatus *st) {
+                                                              float *__restrict__ loss, const DevStatus *st) {
   __shared__ float sh[kFinThreads / 64];
   const ScanDesc &sd = T.s[blockIdx.x];
   float acc = 0.f;
-  if (loss_part) {
-    const float *lp = loss_part + sd.b0;
-    const int64_t nb = sd.bg.nbricks;
-    for (int64_t i0 = threadIdx.x; i0 < nb; i0 += 8 * kFinThreads) {
-      float v[8];
+  const float *lp = loss_part + sd.b0;
+  const int64_t nb = sd.bg.nbricks;
+  for (int64_t i0 = threadIdx.x; i0 < nb; i0 += 8 * kFinThreads) {
+    float v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t i = i0 + (int64_t)j * kFinThreads;
-        v[j] = i < nb ? lp[i] : 0.f;
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc += v[j];
+    for (int j = 0; j < 8; ++j) {
+      const int64_t i = i0 + (int64_t)j * kFinThreads;
+      v[j] = i < nb ? lp[i] : 0.f;
     }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
   }
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
@@ -293,8 +327,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fit_finalize(const ScanTable T,
   if (threadIdx.x == 0 && !st->overflow) {
     float tot = 0.f;
     for (int w = 0; w < kFinThreads / 64; ++w) tot += sh[w];
-    if (loss_part) loss[blockIdx.x] = tot * sd.lscale;
-    step[blockIdx.x] += 1;
+    loss[blockIdx.x] = tot * sd.lscale;
   }
 }
 
@@ -314,8 +347,9 @@ hipError_t launch_reduce_adam(const ScanTable &T, const gs_fit_state_t &g, const
     k_reduce_adam<<<(unsigned)((g.n + kRedThreads - 1) / kRedThreads), kRedThreads, 0, s>>>(
         T, g.n, g.mu, g.log_scale, g.quat, g.amp, g.relax, (const uint32_t *)(b + L.off),
         (const float4 *)(b + L.partials), (const DevStatus *)(b + L.status), gr.d_mu, gr.d_log_scale, gr.d_quat,
-        gr.d_amp, gr.d_relax, g.m, g.v, g.step, h);
-  k_fit_finalize<<<(unsigned)T.ns, kFinThreads, 0, s>>>(T, loss_part, loss, g.step, (const DevStatus *)(b + L.status));
+        gr.d_amp, gr.d_relax, g.m, g.v, g.step, h, loss_part, loss);
+  else if (loss_part)
+    k_fit_finalize<<<(unsigned)T.ns, kFinThreads, 0, s>>>(T, loss_part, loss, (const DevStatus *)(b + L.status));
   prof_end(s, "reduce_adam");
   return hipGetLastError();
 }
