@@ -20,8 +20,10 @@
 // a wave run similar numbers of iterations (two bricks give the ordering twice as many keys to
 // balance as one); each lane walks the rows of its Gaussian's box inside its brick in one flat loop, skips
 // rows whose maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and
-// accumulates per row the moments sum(k), sum(k dx), sum(k dx^2) and sum(c w) of k = dL/dw * w,
-// folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA.
+// accumulates per row the moments sum(k), sum(k ck), sum(k ck^2) and sum(c w) of k = dL/dw * w
+// (ck: the voxel's x offset from the row's centre, so that dx = dxc + ck h with one dxc per key),
+// folded with the row's (dy, dz) into the 11 brick-local sums of (1, delta, delta delta^T) and dA;
+// the key's x moments follow from the ck moments at its end.
 // The sums of each (Gaussian, brick) pair are written to the key's pre-sort slot; a second kernel
 // reduces each Gaussian's slots in slot order and applies the chain rule (no atomics; deterministic).
 #include <hip/hip_runtime.h>
@@ -501,8 +503,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       float px[BX];
 #pragma unroll
       for (int kk = 0; kk < BX; ++kk) px[kk] = centre(bg.ox, bg.hx, bx0 + kk);
-      float sA = 0.f, sk = 0.f, skx = 0.f, sky = 0.f, skz = 0.f;
-      float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+      // sc, scc, scy, scz: sums of k ck, k ck^2, k ck dy, k ck dz (ck: the voxel's x offset from the
+      // brick row's centre in voxels, see below); the other sums are those of the partial record
+      float sA = 0.f, sk = 0.f, sc = 0.f, sky = 0.f, skz = 0.f;
+      float scc = 0.f, myy = 0.f, mzz = 0.f, scy = 0.f, scz = 0.f, myz = 0.f;
       const float inv4a = 0.25f * __builtin_amdgcn_rcpf(a);
       const float thr_lo = thr - 1e-5f * (1.f + fabsf(thr));  // the row test's allowance, key part
       const int ny_k = yh - yl + 1;
@@ -517,9 +521,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
         const float qmax = fmaf(-(bq * bq), inv4a, cq);
         if (qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo)) {
           const int rb = (iz * 8 + iy) * RP;
+          // dx of voxel kk is dxc + ck h with ck = kk - (BX - 1) / 2 (offset from the row's centre):
+          // the row sums of k dx and k dx^2 follow from m1 = sum ck k and m2 = sum ck^2 k
           float tA, m0, m1, m2;
 #pragma unroll
           for (int kk = 0; kk < BX; ++kk) {
+            constexpr float half = 0.5f * (BX - 1);
+            const float ck = (float)kk - half;
             const float dx = px[kk] - mx;
             const float qv = row_q(a, bq, cq, dx);
             float wt = fast_exp2(qv);
@@ -527,27 +535,26 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
             const float2 ci = sC[rb + kk];
             const float tt = ci.x * wt;
             const float kap = (A - ci.y) * tt;
-            const float u = kap * dx;
             if (kk == 0) {  // the row's sums start from the first voxel's terms
               tA = tt;
               m0 = kap;
-              m1 = u;
-              m2 = u * dx;
+              m1 = ck * kap;
+              m2 = (ck * ck) * kap;
             } else {
               tA += tt;
               m0 += kap;
-              m1 += u;
-              m2 = fmaf(u, dx, m2);
+              m1 = fmaf(ck, kap, m1);
+              m2 = fmaf(ck * ck, kap, m2);
             }
           }
           sA += tA;
           sk += m0;
-          skx += m1;
+          sc += m1;
           sky = fmaf(m0, dy, sky);
           skz = fmaf(m0, dz, skz);
-          mxx += m2;
-          mxy = fmaf(m1, dy, mxy);
-          mxz = fmaf(m1, dz, mxz);
+          scc += m2;
+          scy = fmaf(m1, dy, scy);
+          scz = fmaf(m1, dz, scz);
           const float m0dy = m0 * dy;
           myy = fmaf(m0dy, dy, myy);
           myz = fmaf(m0dy, dz, myz);
@@ -558,6 +565,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
           ++iz;
         }
       }
+      // back from row-centre offsets to dx: sum k dx = dxc sum k + h sum ck k, sum k dx^2 =
+      // dxc^2 sum k + 2 dxc h sum ck k + h^2 sum ck^2 k, sum k dx d = dxc sum k d + h sum ck k d
+      const float hx = bg.hx, dxc = fmaf(0.5f * (BX - 1), hx, px[0] - mx);
+      const float skx = fmaf(hx, sc, dxc * sk);
+      const float mxx = fmaf(dxc, fmaf(dxc, sk, 2.f * hx * sc), (hx * hx) * scc);
+      const float mxy = fmaf(hx, scy, dxc * sky);
+      const float mxz = fmaf(hx, scz, dxc * skz);
       float4 *o = part + (int64_t)slot * 3;
       o[0] = make_float4(sA, sk, skx, sky);
       o[1] = make_float4(skz, mxx, myy, mzz);
