@@ -245,7 +245,7 @@ int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_ada
  * gradients and the loss; updates the parameters, the moments and *step.  The gradient reduction
  * is fused with Adam; when zdown equals the brick depth the loss is also computed inside the
  * backward kernel.  No host synchronisation; check gs_status() for capacity overflow (the step then
- * leaves the parameters and *step unchanged). */
+ * writes none of its outputs: the parameters, the moments, *step and the loss keep their values). */
 int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts_t *fo, const gs_bins_t *bins,
                 const gs_fit_buffers_t *buf, void *stream);
 

@@ -541,7 +541,7 @@ int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_ba
   for (int k = 0; k < T.ns; ++k) {
     const ScanDesc &sd = T.s[k];
     e = launch_loss_l1z(buf->I + sd.v0, lr_obs + sd.o0, sd.bg.nx, sd.bg.ny, sd.bg.nz, fo->zdown, buf->dL_dI + sd.v0,
-                        buf->loss + k, buf->scratch, s);
+                        buf->loss + k, buf->scratch, s, (const DevStatus *)((char *)bins->ws + L.status));
     if (e != hipSuccess) return hip_fail(e, "loss_l1z");
   }
   e = launch_bwd(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, buf->dL_dI, s);

@@ -47,10 +47,13 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_mse(const float *__restri
 }
 
 // LR voxel q = (k, y, x): lr = (((I[fk] + I[fk+1]) + ...) + I[fk+f-1]) * (1/f); diff = lr - obs;
-// dL/dI = sign(diff) * gscale on the f HR voxels of q.
+// dL/dI = sign(diff) * gscale on the f HR voxels of q.  st (a fit step's binning status, or NULL):
+// after a key-capacity overflow the step writes nothing, this kernel included.
 __global__ __launch_bounds__(kLossThreads) void k_loss_l1z(const float *__restrict__ I, const float *__restrict__ obs,
                                                             int64_t nlr, int64_t plane, int f, float invf, float gscale,
-                                                            float *__restrict__ g, float *__restrict__ partial) {
+                                                            float *__restrict__ g, float *__restrict__ partial,
+                                                            const DevStatus *st) {
+  if (st && st->overflow) return;
   __shared__ float sh[kLossThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kLossThreads * kLossItems;
   float acc = 0.f;
@@ -73,7 +76,8 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_l1z(const float *__restri
 }
 
 __global__ __launch_bounds__(256) void k_loss_finalize(const float *__restrict__ partial, int nb, float scale,
-                                                       float *__restrict__ loss) {
+                                                       float *__restrict__ loss, const DevStatus *st = nullptr) {
+  if (st && st->overflow) return;
   __shared__ float sh[4];
   float acc = 0.f;
   for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
@@ -93,15 +97,15 @@ hipError_t launch_loss_mse(const float *I, const float *T, int64_t nvox, float *
 }
 
 hipError_t launch_loss_l1z(const float *I, const float *obs, int nx, int ny, int nz, int f, float *g, float *loss,
-                           void *scratch, hipStream_t s) {
+                           void *scratch, hipStream_t s, const DevStatus *st) {
   int64_t plane = (int64_t)nx * ny;
   int64_t nlr = plane * (nz / f);
   int nb = loss_blocks(nlr);
   if (nb == 0) return hipSuccess;
   prof_begin(s);
   k_loss_l1z<<<nb, kLossThreads, 0, s>>>(I, obs, nlr, plane, f, (float)(1.0 / f), (float)(1.0 / ((double)f * nlr)),
-                                         g, (float *)scratch);
-  k_loss_finalize<<<1, 256, 0, s>>>((const float *)scratch, nb, (float)(1.0 / (double)nlr), loss);
+                                         g, (float *)scratch, st);
+  k_loss_finalize<<<1, 256, 0, s>>>((const float *)scratch, nb, (float)(1.0 / (double)nlr), loss, st);
   prof_end(s, "loss_l1z");
   return hipGetLastError();
 }

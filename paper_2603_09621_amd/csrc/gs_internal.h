@@ -155,7 +155,7 @@ hipError_t launch_reduce_adam(const ScanTable &T, const gs_fit_state_t &g, const
 hipError_t launch_loss_mse(const float *I, const float *T, int64_t nvox, float *g, float *loss, void *scratch,
                            hipStream_t s);
 hipError_t launch_loss_l1z(const float *I, const float *obs, int nx, int ny, int nz, int f, float *g, float *loss,
-                           void *scratch, hipStream_t s);
+                           void *scratch, hipStream_t s, const DevStatus *st = nullptr);
 hipError_t launch_adam(const gs_fit_state_t &st, const gs_grads_t &gr, const gs_adam_t &hp, const void *ws_status,
                        hipStream_t s);
 

@@ -204,6 +204,45 @@ def test_capacity_overflow_is_reported_and_outputs_untouched():
     assert_fwd_close(np64(I), Io, "after retry")
 
 
+@pytest.mark.parametrize("zdown", [4, 2])
+def test_fit_step_with_capacity_overflow_changes_nothing(zdown):
+    """A fit step whose keys overflow the capacity leaves the parameters, the moments, the step
+    counter and the loss as they were (the fused path and the separate loss kernel); the same step
+    with enough capacity then advances the counter by one."""
+    gs = gs_mod()
+    dims = (32, 32, 16)
+    hr = synth.phantom(41, dims)
+    lr_obs = synth.zmean_observation(hr, zdown)
+    p = synth.lattice_init(42, lr_obs, 600, f=zdown)
+    say("fit step overflow", dims, p["amp"].shape[0], "zdown", zdown)
+    g = gs.Gaussians.from_numpy(p)
+    ggrid = gs.Grid(*dims)
+    fo = gs.FitOpts(ggrid, zdown=zdown)
+    st = gs.FitState(g)
+    st.step.fill_(5)
+    st.m.fill_(0.25)
+    st.v.fill_(0.5)
+    buf = gs.FitBuffers(g.n, ggrid, relax=True)
+    buf.loss.fill_(-3.0)
+    obs_t = torch.from_numpy(lr_obs).cuda()
+    before = {k: getattr(g, k).clone() for k in gs.GROUPS if getattr(g, k) is not None}
+    small = gs.Bins(g.n, ggrid, fo.opts, 100)
+    gs.gs_fit_step(st, obs_t, fo, small, buf)
+    with pytest.raises(gs.CapacityError):
+        gs.gs_status(small)
+    for k, v in before.items():
+        assert torch.equal(getattr(g, k), v), k
+    assert bool(torch.all(st.m == 0.25)) and bool(torch.all(st.v == 0.5))
+    assert int(st.step.item()) == 5
+    assert float(buf.loss.item()) == -3.0
+    bins = gs.plan_bins(g, ggrid, fo.opts, headroom=1.5)
+    gs.gs_fit_step(st, obs_t, fo, bins, buf)
+    gs.gs_status(bins)
+    assert int(st.step.item()) == 6
+    assert math.isfinite(float(buf.loss.item())) and float(buf.loss.item()) >= 0.0
+    assert any(not torch.equal(getattr(g, k), v) for k, v in before.items())
+
+
 def test_losses_match_oracle():
     gs = gs_mod()
     rng = np.random.default_rng(4)
