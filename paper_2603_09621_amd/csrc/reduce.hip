@@ -169,7 +169,8 @@ __global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const 
 // Fused gradient + Adam for the fit step: the gradient of Gaussian i (as k_reduce_chain, also
 // written to the gradient outputs) and the bias-corrected Adam update of its 12 parameters, moments
 // in the group layout mu (3n), log_scale (3n), quat (4n), amp (n), relax (n).  Each scan of the table
-// has its own step counter: Gaussian i of scan k takes step t = step[k] + 1.
+// has its own step counter, already advanced by this step's binning (the count scan): Gaussian i of
+// scan k takes step t = step[k].  Block 0 also writes the fit loss of every scan.
 struct AdamArgs {
   float lr[5];
   float b1, b2, eps;
