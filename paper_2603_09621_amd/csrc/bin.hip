@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, 
     er[i] = e;
     cr[i] = r;
     // the runs are kept in registers (run k goes to rr[k] by selects: the index is not a constant)
-    // and written as two 16-byte stores
+    // and written as 16-byte stores
     uint32_t rr[kRuns];
 #pragma unroll
     for (int k = 0; k < kRuns; ++k) rr[k] = kRunEnd;
@@ -167,8 +167,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, 
     });
     if (redo) rr[0] = kRunRedo;
     uint4 *rc = reinterpret_cast<uint4 *>(runs + (int64_t)kRuns * i);
-    rc[0] = make_uint4(rr[0], rr[1], rr[2], rr[3]);
-    rc[1] = make_uint4(rr[4], rr[5], rr[6], rr[7]);
+#pragma unroll
+    for (int q = 0; q < kRuns / 4; ++q) rc[q] = make_uint4(rr[4 * q], rr[4 * q + 1], rr[4 * q + 2], rr[4 * q + 3]);
     cnt[i] = c;
   }
   uint64_t v = c;
@@ -318,8 +318,15 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
     // the Gaussian's runs: from the run cache, or enumerated again if they did not fit there
     auto for_runs = [&](auto &&visit) {
       const uint4 *rc = reinterpret_cast<const uint4 *>(runs + (int64_t)kRuns * i);
-      const uint4 ra = rc[0], rb = rc[1];
-      const uint32_t rr[kRuns] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+      uint32_t rr[kRuns];
+#pragma unroll
+      for (int q = 0; q < kRuns / 4; ++q) {
+        const uint4 v = rc[q];
+        rr[4 * q] = v.x;
+        rr[4 * q + 1] = v.y;
+        rr[4 * q + 2] = v.z;
+        rr[4 * q + 3] = v.w;
+      }
       if (rr[0] == kRunRedo) {
         enumerate_bricks(sd.bg, er[i], cr[i], cutoff, visit);
       } else {

@@ -106,6 +106,7 @@ constexpr int kRadix = 1 << kRadixBits;
 // or r <= 0).
 constexpr int kPrepThreads = 256;
 constexpr int kRuns = 8;  // brick runs cached per Gaussian between the count and the emit pass
+static_assert(kRuns % 4 == 0, "the run cache is read and written as 16-byte words");
 constexpr uint64_t kBadBlock = 1ull << 63;
 
 // Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
