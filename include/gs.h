@@ -74,7 +74,8 @@ typedef struct {
 /* Rasterizer options.  Brick shape (bx, by, bz) in voxels (§3.3 uses 8x8x4; the library also runs
  * 4x8x4 and 16x8x4, a choice that changes speed and FP32 summation order only);
  * gs_brick_supported() tells.  cutoff: Mahalanobis truncation radius (3 = the 3-sigma ellipsoid).
- * eps: denominator regulariser (>= 0). */
+ * eps: denominator regulariser, > 0 (the rendering equation has none; with eps = 0 a voxel that no
+ * Gaussian reaches would be 0/0, so the library requires a positive eps). */
 typedef struct {
   int32_t bx, by, bz;
   float cutoff;
@@ -240,7 +241,8 @@ int gs_loss_l1_zmean(const float *I, const float *obs, const gs_grid_t *hr, int3
 int gs_adam_step(const gs_fit_state_t *st, const gs_grads_t *grads, const gs_adam_t *hp, const gs_bins_t *bins,
                  void *stream);
 
-/* One step of the per-scan zero-shot fit (§3.3 "end-to-end", Fig. 1): bin -> render -> z-mean ->
+/* One step of the per-scan zero-shot fit (§3.2: the whole rendering is differentiable and optimised
+ * end to end; Fig. 1 for the fit loop): bin -> render -> z-mean ->
  * L1 vs lr_obs -> backward -> Adam.  lr_obs: device [hr.nz/zdown][hr.ny][hr.nx].  Writes I, W, the
  * gradients and the loss; updates the parameters, the moments and *step.  The gradient reduction
  * is fused with Adam; when zdown equals the brick depth the loss is also computed inside the

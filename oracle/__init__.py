@@ -7,7 +7,14 @@ Contents (FP64 unless stated):
   * ``render``, ``render_points``, ``grad``, ``count_pairs``, ``ambiguous``, ``frames``,
     ``index_boxes``: ctypes wrappers over ``oracle.c`` (the rendering equation of §3.2 truncated
     to the 3-sigma ellipsoid of §3.3, and the two gradient equations of §3.3).
-  * ``mse_loss``, ``zmean``, ``zmean_adjoint``, ``fit_l1_loss``: the losses of the fit (numpy).
+  * ``render_bound``, ``grad_bound``: a-priori bounds of this oracle's own rounding error per output
+    entry (its FP64 error), from the sums of absolute terms and the term counts.
+  * ``render_envelope``: the forward with the inclusion of ambiguous pairs (|d^2 - 9| within a band)
+    left open: per voxel the extremes over every include/exclude choice.
+  * ``weights_box``: one Gaussian's weights over its index box with the support held fixed (for
+    box-local finite differences).
+  * ``mse_loss``, ``zmean``, ``zmean_adjoint``, ``fit_l1_loss``, ``l1_sign_ties``: the losses of the
+    fit (numpy, FP64) and the LR voxels whose L1 sign a correct FP32 render may take either way.
   * ``adam_step``: Adam with bias correction (numpy), the optimiser of the per-scan fit.
   * ``fit_step``: render -> loss -> gradient -> Adam, composed from the above.
 
@@ -74,6 +81,18 @@ def _lib(long_double: bool = False):
     lib.og_render_frozen.restype = _int
     lib.og_ambiguous_voxels.argtypes = [_i64, _f32p, _f32p, _f32p, *grid_args, _dbl, _dbl, _i32p, _int]
     lib.og_ambiguous_voxels.restype = _int
+    lib.og_render_bound.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _vp, *grid_args, _dbl, _dbl, _f64p, _f64p,
+                                    _f64p, _int]
+    lib.og_render_bound.restype = _int
+    lib.og_grad_bound.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _vp, *grid_args, _dbl, _dbl, _f64p, _f64p, _f64p,
+                                  _i64, _vp, _f64p, _f64p, _int]
+    lib.og_grad_bound.restype = _int
+    lib.og_render_envelope.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _vp, *grid_args, _dbl, _dbl, _dbl, _int,
+                                       _f64p, _f64p, _f64p, _f64p, _vp, _int]
+    lib.og_render_envelope.restype = _i64
+    lib.og_weights_box.argtypes = [_f32p, _f32p, _f32p, _f32p, _vp, _f32p, _f32p, _f32p, *grid_args, _dbl, _i32p,
+                                   _i64, _vp, _vp]
+    lib.og_weights_box.restype = _i64
     _LIBS[name] = lib
     return lib
 
@@ -242,6 +261,89 @@ def index_boxes(p: dict, grid: Grid, cutoff: float = 3.0):
     return box
 
 
+def render_bound(p: dict, grid: Grid, cutoff: float = 3.0, eps: float = 1e-8, threads: Optional[int] = None,
+                 long_double: bool = False):
+    """A-priori bound of this oracle's rounding error in ``render``: per voxel |I_computed - I_exact|
+    <= bI and likewise bW (arrays [nz, ny, nx]), valid when every pair is decided as exact
+    arithmetic decides it, i.e. when the returned margin (the smallest |d^2 - cutoff^2| minus that
+    pair's d^2 error bound over all visited pairs) is positive.  Returns (bI, bW, margin)."""
+    n, mu, ls, q, amp, relax = _params(p)
+    bI = np.zeros(grid.size)
+    bW = np.zeros(grid.size)
+    margin = np.zeros(1)
+    rc = _lib(long_double).og_render_bound(n, mu, ls, q, amp, _ptr(relax), *grid._args(), float(cutoff), float(eps),
+                                           bI, bW, margin, threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle render_bound failed ({rc})")
+    return bI.reshape(grid.shape), bW.reshape(grid.shape), float(margin[0])
+
+
+def grad_bound(p: dict, grid: Grid, I, W, gI, cutoff: float = 3.0, eps: float = 1e-8, sel=None,
+               threads: Optional[int] = None, long_double: bool = False):
+    """A-priori bound of this oracle's rounding error in ``grad`` (same arguments): a dict of arrays
+    shaped like ``grad``'s outputs (rows not selected are NaN), and the margin as in
+    ``render_bound``."""
+    n, mu, ls, q, amp, relax = _params(p)
+    I = np.ascontiguousarray(I, dtype=np.float64).reshape(-1)
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(-1)
+    gI = np.ascontiguousarray(gI, dtype=np.float64).reshape(-1)
+    assert I.size == W.size == gI.size == grid.size
+    b = np.full((n, 12), np.nan)
+    margin = np.zeros(1)
+    selv = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    rc = _lib(long_double).og_grad_bound(n, mu, ls, q, amp, _ptr(relax), *grid._args(), float(cutoff), float(eps), I,
+                                         W, gI, 0 if selv is None else selv.shape[0], _ptr(selv), b, margin,
+                                         threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle grad_bound failed ({rc})")
+    out = {"mu": b[:, 0:3], "log_scale": b[:, 3:6], "quat": b[:, 6:10], "amp": b[:, 10], "relax": b[:, 11]}
+    return {k: np.ascontiguousarray(v) for k, v in out.items()}, float(margin[0])
+
+
+def render_envelope(p: dict, grid: Grid, band: float, cutoff: float = 3.0, eps: float = 1e-8, maxk: int = 12,
+                    threads: Optional[int] = None):
+    """Forward with every ambiguous pair (|d^2 - cutoff^2| <= band) free to be included or not.
+    Returns (Ilo, Ihi, Wlo, Whi, namb, skipped): per voxel the extremes of I and W over all
+    include/exclude choices of its namb ambiguous pairs (lo = hi = the forward where namb = 0;
+    -inf / +inf where namb > maxk, counted in skipped)."""
+    n, mu, ls, q, amp, relax = _params(p)
+    Ilo, Ihi, Wlo, Whi = (np.zeros(grid.size) for _ in range(4))
+    namb = np.zeros(grid.size, dtype=np.int32)
+    sk = _lib().og_render_envelope(n, mu, ls, q, amp, _ptr(relax), *grid._args(), float(cutoff), float(eps),
+                                   float(band), int(maxk), Ilo, Ihi, Wlo, Whi, _ptr(namb),
+                                   threads or default_threads())
+    if sk < 0:
+        raise ValueError(f"oracle render_envelope failed ({sk})")
+    sh = grid.shape
+    return Ilo.reshape(sh), Ihi.reshape(sh), Wlo.reshape(sh), Whi.reshape(sh), namb.reshape(sh), int(sk)
+
+
+def weights_box(p: dict, j: int, grid: Grid, support: Optional[dict] = None, cutoff: float = 3.0):
+    """Weights of Gaussian j of ``p`` over the padded index box of Gaussian j of ``support`` (default
+    ``p``), with the pair predicate taken from ``support`` (the support held fixed).  Returns
+    (flat voxel indices int64, weights float64); pairs outside the support weigh 0."""
+    support = p if support is None else support
+
+    def one(d, keys):
+        return [_f32(d[k]).reshape(np.asarray(d[k]).shape[0], -1)[j].copy() for k in keys]
+
+    mu, ls, q, amp = one(p, ("mu", "log_scale", "quat", "amp"))
+    relax = None if p.get("relax") is None else _f32(p["relax"]).reshape(-1)[j:j + 1].copy()
+    mu0, ls0, q0 = one(support, ("mu", "log_scale", "quat"))
+    box = np.zeros(6, dtype=np.int32)
+    lib = _lib()
+    cnt = lib.og_weights_box(mu, ls, q, amp, _ptr(relax), mu0, ls0, q0, *grid._args(), float(cutoff), box, 0, None,
+                             None)
+    if cnt < 0:
+        raise ValueError("oracle weights_box: invalid Gaussian")
+    vox = np.zeros(cnt, dtype=np.int64)
+    w = np.zeros(cnt)
+    if cnt:
+        lib.og_weights_box(mu, ls, q, amp, _ptr(relax), mu0, ls0, q0, *grid._args(), float(cutoff), box, cnt,
+                           _ptr(vox), _ptr(w))
+    return vox, w
+
+
 # ------------------------------------------------------------------------------------------------
 # Losses of the fit (numpy, FP64).
 
@@ -269,24 +371,35 @@ def zmean_adjoint(G, f: int = 4):
 
 
 def fit_l1_loss(I, O, f: int = 4):
-    """Fit loss: L = mean |zmean(I) - O| over LR voxels; returns (L, dL/dI at HR).
+    """Fit loss: L = mean |zmean(I) - O| over LR voxels; returns (L, dL/dI at HR), with
+    dL/dI = sign(zmean(I) - O) / (f * nLR) on the f HR voxels of each LR voxel and sign(0) = 0, all
+    in FP64."""
+    LR = zmean(I, f)
+    d = LR - np.asarray(O, dtype=np.float64)
+    L = float(np.mean(np.abs(d)))
+    return L, zmean_adjoint(np.sign(d) / d.size, f)
 
-    The sign of (zmean(I) - O) decides the gradient; that decision is taken in float32, on the
-    z-mean summed in slice order and scaled by 1/f, the precision and order of the kernel.  sign(0)
-    is 0.
-    """
-    I32 = np.asarray(I, dtype=np.float32)
-    O32 = np.asarray(O, dtype=np.float32)
-    nz, ny, nx = I32.shape
-    Iv = I32.reshape(nz // f, f, ny, nx)
-    acc = Iv[:, 0].copy()
-    for j in range(1, f):
-        acc = (acc + Iv[:, j]).astype(np.float32)
-    lr32 = (acc * np.float32(1.0 / f)).astype(np.float32)
-    sgn = np.sign((lr32 - O32).astype(np.float32)).astype(np.float64)
-    LR = zmean(np.asarray(I, dtype=np.float64), f)
-    L = float(np.mean(np.abs(LR - np.asarray(O, dtype=np.float64))))
-    return L, zmean_adjoint(sgn / sgn.size, f)
+
+# An FP32 render that meets the forward tolerance (|I - I_exact| <= FWD_RTOL |I| + FWD_ATOL per
+# voxel) has a z-mean within FWD_RTOL max|I| + FWD_ATOL of the exact one, plus the FP32 rounding of
+# the f-term sum and its scaling (at most (f + 1) 2^-24 of the sum of |I|).
+FWD_RTOL, FWD_ATOL = 1e-5, 1e-7
+
+
+def l1_sign_band(I, f: int = 4):
+    """Per LR voxel [nz/f, ny, nx]: how far a render meeting the forward tolerance may put its
+    z-mean from this one, FWD_RTOL max_j |I_j| + FWD_ATOL + (f + 1) 2^-24 sum_j |I_j| / f over the
+    LR voxel's f HR voxels j."""
+    I = np.asarray(I, dtype=np.float64)
+    nz, ny, nx = I.shape
+    g = np.abs(I).reshape(nz // f, f, ny, nx)
+    return FWD_RTOL * g.max(axis=1) + FWD_ATOL + (f + 1) * 2.0 ** -24 * g.sum(axis=1) / f
+
+
+def l1_sign_ties(I, O, f: int = 4):
+    """LR voxels where |zmean(I) - O| is within ``l1_sign_band``: there either sign (and 0) of the
+    L1 gradient is a correct result."""
+    return np.abs(zmean(I, f) - np.asarray(O, dtype=np.float64)) <= l1_sign_band(I, f)
 
 
 # ------------------------------------------------------------------------------------------------

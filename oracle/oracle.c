@@ -33,6 +33,7 @@
  * Grid convention: voxel (ix, iy, iz) has centre origin + spacing * (ix, iy, iz); volumes are
  * stored [nz][ny][nx] with x fastest.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -582,4 +583,460 @@ int og_ambiguous_voxels(int64_t n, const float *mu, const float *log_scale, cons
   }
   free(G);
   return 0;
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * A-priori rounding-error bounds of this oracle's own arithmetic, per output entry (the FP64
+ * oracle error; the same code bounds the long double build with its own unit roundoff).
+ *
+ * u is the unit roundoff of real_t and gam(k) = k u / (1 - k u), the classical bound on the
+ * relative error of k successive roundings (a recursive sum of k + 1 terms, or a product chain).
+ *
+ * One pair (voxel p, Gaussian i).  The computed delta_a = (o_a + h_a i_a) - mu_a is within
+ * e_a = 3 u (|o_a| + |h_a i_a| + |mu_a|) of the exact one.  The computed P = R diag(D) R^T,
+ * D_k = exp(-2 s_k), is within gam(5) Pabs + 40 u Dmax of the exact one entrywise, where
+ * Pabs = |R| diag(D) |R|^T >= |P| and Dmax = max_k D_k (the rotation entries come from the
+ * normalised quaternion within about 8 u absolute each, |R| <= 1; exp within one ulp).  The
+ * quadratic form sums 9 terms of two products each.  Hence the computed d^2 is within
+ *   D2 = gam(30) |delta|^T Pabs |delta| + 40 u Dmax (sum_a |delta_a|)^2 + 2 e^T Pabs |delta|
+ * of the exact d^2, and the weight w = r exp(-d^2 / 2) has relative error at most
+ *   tau = 0.505 D2 + 3 u      (exp and the product with r within one ulp each),
+ * provided the pair is decided as the exact arithmetic decides it, i.e. |d^2 - cutoff^2| > D2.
+ * The functions below report the smallest |d^2 - cutoff^2| - D2 over every pair of every box they
+ * visit (min_margin) so that this precondition can be checked.
+ */
+#ifdef OG_LONG_DOUBLE
+#define OG_U ((real_t)LDBL_EPSILON / 2)
+#else
+#define OG_U ((real_t)DBL_EPSILON / 2)
+#endif
+
+static real_t gam(real_t k) { return k * OG_U / (1 - k * OG_U); }
+
+/* Pabs and Dmax of a Gaussian (see above). */
+static void abs_frame(const og_gauss_t *G, real_t Pabs[3][3], real_t *Dmax) {
+  real_t D[3];
+  *Dmax = 0;
+  for (int k = 0; k < 3; ++k) {
+    D[k] = 1 / G->ev[k];
+    if (D[k] > *Dmax) *Dmax = D[k];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      real_t s = 0;
+      for (int k = 0; k < 3; ++k) s += R_FABS(G->R[a][k]) * D[k] * R_FABS(G->R[b][k]);
+      Pabs[a][b] = s;
+    }
+}
+
+/* D2 of the pair (see above); e receives the error bound of each delta entry. */
+static real_t pair_d2_err(const og_gauss_t *G, const og_grid_t *g, const real_t Pabs[3][3], real_t Dmax, int ix,
+                          int iy, int iz, const real_t d[3], real_t e[3]) {
+  const int idx[3] = {ix, iy, iz};
+  real_t ad[3], l1 = 0;
+  for (int a = 0; a < 3; ++a) {
+    ad[a] = R_FABS(d[a]);
+    l1 += ad[a];
+    e[a] = 3 * OG_U * (R_FABS(g->o[a]) + R_FABS(g->h[a] * idx[a]) + R_FABS(G->mu[a]));
+  }
+  real_t quad = 0, lin = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      quad += ad[a] * Pabs[a][b] * ad[b];
+      lin += e[a] * Pabs[a][b] * ad[b];
+    }
+  return gam(30) * quad + 40 * OG_U * Dmax * l1 * l1 + 2 * lin;
+}
+
+/* Error bound of the forward at every voxel: |I_computed - I_exact| <= bI, likewise bW, for the
+ * truncated sums of og_render (each voxel: W = sum of K weights with relative errors <= tau,
+ * summed recursively; S = sum of A w; I = S / (W + eps)):
+ *   bW = (tau + gam(K) (1 + tau)) W,    bS = (tau + u + gam(K) (1 + tau + u)) sum |A w|,
+ *   bI = (bS + |I| bW) / (W + eps) + 2 u |I|          (the addition of eps and the division),
+ * all times (1 + 1e-9) for the second-order terms.  *min_margin: see above. */
+int og_render_bound(int64_t n, const float *mu, const float *log_scale, const float *quat, const float *amp,
+                    const float *relax, int nx, int ny, int nz, const double *origin, const double *spacing,
+                    double cutoff, double eps, double *bI, double *bW, double *min_margin, int nthreads) {
+  og_grid_t g;
+  make_grid(&g, nx, ny, nz, origin, spacing);
+  int64_t V = (int64_t)nx * ny * nz;
+  og_gauss_t *G = (og_gauss_t *)malloc(sizeof(og_gauss_t) * (size_t)(n > 0 ? n : 1));
+  real_t *Wa = (real_t *)calloc((size_t)V, sizeof(real_t));
+  real_t *Sa = (real_t *)calloc((size_t)V, sizeof(real_t));
+  real_t *Sabs = (real_t *)calloc((size_t)V, sizeof(real_t));
+  real_t *tau = (real_t *)calloc((size_t)V, sizeof(real_t));
+  int32_t *K = (int32_t *)calloc((size_t)V, sizeof(int32_t));
+  if (!G || !Wa || !Sa || !Sabs || !tau || !K) {
+    free(G); free(Wa); free(Sa); free(Sabs); free(tau); free(K);
+    return -2;
+  }
+  int rc = setup_all(G, n, mu, log_scale, quat, amp, relax, &g, (real_t)cutoff, nthreads);
+  real_t c2 = (real_t)cutoff * (real_t)cutoff;
+  real_t margin = INFINITY;
+  if (rc == 0) {
+#pragma omp parallel num_threads(nthreads) reduction(min : margin)
+    {
+      int T = omp_get_num_threads(), t = omp_get_thread_num();
+      int z0 = (int)((int64_t)nz * t / T), z1 = (int)((int64_t)nz * (t + 1) / T);
+      for (int64_t i = 0; i < n; ++i) {
+        const og_gauss_t *Gi = &G[i];
+        if (Gi->lo[0] > Gi->hi[0] || Gi->lo[1] > Gi->hi[1] || Gi->lo[2] > Gi->hi[2]) continue;
+        int za = Gi->lo[2] > z0 ? Gi->lo[2] : z0;
+        int zb = Gi->hi[2] < z1 - 1 ? Gi->hi[2] : z1 - 1;
+        if (za > zb) continue;
+        real_t Pabs[3][3], Dmax;
+        abs_frame(Gi, Pabs, &Dmax);
+        for (int iz = za; iz <= zb; ++iz)
+          for (int iy = Gi->lo[1]; iy <= Gi->hi[1]; ++iy)
+            for (int ix = Gi->lo[0]; ix <= Gi->hi[0]; ++ix) {
+              real_t d[3], e[3];
+              real_t d2 = maha2(Gi, &g, ix, iy, iz, d);
+              real_t D2 = pair_d2_err(Gi, &g, Pabs, Dmax, ix, iy, iz, d, e);
+              real_t m = R_FABS(d2 - c2) - D2;
+              if (m < margin) margin = m;
+              if (d2 <= c2) {
+                real_t w = Gi->r * R_EXP(-d2 / 2);
+                int64_t v = vidx(&g, ix, iy, iz);
+                real_t tp = (real_t)0.505 * D2 + 3 * OG_U;
+                Wa[v] += w;
+                Sa[v] += Gi->A * w;
+                Sabs[v] += R_FABS(Gi->A * w);
+                if (tp > tau[v]) tau[v] = tp;
+                K[v] += 1;
+              }
+            }
+      }
+    }
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t v = 0; v < V; ++v) {
+      real_t gk = gam((real_t)K[v]), tv = tau[v];
+      real_t bw = (tv + gk * (1 + tv)) * Wa[v];
+      real_t bs = (tv + OG_U + gk * (1 + tv + OG_U)) * Sabs[v];
+      real_t I = Sa[v] / (Wa[v] + (real_t)eps);
+      real_t bi = (bs + R_FABS(I) * bw) / (Wa[v] + (real_t)eps) + 2 * OG_U * R_FABS(I);
+      bW[v] = (double)(bw * (1 + (real_t)1e-9));
+      bI[v] = (double)(bi * (1 + (real_t)1e-9));
+    }
+  }
+  if (min_margin) *min_margin = (double)margin;
+  free(G); free(Wa); free(Sa); free(Sabs); free(tau); free(K);
+  return rc;
+}
+
+/* |J| x for the chain rule of og_grad (from the brick sums to d_mu, d_log_scale, d_quat), with
+ * every signed quantity replaced by its magnitude (and the rotation entries by |R| + 16 u, which
+ * covers their own rounding): an upper bound of the map's absolute value applied to the nonnegative
+ * vector x = (x_sk[3], x_M[3][3]).  out: d_mu 3, d_log_scale 3, d_quat 4. */
+static void chain_abs(const og_gauss_t *G, const real_t xsk[3], const real_t xM[3][3], real_t out[10]) {
+  real_t Ra[3][3], D[3], Pa[3][3], qa[4];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Ra[a][b] = R_FABS(G->R[a][b]) + 16 * OG_U;
+  for (int k = 0; k < 3; ++k) D[k] = 1 / G->ev[k];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      real_t s = 0;
+      for (int k = 0; k < 3; ++k) s += Ra[a][k] * D[k] * Ra[b][k];
+      Pa[a][b] = s;
+    }
+  for (int k = 0; k < 4; ++k) qa[k] = R_FABS(G->qhat[k]) + 4 * OG_U;
+  for (int a = 0; a < 3; ++a) {
+    real_t s = 0;
+    for (int b = 0; b < 3; ++b) s += Pa[a][b] * xsk[b];
+    out[a] = s;
+  }
+  real_t xG[3][3], dR[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) xG[a][b] = xM[a][b] / 2;
+  for (int k = 0; k < 3; ++k) {
+    real_t s = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) s += Ra[a][k] * xG[a][b] * Ra[b][k];
+    out[3 + k] = 2 * D[k] * s;
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) {
+      real_t s = 0;
+      for (int b = 0; b < 3; ++b) s += xG[a][b] * Ra[b][k];
+      dR[a][k] = 2 * s * D[k];
+    }
+  real_t w = qa[0], x = qa[1], y = qa[2], z = qa[3];
+  real_t gw = 2 * (z * dR[0][1] + y * dR[0][2] + z * dR[1][0] + x * dR[1][2] + y * dR[2][0] + x * dR[2][1]);
+  real_t gx = 2 * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] + 2 * x * dR[1][1] + w * dR[1][2] + z * dR[2][0] +
+                   w * dR[2][1] + 2 * x * dR[2][2]);
+  real_t gy = 2 * (2 * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] + w * dR[2][0] +
+                   z * dR[2][1] + 2 * y * dR[2][2]);
+  real_t gz = 2 * (2 * z * dR[0][0] + w * dR[0][1] + x * dR[0][2] + w * dR[1][0] + 2 * z * dR[1][1] +
+                   y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+  real_t gq[4] = {gw, gx, gy, gz};
+  real_t dot = 0;
+  for (int k = 0; k < 4; ++k) dot += qa[k] * gq[k];
+  for (int k = 0; k < 4; ++k) out[6 + k] = (gq[k] + dot * qa[k]) / G->qnorm;
+}
+
+/* Error bound of og_grad's outputs for the selected Gaussians (the stage-wise gradient: I, W and
+ * dL/dI given exactly as doubles).  Per pair, the terms of the 11 sums and their relative errors:
+ *   cp = gI / (W + eps) (2 u), G = exp(-d^2/2) (0.505 D2 + 2 u), w = r G (+ u),
+ *   e = cp (A - I) (+ 2 u), kappa = e w (+ u); terms cp w, e G, kappa delta_a (+ u, and |kappa| e_a
+ *   from delta), kappa delta_a delta_b (+ 2 u, and |kappa| (e_a |delta_b| + |delta_a| e_b)).
+ * For each sum j: A_j = sum |t| and E_j = sum |dt| over its K terms; its error is at most
+ * B_j = E_j + gam(K) (A_j + E_j).  The chain rule (from the sums to the parameters) is linear in the
+ * sums with coefficients made of R, D and the normalised quaternion; its output error is at most
+ * |J| B + gam(60) |J| (A + B) (the second term: the chain's own roundings), with |J| as in
+ * chain_abs.  bound: [n][12] per Gaussian, in the order d_mu 3, d_log_scale 3, d_quat 4, d_amp,
+ * d_relax; rows not selected are left untouched.  *min_margin: see above. */
+int og_grad_bound(int64_t n, const float *mu, const float *log_scale, const float *quat, const float *amp,
+                  const float *relax, int nx, int ny, int nz, const double *origin, const double *spacing,
+                  double cutoff, double eps, const double *I, const double *W, const double *gI, int64_t nsel,
+                  const int64_t *sel, double *bound, double *min_margin, int nthreads) {
+  og_grid_t g;
+  make_grid(&g, nx, ny, nz, origin, spacing);
+  int64_t m = sel ? nsel : n;
+  int bad = 0;
+  real_t c2 = (real_t)cutoff * (real_t)cutoff;
+  real_t margin = INFINITY;
+  const real_t u = OG_U;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16) reduction(| : bad) reduction(min : margin)
+  for (int64_t k = 0; k < m; ++k) {
+    int64_t i = sel ? sel[k] : k;
+    og_gauss_t Gi;
+    if (i < 0 || i >= n || setup_gauss(&Gi, i, mu, log_scale, quat, amp, relax, &g, (real_t)cutoff) != 0) {
+      bad = 1;
+      continue;
+    }
+    real_t Pabs[3][3], Dmax;
+    abs_frame(&Gi, Pabs, &Dmax);
+    /* sums: 0 = dA, 1 = dr, 2..4 = kappa delta, 5..13 = kappa delta delta^T (3 x 3, row-major) */
+    real_t As[14], Es[14];
+    for (int j = 0; j < 14; ++j) As[j] = Es[j] = 0;
+    int64_t K = 0;
+    if (!(Gi.lo[0] > Gi.hi[0] || Gi.lo[1] > Gi.hi[1] || Gi.lo[2] > Gi.hi[2])) {
+      for (int iz = Gi.lo[2]; iz <= Gi.hi[2]; ++iz)
+        for (int iy = Gi.lo[1]; iy <= Gi.hi[1]; ++iy)
+          for (int ix = Gi.lo[0]; ix <= Gi.hi[0]; ++ix) {
+            real_t d[3], e[3];
+            real_t d2 = maha2(&Gi, &g, ix, iy, iz, d);
+            real_t D2 = pair_d2_err(&Gi, &g, Pabs, Dmax, ix, iy, iz, d, e);
+            real_t mg = R_FABS(d2 - c2) - D2;
+            if (mg < margin) margin = mg;
+            if (!(d2 <= c2)) continue;
+            ++K;
+            int64_t v = vidx(&g, ix, iy, iz);
+            real_t Gv = R_EXP(-d2 / 2);
+            real_t w = Gi.r * Gv;
+            real_t cp = (real_t)gI[v] / ((real_t)W[v] + (real_t)eps);
+            real_t ee = cp * (Gi.A - (real_t)I[v]);
+            real_t kap = ee * w;
+            real_t tG = (real_t)0.505 * D2 + 2 * u;
+            real_t rA = 2 * u + tG + u + u;          /* cp w */
+            real_t rr = 4 * u + tG + u;              /* e G */
+            real_t rk = 4 * u + tG + u + u;          /* kappa */
+            real_t t;
+            t = R_FABS(cp * w);
+            As[0] += t;
+            Es[0] += rA * t;
+            t = R_FABS(ee * Gv);
+            As[1] += t;
+            Es[1] += rr * t;
+            for (int a = 0; a < 3; ++a) {
+              t = R_FABS(kap * d[a]);
+              As[2 + a] += t;
+              Es[2 + a] += (rk + u) * t + R_FABS(kap) * e[a];
+              for (int b = 0; b < 3; ++b) {
+                t = R_FABS(kap * d[a] * d[b]);
+                As[5 + 3 * a + b] += t;
+                Es[5 + 3 * a + b] += (rk + 2 * u) * t + R_FABS(kap) * (e[a] * R_FABS(d[b]) + R_FABS(d[a]) * e[b]);
+              }
+            }
+          }
+    }
+    real_t gk = gam((real_t)K);
+    real_t B[14], AB[14];
+    for (int j = 0; j < 14; ++j) {
+      B[j] = Es[j] + gk * (As[j] + Es[j]);
+      AB[j] = As[j] + B[j];
+    }
+    real_t oB[10], oAB[10];
+    real_t xM[3][3], xMA[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        xM[a][b] = B[5 + 3 * a + b];
+        xMA[a][b] = AB[5 + 3 * a + b];
+      }
+    chain_abs(&Gi, B + 2, xM, oB);
+    chain_abs(&Gi, AB + 2, xMA, oAB);
+    real_t gc = gam(60);
+    for (int j = 0; j < 10; ++j) bound[12 * i + j] = (double)((oB[j] + gc * oAB[j]) * (1 + (real_t)1e-9));
+    bound[12 * i + 10] = (double)(B[0] * (1 + (real_t)1e-9));
+    bound[12 * i + 11] = (double)(B[1] * (1 + (real_t)1e-9));
+  }
+  if (min_margin) *min_margin = (double)margin;
+  return bad ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * Forward with the inclusion of every ambiguous pair left open.  A pair with
+ * |d^2 - cutoff^2| <= band may be included or excluded (an FP32 and an FP64 evaluation of d^2 can
+ * disagree there, and both are correct readings of the 3-sigma truncation).  Per voxel with k such
+ * pairs (k <= maxk), Ilo/Ihi and Wlo/Whi receive the minimum and maximum of I and W over all 2^k
+ * include/exclude choices, the other pairs being decided as og_render decides them; voxels with no
+ * ambiguous pair get lo = hi = og_render's value; voxels with k > maxk get lo = -inf, hi = +inf.
+ * namb (may be NULL) receives k per voxel.  Returns the number of voxels with k > maxk, or a
+ * negative code. */
+int64_t og_render_envelope(int64_t n, const float *mu, const float *log_scale, const float *quat, const float *amp,
+                           const float *relax, int nx, int ny, int nz, const double *origin, const double *spacing,
+                           double cutoff, double eps, double band, int maxk, double *Ilo, double *Ihi, double *Wlo,
+                           double *Whi, int32_t *namb, int nthreads) {
+  og_grid_t g;
+  make_grid(&g, nx, ny, nz, origin, spacing);
+  int64_t V = (int64_t)nx * ny * nz;
+  real_t c2 = (real_t)cutoff * (real_t)cutoff, bd = (real_t)band;
+  og_gauss_t *G = (og_gauss_t *)malloc(sizeof(og_gauss_t) * (size_t)(n > 0 ? n : 1));
+  real_t *W0 = (real_t *)calloc((size_t)V, sizeof(real_t));
+  real_t *S0 = (real_t *)calloc((size_t)V, sizeof(real_t));
+  int32_t *cnt = (int32_t *)calloc((size_t)V, sizeof(int32_t));
+  int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(V + 1));
+  if (!G || !W0 || !S0 || !cnt || !start) {
+    free(G); free(W0); free(S0); free(cnt); free(start);
+    return -2;
+  }
+  /* the index box is widened so that pairs just outside the cutoff are seen */
+  int rc = setup_all(G, n, mu, log_scale, quat, amp, relax, &g, R_SQRT(c2 + bd), nthreads);
+  if (rc != 0) {
+    free(G); free(W0); free(S0); free(cnt); free(start);
+    return rc;
+  }
+  /* pass 1: the sums over the decided pairs, and the number of open pairs per voxel */
+#pragma omp parallel num_threads(nthreads)
+  {
+    int T = omp_get_num_threads(), t = omp_get_thread_num();
+    int z0 = (int)((int64_t)nz * t / T), z1 = (int)((int64_t)nz * (t + 1) / T);
+    for (int64_t i = 0; i < n; ++i) {
+      const og_gauss_t *Gi = &G[i];
+      if (Gi->lo[0] > Gi->hi[0] || Gi->lo[1] > Gi->hi[1] || Gi->lo[2] > Gi->hi[2]) continue;
+      int za = Gi->lo[2] > z0 ? Gi->lo[2] : z0;
+      int zb = Gi->hi[2] < z1 - 1 ? Gi->hi[2] : z1 - 1;
+      for (int iz = za; iz <= zb; ++iz)
+        for (int iy = Gi->lo[1]; iy <= Gi->hi[1]; ++iy)
+          for (int ix = Gi->lo[0]; ix <= Gi->hi[0]; ++ix) {
+            real_t d[3];
+            real_t d2 = maha2(Gi, &g, ix, iy, iz, d);
+            int64_t v = vidx(&g, ix, iy, iz);
+            if (R_FABS(d2 - c2) <= bd) {
+              cnt[v] += 1;
+            } else if (d2 <= c2) {
+              real_t w = Gi->r * R_EXP(-d2 / 2);
+              W0[v] += w;
+              S0[v] += Gi->A * w;
+            }
+          }
+    }
+  }
+  start[0] = 0;
+  for (int64_t v = 0; v < V; ++v) start[v + 1] = start[v] + cnt[v];
+  int64_t total = start[V];
+  real_t *pw = (real_t *)malloc(sizeof(real_t) * (size_t)(total > 0 ? total : 1));
+  real_t *ps = (real_t *)malloc(sizeof(real_t) * (size_t)(total > 0 ? total : 1));
+  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(V > 0 ? V : 1));
+  if (!pw || !ps || !cur) {
+    free(G); free(W0); free(S0); free(cnt); free(start); free(pw); free(ps); free(cur);
+    return -2;
+  }
+  memcpy(cur, start, sizeof(int64_t) * (size_t)V);
+  /* pass 2: the open pairs' weights, per voxel in ascending Gaussian order */
+#pragma omp parallel num_threads(nthreads)
+  {
+    int T = omp_get_num_threads(), t = omp_get_thread_num();
+    int z0 = (int)((int64_t)nz * t / T), z1 = (int)((int64_t)nz * (t + 1) / T);
+    for (int64_t i = 0; i < n; ++i) {
+      const og_gauss_t *Gi = &G[i];
+      if (Gi->lo[0] > Gi->hi[0] || Gi->lo[1] > Gi->hi[1] || Gi->lo[2] > Gi->hi[2]) continue;
+      int za = Gi->lo[2] > z0 ? Gi->lo[2] : z0;
+      int zb = Gi->hi[2] < z1 - 1 ? Gi->hi[2] : z1 - 1;
+      for (int iz = za; iz <= zb; ++iz)
+        for (int iy = Gi->lo[1]; iy <= Gi->hi[1]; ++iy)
+          for (int ix = Gi->lo[0]; ix <= Gi->hi[0]; ++ix) {
+            real_t d[3];
+            real_t d2 = maha2(Gi, &g, ix, iy, iz, d);
+            if (R_FABS(d2 - c2) <= bd) {
+              int64_t v = vidx(&g, ix, iy, iz);
+              real_t w = Gi->r * R_EXP(-d2 / 2);
+              pw[cur[v]] = w;
+              ps[cur[v]] = Gi->A * w;
+              cur[v] += 1;
+            }
+          }
+    }
+  }
+  /* pass 3: extremes over the include/exclude choices */
+  int64_t skipped = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(+ : skipped)
+  for (int64_t v = 0; v < V; ++v) {
+    int k = cnt[v];
+    if (namb) namb[v] = k;
+    if (k > maxk) {
+      Ilo[v] = Wlo[v] = -INFINITY;
+      Ihi[v] = Whi[v] = INFINITY;
+      ++skipped;
+      continue;
+    }
+    real_t ilo = INFINITY, ihi = -INFINITY, wlo = INFINITY, whi = -INFINITY;
+    for (int64_t mask = 0; mask < ((int64_t)1 << k); ++mask) {
+      real_t Wv = W0[v], Sv = S0[v];
+      for (int j = 0; j < k; ++j)
+        if ((mask >> j) & 1) {
+          Wv += pw[start[v] + j];
+          Sv += ps[start[v] + j];
+        }
+      real_t Iv = Sv / (Wv + (real_t)eps);
+      if (Iv < ilo) ilo = Iv;
+      if (Iv > ihi) ihi = Iv;
+      if (Wv < wlo) wlo = Wv;
+      if (Wv > whi) whi = Wv;
+    }
+    Ilo[v] = (double)ilo;
+    Ihi[v] = (double)ihi;
+    Wlo[v] = (double)wlo;
+    Whi[v] = (double)whi;
+  }
+  free(G); free(W0); free(S0); free(cnt); free(start); free(pw); free(ps); free(cur);
+  return skipped;
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * Weights of one Gaussian with its support held fixed, over the padded index box of the support:
+ * the Gaussian (mu, log_scale, quat, amp, relax; one entry each) is weighed as in og_render, and
+ * the pair predicate d^2 <= cutoff^2 is taken with a second parameter set (mu0, log_scale0, quat0;
+ * one entry each) whose box is used.  Writes box[6] = (lo x, y, z, hi x, y, z) of that box and, if
+ * vox and w are not NULL and cap is at least the box's voxel count, the flat index (x fastest) and
+ * the weight (0 for a pair outside the support) of every box voxel in x-fastest order.  Returns the
+ * box's voxel count, or -1 for an invalid input.  (Finite differences of the loss in one parameter
+ * of one Gaussian change only these voxels.) */
+int64_t og_weights_box(const float *mu, const float *log_scale, const float *quat, const float *amp,
+                       const float *relax, const float *mu0, const float *log_scale0, const float *quat0, int nx,
+                       int ny, int nz, const double *origin, const double *spacing, double cutoff, int32_t *box,
+                       int64_t cap, int64_t *vox, double *w) {
+  og_grid_t g;
+  make_grid(&g, nx, ny, nz, origin, spacing);
+  og_gauss_t Gw, Gs;
+  float one = 1;
+  if (setup_gauss(&Gw, 0, mu, log_scale, quat, amp, relax, &g, (real_t)cutoff) != 0) return -1;
+  if (setup_gauss(&Gs, 0, mu0, log_scale0, quat0, &one, NULL, &g, (real_t)cutoff) != 0) return -1;
+  for (int k = 0; k < 3; ++k) {
+    box[k] = Gs.lo[k];
+    box[3 + k] = Gs.hi[k];
+  }
+  if (Gs.lo[0] > Gs.hi[0] || Gs.lo[1] > Gs.hi[1] || Gs.lo[2] > Gs.hi[2]) return 0;
+  int64_t cnt = (int64_t)(Gs.hi[0] - Gs.lo[0] + 1) * (Gs.hi[1] - Gs.lo[1] + 1) * (Gs.hi[2] - Gs.lo[2] + 1);
+  if (!vox || !w || cap < cnt) return cnt;
+  real_t c2 = (real_t)cutoff * (real_t)cutoff;
+  int64_t k = 0;
+  for (int iz = Gs.lo[2]; iz <= Gs.hi[2]; ++iz)
+    for (int iy = Gs.lo[1]; iy <= Gs.hi[1]; ++iy)
+      for (int ix = Gs.lo[0]; ix <= Gs.hi[0]; ++ix) {
+        real_t d[3];
+        vox[k] = vidx(&g, ix, iy, iz);
+        w[k] = maha2(&Gs, &g, ix, iy, iz, d) <= c2 ? (double)(Gw.r * R_EXP(-maha2(&Gw, &g, ix, iy, iz, d) / 2)) : 0.0;
+        ++k;
+      }
+  return cnt;
 }

@@ -168,7 +168,7 @@ static int check_opts(const gs_opts_t *opts) {
   if (!brick_supported(opts->bx, opts->by, opts->bz))
     return fail(GS_ERR_UNSUPPORTED, "brick %dx%dx%d not supported by this library", opts->bx, opts->by, opts->bz);
   if (!(opts->cutoff > 0.f) || !std::isfinite(opts->cutoff)) return fail(GS_ERR_INVALID_ARG, "cutoff must be > 0");
-  if (!(opts->eps >= 0.f) || !std::isfinite(opts->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be >= 0");
+  if (!(opts->eps > 0.f) || !std::isfinite(opts->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be > 0 and finite");
   if ((opts->flags & ~(uint32_t)GS_FLAG_FORWARD_ONLY) != 0) return fail(GS_ERR_INVALID_ARG, "unknown flags");
   return GS_OK;
 }

@@ -34,16 +34,25 @@ def condition(p: dict, grid: oracle.Grid, seed: int = 12345, band: float = BAND,
     return p
 
 
-def condition_obs(p: dict, grid: oracle.Grid, obs, f: int = 4, band: float = 1e-5):
-    """Observation without near-ties: the fit loss's gradient is sign(zmean(I) - obs), and where
-    |zmean(I) - obs| is at rounding level an FP32 and an FP64 render may take different signs (both
-    correct).  Such observation values are moved 2 * band away from the oracle's z-mean."""
+def condition_obs(p: dict, grid: oracle.Grid, obs, f: int = 4):
+    """Observation without sign ties: the fit loss's gradient is sign(zmean(I) - obs), and where
+    |zmean(I) - obs| is within the error a correct FP32 render may have in its z-mean
+    (``oracle.l1_sign_band``) either sign is correct.  Such observation values are moved to three
+    bands from the oracle's z-mean, on the side they were on (below it for an exact tie)."""
     I, _, _ = oracle.render(p, grid)
+    return condition_obs_from(I, obs, f)
+
+
+def condition_obs_from(I, obs, f: int = 4):
+    """``condition_obs`` given the oracle's forward I."""
     lr = oracle.zmean(I, f)
+    band = oracle.l1_sign_band(I, f)
     obs = np.array(obs, dtype=np.float32, copy=True)
     d = lr - obs.astype(np.float64)
-    near = np.abs(d) < band
-    obs[near] = (obs[near].astype(np.float64) - np.where(d[near] >= 0, 2 * band, -2 * band)).astype(np.float32)
+    near = np.abs(d) <= band
+    moved = lr[near] - np.where(d[near] >= 0, 3 * band[near], -3 * band[near])
+    obs[near] = moved.astype(np.float32)
+    assert not oracle.l1_sign_ties(I, obs, f).any()
     return obs
 
 

@@ -35,7 +35,7 @@ def test_invalid_arguments_are_rejected():
         with pytest.raises(gs.GSError) as e:
             gs.gs_workspace_size(10, bad, gs.Opts(), 10)
         assert e.value.code == gs.GS_ERR_INVALID_ARG
-    for bad in (gs.Opts(cutoff=0.0), gs.Opts(eps=-1.0), gs.Opts(cutoff=float("inf"))):
+    for bad in (gs.Opts(cutoff=0.0), gs.Opts(eps=-1.0), gs.Opts(eps=0.0), gs.Opts(cutoff=float("inf"))):
         with pytest.raises(gs.GSError) as e:
             gs.gs_workspace_size(10, g, bad, 10)
         assert e.value.code == gs.GS_ERR_INVALID_ARG

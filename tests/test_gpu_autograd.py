@@ -38,11 +38,13 @@ def test_autograd_matches_oracle_gradient():
 
 
 def test_autograd_matches_frozen_support_finite_differences():
-    """64 random parameter entries, h = 1e-3: the GPU gradient of L = <g, I> equals the central
-    difference of the oracle's FP64 forward with the support held fixed."""
+    """64 random parameter entries (every group, the relaxation factor included), h = 1e-3: the GPU
+    gradient of L = <g, I> equals the central difference of the oracle's FP64 forward with the
+    support held fixed."""
     from paper_2603_09621_amd import autograd
 
     p, grid = cases.small_case(43, dims=(32, 28, 20), n=300, ls_std=0.8, max_ratio=8.0)
+    p["relax"] = np.random.default_rng(43).uniform(0.4, 1.0, 300).astype(np.float32)
     g = np.random.default_rng(44).standard_normal(grid.shape)
     say("autograd vs finite differences", grid.shape)
     ts = _tensors(p)
@@ -52,7 +54,7 @@ def test_autograd_matches_frozen_support_finite_differences():
     rng = np.random.default_rng(45)
     h = 1e-3
     for _ in range(64):
-        k = ("mu", "log_scale", "quat", "amp")[rng.integers(4)]
+        k = oracle.GROUPS[rng.integers(len(oracle.GROUPS))]
         j = int(rng.integers(p[k].size))
         pp = {kk: vv.copy() for kk, vv in p.items()}
         pm = {kk: vv.copy() for kk, vv in p.items()}

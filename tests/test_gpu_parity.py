@@ -104,7 +104,7 @@ def test_plain_workload_forward_and_backward():
     gg = gpu_grads(g, ggrid, opts, bins, I, W, gI)
     Lo, go = oracle.mse_loss(Io, T)
     ref = oracle.grad(p, grid, Io, Wo, go)
-    for k in ("mu", "log_scale", "quat", "amp"):
+    for k in oracle.GROUPS:
         assert_grad_close(gg[k], ref[k], f"plain d_{k}")
         say(f"  d_{k} rel_l2 {rel_l2(gg[k], ref[k]):.2e}")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -264,7 +264,14 @@ def test_losses_match_oracle():
     gs.gs_loss_l1_zmean(It, Ot, grid, 4, g, loss, scratch)
     L1, g1 = oracle.fit_l1_loss(I, O)
     assert float(loss.item()) == pytest.approx(L1, rel=1e-5)
-    np.testing.assert_allclose(np64(g), g1, rtol=1e-6, atol=0)
+    # where |z-mean - obs| is within the FP32 error band of the z-mean either sign (or 0) is correct
+    ties = np.repeat(oracle.l1_sign_ties(I, O), 4, axis=0)
+    assert ties.sum() >= 12  # the three planted ties, 4 HR voxels each
+    got = np64(g)
+    np.testing.assert_allclose(got[~ties], g1[~ties], rtol=1e-6, atol=0)
+    gscale = 1.0 / (4 * O.size)
+    assert np.all(np.isin(np.round(got[ties] / gscale), [-1.0, 0.0, 1.0]))
+    np.testing.assert_allclose(np.abs(got[ties]), np.where(got[ties] == 0, 0, gscale), rtol=1e-6)
 
 
 def test_adam_matches_oracle():
@@ -348,9 +355,13 @@ def test_crowded_bricks_long_lists():
     assert_fwd_close(np64(I), Io, "crowded I")
     T = synth.uniform_volume(9, dims)
     _, go = oracle.mse_loss(Io, T)
-    gg = gpu_grads(g, ggrid, opts, bins, I, W, torch.from_numpy(go.astype(np.float32)).cuda())
-    ref = oracle.grad(p, grid, np64(I), np64(W), go.astype(np.float32).astype(np.float64))
-    for k in ("mu", "amp"):
+    # stage-wise: both sides take the oracle's forward and MSE adjoint (rounded to FP32)
+    I32, W32, g32 = (x.astype(np.float32) for x in (Io, Wo, go))
+    d = torch.device("cuda")
+    gg = gpu_grads(g, ggrid, opts, bins, torch.from_numpy(I32).to(d), torch.from_numpy(W32).to(d),
+                   torch.from_numpy(g32).to(d))
+    ref = oracle.grad(p, grid, I32.astype(np.float64), W32.astype(np.float64), g32.astype(np.float64))
+    for k in oracle.GROUPS:
         assert_grad_close(gg[k], ref[k], f"crowded d_{k}")
 
 
