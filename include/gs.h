@@ -18,7 +18,8 @@
  *  - Pointers named d_* or documented as "device" are device pointers (e.g. torch tensors on the
  *    GPU); pointers documented as "host" are host memory.  All floating-point data is FP32.
  *  - The caller owns every buffer, including workspaces; the library allocates no device memory
- *    and keeps no state between calls.
+ *    and keeps no state between calls (the one exception: the static scratch array behind
+ *    gs_render_fwd_noalloc, part of the library's code object on each GPU).
  *  - Every call is asynchronous on the given stream (a hipStream_t passed as void*; NULL = the null
  *    stream) unless documented as synchronising.  Host-detectable argument errors are returned at
  *    once; errors detected on the device (non-finite input, key-capacity overflow) are latched in
@@ -277,6 +278,28 @@ int gs_render_bwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const 
  * (each has its own Adam bias correction). */
 int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_batch_t *batch,
                       const gs_fit_opts_t *fo, const gs_bins_t *bins, const gs_fit_buffers_t *buf, void *stream);
+
+/* ---- rendering without allocation ------------------------------------------------------------ */
+
+/* Bytes of the static device scratch behind gs_render_fwd_noalloc (64 MiB), held by the library on
+ * every GPU it renders on until the process ends. */
+#define GS_STATIC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory or pass a workspace (code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation): gs_bin followed by gs_render_fwd
+ * (forward-only), with the binning workspace in the library's static scratch instead of a
+ * caller-owned one.  I (and W, may be NULL) are caller-owned device [nz][ny][nx] outputs, bitwise
+ * equal to those of gs_bin + gs_render_fwd on the same inputs.  Allocates nothing and does not
+ * synchronise.  The key capacity is whatever the scratch holds after the per-Gaussian and
+ * per-brick parts (about 2.3M keys for 20k Gaussians on 64x64x32); a set whose per-Gaussian and
+ * per-brick parts alone exceed GS_STATIC_SCRATCH_BYTES is rejected with GS_ERR_INVALID_ARG before
+ * anything is launched.  More keys than the capacity are detected on the device: I and W are then
+ * left unwritten and the status says overflow.  d_status (device, may be NULL) receives the
+ * binning's status block (key count, overflow, non-finite flags) when the call's work has run.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and must be serialised by the caller. */
+int gs_render_fwd_noalloc(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, float *I, float *W,
+                          gs_status_t *d_status, void *stream);
 
 /* ---- status, errors, profiling ---------------------------------------------------------------- */
 

@@ -299,6 +299,56 @@ static int64_t bricks_at(const gs_grid_t &g, int bx) {
   return (int64_t)((g.nx + bx - 1) / bx) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
 }
 
+// ---- static scratch for callers that cannot allocate ------------------------------------------------
+//
+// gs_render_fwd_noalloc keeps its binning workspace (forward-only layout) in this array.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol: its device address is looked up once per device, with that device
+// current, and only that address is ever passed to kernels.  Nothing in the array has to start at
+// zero: the binning writes every part of the workspace it later reads, the status block included.
+static __device__ __align__(256) unsigned char scratch[GS_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_at[kMaxDevices];
+
+static int static_scratch(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+    if (!p) return fail(GS_ERR_HIP, "hipGetSymbolAddress(static scratch) returned NULL");
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return GS_OK;
+}
+
+// The largest key capacity whose forward-only layout fits the static scratch (-1: not even with 0).
+static int64_t static_key_capacity(int64_t n, int64_t nbricks) {
+  if (make_layout(n, nbricks, 0, false).total > GS_STATIC_SCRATCH_BYTES) return -1;
+  int64_t lo = 0, hi = GS_STATIC_SCRATCH_BYTES / (4 * 7);
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (make_layout(n, nbricks, mid, false).total <= GS_STATIC_SCRATCH_BYTES) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_copy_status(const DevStatus *src, gs_status_t *dst) {
+  if (threadIdx.x == 0) {
+    dst->n_keys = src->n_keys;
+    dst->overflow = src->overflow;
+    dst->nonfinite = src->nonfinite;
+  }
+}
+
 }  // namespace gs
 
 using namespace gs;
@@ -555,6 +605,37 @@ int gs_fit_step(const gs_fit_state_t *st, const float *lr_obs, const gs_fit_opts
   if (!fo) return fail(GS_ERR_INVALID_ARG, "fit opts are required");
   Single one(st ? st->n : 0, &fo->hr);
   return gs_fit_step_batch(st, lr_obs, &one.b, fo, bins, buf, stream);
+}
+
+int gs_render_fwd_noalloc(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, float *I, float *W,
+                          gs_status_t *d_status, void *stream) {
+  Single one(g ? g->n : 0, grid);
+  ScanTable T;
+  int rc;
+  if ((rc = make_table(&one.b, opts, 0, &T)) || (rc = bind_gaussians(g, &one.b, &T))) return rc;
+  if (!I) return fail(GS_ERR_INVALID_ARG, "I is NULL");
+  const int64_t cap = static_key_capacity(T.n_total, T.nbricks_total);
+  if (cap < 0)
+    return fail(GS_ERR_INVALID_ARG,
+                "%lld Gaussians on %lld bricks need %zu bytes of workspace before any key; the static scratch "
+                "holds %llu bytes",
+                (long long)T.n_total, (long long)T.nbricks_total, make_layout(T.n_total, T.nbricks_total, 0, false).total,
+                (unsigned long long)GS_STATIC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  if ((rc = static_scratch(&ws))) return rc;
+  gs_opts_t o = *opts;
+  o.flags |= GS_FLAG_FORWARD_ONLY;
+  const gs_bins_t bins{ws, (size_t)GS_STATIC_SCRATCH_BYTES, cap};
+  const WsLayout L = make_layout(T.n_total, T.nbricks_total, cap, false);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = bin_all(g, T, &o, &bins, L, s))) return rc;
+  hipError_t e = launch_fwd(T, o.bx, o.cutoff, o.eps, ws, L, I, W, s);
+  if (e != hipSuccess) return hip_fail(e, "render_fwd");
+  if (d_status) {
+    k_copy_status<<<1, 64, 0, s>>>((const DevStatus *)((char *)ws + L.status), d_status);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "copy_status");
+  }
+  return GS_OK;
 }
 
 int gs_status(const gs_bins_t *bins, void *stream, gs_status_t *out) {

@@ -25,6 +25,7 @@ if not os.path.exists(LIB_PATH):
                       "or `python paper_2603_09621_amd/build.py`")
 _lib = ctypes.CDLL(LIB_PATH)
 
+GS_STATIC_SCRATCH_BYTES = 64 << 20  # the header's GS_STATIC_SCRATCH_BYTES
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_NONFINITE, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 _ERR_NAMES = {-1: "INVALID_ARG", -2: "CAPACITY", -3: "NONFINITE", -4: "HIP", -5: "UNSUPPORTED"}
 
@@ -109,6 +110,7 @@ _sigs = {
     "gs_adam_step": [_P(gs_fit_state_t), _P(gs_grads_t), _P(gs_adam_t), _P(gs_bins_t), _vp],
     "gs_fit_step": [_P(gs_fit_state_t), _vp, _P(gs_fit_opts_t), _P(gs_bins_t), _P(gs_fit_buffers_t), _vp],
     "gs_status": [_P(gs_bins_t), _vp, _P(gs_status_t)],
+    "gs_render_fwd_noalloc": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _vp, _vp, _vp, _vp],
     "gs_workspace_size_batch": [_P(gs_batch_t), _P(gs_opts_t), ctypes.c_int64, _P(ctypes.c_size_t)],
     "gs_bin_query_batch": [_P(gs_gaussians_t), _P(gs_batch_t), _P(gs_opts_t), _P(gs_bins_t), _vp,
                            _P(ctypes.c_int64)],
@@ -370,6 +372,24 @@ def gs_render_fwd(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, I: torch.Ten
                   stream=None) -> None:
     _check(_lib.gs_render_fwd(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
                               ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _stream(stream)))
+
+
+def gs_render_fwd_noalloc(g: Gaussians, grid: Grid, opts: Opts, I: torch.Tensor, W: Optional[torch.Tensor] = None,
+                          status: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Bin + forward with the binning workspace in the library's static device scratch.  status: an
+    optional device int64 tensor of 2 entries receiving the gs_status_t block (n_keys, then overflow
+    and nonfinite as two int32 in the second entry)."""
+    if status is not None and (status.dtype != torch.int64 or status.numel() < 2 or not status.is_contiguous()):
+        raise ValueError("status must be a contiguous int64 tensor of at least 2 entries")
+    _check(_lib.gs_render_fwd_noalloc(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
+                                      _ptr(_f32(I)), _ptr(_f32(W)), _ptr(status), _stream(stream)))
+
+
+def unpack_status(status: torch.Tensor) -> dict:
+    """The gs_status_t block written by gs_render_fwd_noalloc, read back to the host."""
+    v = status[:2].cpu()
+    flags = int(v[1])
+    return {"n_keys": int(v[0]), "overflow": flags & 0xFFFFFFFF, "nonfinite": (flags >> 32) & 0xFFFFFFFF}
 
 
 def gs_count_pairs(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, out: torch.Tensor, stream=None) -> None:

@@ -121,3 +121,20 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "libgs.so is missing" in r.stderr
+
+
+def test_noalloc_rejects_sets_beyond_the_static_scratch():
+    """The no-allocation render refuses, before touching any device, a set whose per-Gaussian
+    workspace alone exceeds the static scratch (the pointers are never dereferenced)."""
+    fake = ctypes.c_void_p(256)
+    n = 2_000_000  # 2M x (48 + 32 + 4 + 32) B of records, offsets and run cache > 64 MiB
+    g = gs.gs_gaussians_t(n, fake, fake, fake, fake, None)
+    grid = gs.Grid(64, 64, 32).c()
+    opts = gs.Opts().c()
+    rc = gs._lib.gs_render_fwd_noalloc(ctypes.byref(g), ctypes.byref(grid), ctypes.byref(opts), fake, None, None, None)
+    assert rc == gs.GS_ERR_INVALID_ARG
+    assert "static scratch" in gs.gs_last_error()
+    m = re.search(r"#define GS_STATIC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", open(os.path.join(ROOT, "include", "gs.h")).read())
+    assert m and gs.GS_STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+    rc = gs._lib.gs_render_fwd_noalloc(ctypes.byref(g), ctypes.byref(grid), ctypes.byref(opts), None, None, None, None)
+    assert rc == gs.GS_ERR_INVALID_ARG
