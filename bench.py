@@ -26,13 +26,58 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU lane-instructions per useful pair (forward: delta 3, quadratic form 9, cutoff
-# compare + select 2, exp2 counted as 4 issue slots, two accumulations 2; backward: delta 3,
-# P delta 9, d^2 3, compare/exp/select 6, t, dA, kappa 4, dmu 3, the six second moments 9, dr 1).
+# Algorithmic work per useful pair (voxel, Gaussian with d^2 <= 9), per-Gaussian constants hoisted
+# (the exponent's matrix pre-scaled, log2 r folded in):
+#  flops: forward 21 (delta, the quadratic form, exp2 and the two accumulations), backward 50 (delta,
+#  P delta, d^2, exp2, t, dA, kappa, dmu, the six second moments, dr);
+#  issue slots: forward 20, backward 38 (VALU instructions with exp2 charged 4 slots as a quarter-rate
+#  transcendental; compares and selects count).
+F_FWD, F_BWD = 21, 50
 C_FWD, C_BWD = 20, 38
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: FP32 VALU lane-instructions per second (non-packed).
+# MI355X published FP32 vector peak (packed FMA: 256 CU x 64 lanes x 4 flops x 2.4 GHz).
+FP32_PEAK_TFLOPS = 157.3
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: FP32 VALU lane-instructions per second (non-packed issue).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+
+
+def alu_roofline(name, ms, pairs, flops_per_pair, slots_per_pair, traffic=None):
+    """Flops per launch over the launch's mean duration against the FP32 vector peak, and the same
+    launch as issue slots against the non-packed VALU issue rate."""
+    tflops = pairs * flops_per_pair / (ms * 1e-3) / 1e12
+    tslots = pairs * slots_per_pair / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": name, "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+            "flops_per_pair": flops_per_pair, "ms": round(ms, 5),
+            "issue": {"achieved": round(tslots, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tlane-instr/s",
+                      "frac": round(tslots / VALU_PEAK_TOPS, 4), "slots_per_pair": slots_per_pair}}
+
+
+def hbm_fractions(kern, K, N, B, V, nLR, passes):
+    """Algorithmic HBM bytes per launch of the binning, reduction and Adam kernels (what each must
+    read and write once) over the launch's mean duration, against 8 TB/s."""
+    per_launch = {
+        # parameters 13 floats read; evaluation (48 B) + culling (32 B) records, key count, run cache
+        "prep_count": 52 * N + (48 + 32 + 4 + 32) * N,
+        # run cache + key offsets read; (brick id, Gaussian id) per key written
+        "emit": (32 + 4) * N + 8 * K,
+        # one digit histogram pass: brick ids read
+        "radix_hist": 4 * K,
+        # a scatter pass: brick ids and slots read and written (the last pass also reads the
+        # Gaussian id by slot: 4 B per key in one of the passes)
+        "radix_scatter": 16 * K + 4 * K / passes,
+        "brick_offsets": 4 * K + 4 * B,
+        # partials 48 B per key and key offsets read; 12 parameters, m, v read and written, the
+        # 12 gradients written
+        "reduce_adam": 48 * K + 4 * N + 12 * 4 * (3 + 3 + 1) * N,
+    }
+    out = {}
+    for k, b in per_launch.items():
+        if k in kern:
+            ms = kern[k]["avg_ms"]
+            gbs = b / (ms * 1e-3) / 1e9
+            out[k] = {"bytes": int(b), "ms": round(ms, 5), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def parse():
@@ -48,9 +93,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-scan comparison")
     ap.add_argument("--no-graph", action="store_true", help="skip timing the fit step replayed from a HIP graph")
-    ap.add_argument("--batch-steps", type=int, default=20, help="timed steps of the batched comparison")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--batch-steps", type=int, default=100, help="timed steps of the batched comparison")
+    ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="seconds of Poisson arrivals for the request-loop section (0: skip)")
+    ap.add_argument("--plain-reps", type=int, default=400,
+                    help="timed graph replays of the plain 64x64x32 / 20k render + gradient (0: skip)")
+    ap.add_argument("--no-cpu-aniso", action="store_true",
+                    help="skip timing the oracle on the anisotropic 2M-Gaussian render + gradient")
     ap.add_argument("--aniso-steps", type=int, default=5,
                     help="timed render+gradient steps of the anisotropic 2M-Gaussian workload (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -141,8 +190,17 @@ def batch_section(args, dev):
             gs.gs_fit_step(st1, o, fo1, b1, buf1)
 
     ms_plain = timed(plain_round, K)
+    # the plain path's time per scan (the catch-up steps below, timed scan by scan)
+    per_scan = np.zeros(len(plain))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in plain]
     for _ in range(K):  # the plain fits catch up with the batched one (W + 2K steps each)
-        plain_round()
+        for (x, st1, o, fo1, b1, buf1), (ea, eb) in zip(plain, evs):
+            ea.record(stream)
+            gs.gs_fit_step(st1, o, fo1, b1, buf1)
+            eb.record(stream)
+        torch.cuda.synchronize()
+        per_scan += [ea.elapsed_time(eb) for ea, eb in evs]
+    per_scan /= K
     for x, st1, o, fo1, b1, buf1 in plain:
         gs.gs_status(b1)
     off = batch.g_offsets
@@ -163,6 +221,82 @@ def batch_section(args, dev):
         "hip_graph": True,
         "bitwise_equal_to_plain": bool(equal),
         "ms_per_batched_step_eager": ms_eager / K,
+        "plain_ms_per_scan": [{"dims": d, "n": x.n, "ms": round(float(t), 4)}
+                              for d, x, t in sorted(zip(dims, sets, per_scan), key=lambda z: z[1].n)],
+    }
+
+
+def plain_section(args, dev):
+    """The plain render + gradient (64x64x32, 20k Gaussians, MSE against a U(0,1) target): one
+    repetition = bin, forward, MSE loss and dL/dI, backward with the reduction, captured once in a
+    HIP graph and replayed; per-replay times from HIP events on the replay stream (median, p99), and
+    the median of the same calls launched eagerly."""
+    import numpy as np
+    import torch
+
+    from paper_2603_09621_amd import gs, synth
+
+    p, T_np = synth.workload_plain(1, (64, 64, 32), 20000)
+    grid = gs.Grid(64, 64, 32)
+    opts = gs.Opts(bx=args.bx)
+    g = gs.Gaussians.from_numpy(p, device=dev)
+    T = torch.from_numpy(T_np).to(dev)
+    bins = gs.plan_bins(g, grid, opts, headroom=1.25)
+    I = torch.empty(grid.shape, dtype=torch.float32, device=dev)
+    W = torch.empty_like(I)
+    gI = torch.empty_like(I)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    scratch = torch.empty(gs.gs_loss_scratch_bytes(I.numel()), dtype=torch.uint8, device=dev)
+    grads = gs.Grads.empty(g.n, relax=g.relax is not None, device=dev)
+
+    def step():
+        gs.gs_bin(g, grid, opts, bins)
+        gs.gs_render_fwd(g, grid, opts, bins, I, W)
+        gs.gs_loss_mse(I, T, gI, loss, scratch)
+        gs.gs_render_bwd(g, grid, opts, bins, I, W, gI, grads)
+
+    for _ in range(5):
+        step()
+    gs.gs_status(bins)
+    ref = grads.mu.clone()
+    pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    gs.gs_count_pairs(g, grid, opts, bins, pairs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def per_rep(fn, reps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+
+    for _ in range(10):
+        graph.replay()
+    t_graph = per_rep(graph.replay, args.plain_reps)
+    same = bool(torch.equal(grads.mu, ref))
+    t_eager = per_rep(step, args.plain_reps)
+    gs.gs_status(bins)
+    U = int(pairs.item())
+    med = float(np.median(t_graph))
+    return {
+        "workload": "plain render + gradient: 64x64x32, 20000 Gaussians (mu ~ U(volume), log-scale ~ N(ln 1.5, 0.3), "
+                    "uniform rotations, A ~ U(0,1)), MSE vs U(0,1) target; bin + forward + loss + backward + reduction",
+        "reps": args.plain_reps,
+        "hip_graph": True,
+        "ms_median": med,
+        "ms_p99": float(np.percentile(t_graph, 99)),
+        "ms_median_eager": float(np.median(t_eager)),
+        "useful_pairs": U,
+        "evals_per_s": U / (med * 1e-3),
+        "replay_equals_eager": same,
     }
 
 
@@ -210,6 +344,24 @@ def aniso_section(args, dev):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / args.aniso_steps
     U = int(pairs.item())
+    cpu = None
+    if not args.no_cpu_aniso:
+        import numpy as np
+
+        import oracle
+
+        del bins, I, W, gI, scratch, grads
+        threads = oracle.default_threads()
+        print(f"[bench] oracle anisotropic render + gradient on {threads} host threads", file=sys.stderr, flush=True)
+        og = oracle.Grid(*dims)
+        c0 = time.perf_counter()
+        Io, Wo, _ = oracle.render(p, og, threads=threads)
+        _, go = oracle.mse_loss(Io, T_np)
+        oracle.grad(p, og, Io, Wo, go, threads=threads)
+        cpu_s = time.perf_counter() - c0
+        cpu = {"s_per_step": cpu_s, "cores": threads, "kind": "oracle", "evals_per_s": U / cpu_s,
+               "sample": "one FP64 forward + MSE + gradient of the full workload"}
+        del Io, Wo, go
     return {
         "workload": f"anisotropic render + gradient: HR {dims[0]}x{dims[1]}x{dims[2]}, {g.n} Gaussians (log-scale "
                     f"std 0.8, axis ratio <= 8, random rotations), MSE vs U(0,1) target; bin + forward + loss + "
@@ -220,6 +372,7 @@ def aniso_section(args, dev):
         "keys": st["n_keys"],
         "useful_pairs": U,
         "evals_per_s": U / (ms * 1e-3),  # useful pairs per second, as the headline value
+        "cpu_oracle": cpu,
     }
 
 
@@ -308,14 +461,35 @@ def main():
     fwd_ms = kern.get("render_fwd", {}).get("avg_ms", float("nan"))
     bwd_ms = kern.get("render_bwd", {}).get("avg_ms", float("nan"))
     U_step = U / args.steps
-    if bwd_ms >= fwd_ms:
-        dom, c, t_k = "render_bwd", C_BWD, bwd_ms
-    else:
-        dom, c, t_k = "render_fwd", C_FWD, fwd_ms
-    achieved = U_step * c / (t_k / 1e3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": traffic_from_profiles(dom, f"fit {dims[0]}x{dims[1]}x{dims[2]} n={args.n} bx={args.bx}")}
+    wl = f"fit {dims[0]}x{dims[1]}x{dims[2]} n={args.n} bx={args.bx}"
+    kernel_roofline = {
+        "render_fwd": alu_roofline("render_fwd", fwd_ms, U_step, F_FWD, C_FWD, traffic_from_profiles("render_fwd", wl)),
+        "render_bwd": alu_roofline("render_bwd", bwd_ms, U_step, F_BWD, C_BWD, traffic_from_profiles("render_bwd", wl)),
+    }
+    dom = "render_bwd" if bwd_ms >= fwd_ms else "render_fwd"
+    roofline = kernel_roofline[dom]
+
+    # evaluation counts at the state after the timed steps: how much of the issued work is useful
+    ev = torch.zeros(6, dtype=torch.int64, device=dev)
+    gs.gs_count_evals(g, grid, fo.opts, bins, ev)
+    ev = dict(zip(gs.EVAL_COUNTS, (int(x) for x in ev.cpu())))
+    K_end = status["n_keys"]
+    nvox = dims[0] * dims[1] * dims[2]
+    cull = {
+        "keys": K_end,
+        "useful_pairs": ev["useful_pairs"],
+        "brick_candidates_per_useful": round(K_end * fo.opts.bx * 32 / max(ev["useful_pairs"], 1), 3),
+        "fwd_evals_per_useful": round(ev["fwd_evals"] / max(ev["useful_pairs"], 1), 3),
+        "fwd_issued_per_useful": round(ev["fwd_issued"] / max(ev["useful_pairs"], 1), 3),
+        "bwd_evals_per_useful": round(ev["bwd_evals"] / max(ev["useful_pairs"], 1), 3),
+        "bwd_issued_per_useful": round(ev["bwd_issued"] / max(ev["useful_pairs"], 1), 3),
+        "bwd_box_rows_per_key": round(ev["bwd_box_rows"] / max(K_end, 1), 3),
+        "fwd_slot_evals_per_s": ev["fwd_evals"] / (fwd_ms * 1e-3),
+        "bwd_slot_evals_per_s": ev["bwd_evals"] / (bwd_ms * 1e-3),
+    }
+    nbricks = -(-dims[0] // fo.opts.bx) * -(-dims[1] // 8) * -(-dims[2] // 4)
+    passes = max(1, -(-max(1, (nbricks - 1).bit_length()) // 8))
+    hbm = hbm_fractions(kern, K_end, args.n, nbricks, nvox, nvox // 4, passes)
 
     # the same steps replayed from a HIP graph (one captured fit step per replay)
     ms_graph = None
@@ -345,28 +519,45 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- CPU baseline: the oracle on the host cores, one full fit step of the same workload -------
+    # ---- CPU baseline: the oracle on the host cores, full fit steps of the same workload ---------
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
         threads = oracle.default_threads()
-        print(f"[bench] oracle fit step on {threads} host threads", file=sys.stderr, flush=True)
+        print(f"[bench] oracle fit steps on {threads} host threads", file=sys.stderr, flush=True)
         og = oracle.Grid(*dims)
         lr = dict(zip(oracle.GROUPS, [float(np.float32(x)) for x in fo.adam.lr]))
-        mom = {k: np.zeros(np.shape(p[k])) for k in oracle.GROUPS}
-        vel = {k: np.zeros(np.shape(p[k])) for k in oracle.GROUPS}
+
+        def oracle_steps(k, nthreads):
+            """k fit steps from the workload's initial state; the time of each."""
+            mom = {key: np.zeros(np.shape(p[key])) for key in oracle.GROUPS}
+            vel = {key: np.zeros(np.shape(p[key])) for key in oracle.GROUPS}
+            cur, times = p, []
+            for s in range(k):
+                c0 = time.perf_counter()
+                _, newp, mom, vel, _ = oracle.fit_step(cur, lr_obs, og, mom, vel, s + 1, lr, threads=nthreads)
+                times.append(time.perf_counter() - c0)
+                cur = {key: np.asarray(v, np.float32) for key, v in newp.items()}
+            return times
+
         pairs0 = oracle.count_pairs(p, og, threads=threads)
-        c0 = time.perf_counter()
-        cur = p
-        for s in range(args.cpu_steps):
-            _, newp, mom, vel, _ = oracle.fit_step(cur, lr_obs, og, mom, vel, s + 1, lr, threads=threads)
-            cur = {k: np.asarray(v, np.float32) for k, v in newp.items()}
-        cpu_s = (time.perf_counter() - c0) / args.cpu_steps
+        times = oracle_steps(args.cpu_steps, threads)
+        cpu_s = float(np.median(times))
+        print("[bench] oracle fit step on 1 host thread", file=sys.stderr, flush=True)
+        one_s = oracle_steps(1, 1)[0]
         cpu = {"value": pairs0 / cpu_s, "unit": "evals/s", "cores": threads, "kind": "oracle",
-               "sample": f"{args.cpu_steps} FP64 fit step(s) (render, z-mean L1, gradient, Adam) of the full "
-                         f"{dims[0]}x{dims[1]}x{dims[2]} / {args.n}-Gaussian workload, "
-                         f"{pairs0} useful pairs per step, {cpu_s:.2f} s per step"}
+               "sample": f"median of {args.cpu_steps} FP64 fit steps (render, z-mean L1, gradient, Adam) of the full "
+                         f"{dims[0]}x{dims[1]}x{dims[2]} / {args.n}-Gaussian workload from its initial state, "
+                         f"{pairs0} useful pairs per step, {cpu_s:.2f} s per step on {threads} threads; "
+                         f"one step on 1 thread {one_s:.2f} s",
+               "s_per_step": cpu_s, "s_per_step_all": [round(x, 3) for x in times],
+               "s_per_step_1core": one_s, "value_1core": pairs0 / one_s}
+
+    plain = None
+    if args.plain_reps > 0:
+        print("[bench] plain 64x64x32 / 20k render + gradient", file=sys.stderr, flush=True)
+        plain = plain_section(args, dev)
 
     aniso = None
     if args.aniso_steps > 0:
@@ -414,7 +605,11 @@ def main():
         "replay_identical": replay_same,
         "kernels_avg_ms": {k: round(v["avg_ms"], 5) for k, v in sorted(kern.items())},
         "roofline": roofline,
+        "kernel_roofline": kernel_roofline,
+        "hbm_roofline": hbm,
+        "cull": cull,
         "cpu_baseline": cpu,
+        "plain": plain,
         "anisotropic": aniso,
         "batched": batched,
         "serving": serving,

@@ -214,6 +214,18 @@ int gs_render_fwd(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_
 int gs_count_pairs(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
                    int64_t *d_count, void *stream);
 
+/* Evaluation counts of the forward and backward kernels on these bins, for measurement (how much
+ * of the work they issue is useful).  d_counts: device int64[6], overwritten:
+ *   [0] useful pairs (voxel, Gaussian) with d^2 <= cutoff^2 (as gs_count_pairs);
+ *   [1] forward: (voxel, Gaussian) evaluations of real cell-list entries inside the grid;
+ *   [2] forward: issued lane-voxel slots (every lane of every list iteration, padding included);
+ *   [3] backward: voxel evaluations of the rows that pass the row test (BX per row);
+ *   [4] backward: issued lane-voxel slots (64 lanes x BX per row iteration a wave executes);
+ *   [5] backward: rows in the keys' voxel boxes.
+ * Same bins contract as gs_render_fwd. */
+int gs_count_evals(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                   int64_t *d_counts, void *stream);
+
 /* ---- backward (§3.3 gradient equations) ---------------------------------------------------- */
 
 /* Gradients of a loss L w.r.t. every Gaussian parameter, given the forward's I and W and

@@ -469,6 +469,18 @@ int gs_count_pairs(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts
   return gs_count_pairs_batch(g, &one.b, opts, bins, d_count, stream);
 }
 
+int gs_count_evals(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t *opts, const gs_bins_t *bins,
+                   int64_t *d_counts, void *stream) {
+  Single one(g ? g->n : 0, grid);
+  ScanTable T;
+  WsLayout L;
+  int rc = check_common(g, &one.b, opts, bins, 0, &T, &L);
+  if (rc) return rc;
+  if (!d_counts) return fail(GS_ERR_INVALID_ARG, "d_counts is NULL");
+  hipError_t e = launch_count_evals(T, opts->bx, opts->cutoff, bins->ws, L, d_counts, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "count_evals");
+}
+
 int gs_render_bwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const gs_opts_t *opts, const gs_bins_t *bins,
                         const float *I, const float *W, const float *dL_dI, const gs_grads_t *grads, void *stream) {
   ScanTable T;

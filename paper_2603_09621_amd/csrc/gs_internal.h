@@ -144,6 +144,10 @@ hipError_t launch_fwd(const ScanTable &T, int bx, float cutoff, float eps, const
                       float *I, float *W, hipStream_t s);
 hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
                               int64_t *d_count, hipStream_t s);
+// Evaluation counts (gs_count_evals): kEvalCounts int64 entries.
+constexpr int kEvalCounts = 6;
+hipError_t launch_count_evals(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
+                              int64_t *d_counts, hipStream_t s);
 hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
                       const float *I, const float *W, const float *dLdI, hipStream_t s);
 hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,

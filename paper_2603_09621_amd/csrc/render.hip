@@ -110,7 +110,8 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
                                                  const uint32_t *__restrict__ list_gid,
                                                  const uint32_t *__restrict__ brick_off, const DevStatus *st,
                                                  float *__restrict__ I, float *__restrict__ W,
-                                                 unsigned long long *__restrict__ pair_count) {
+                                                 unsigned long long *__restrict__ pair_count,
+                                                 unsigned long long *__restrict__ eval_count) {
   constexpr int NT = 32 * BX, NW = BX / 2, NQX = BX / 4;
   if (st->overflow) return;
   // srec[NT] is an empty record (threshold +inf: never a pair) that pads the cell lists; the lists
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
   __shared__ uint32_t smask[NT];
   __shared__ uint16_t wlist[NW][4][NT + 4];
   constexpr uint16_t kPad = (uint16_t)(NT * sizeof(EvalRec));
-  __shared__ unsigned long long scount[NW];
+  __shared__ unsigned long long scount[NW][3];
 
   const int64_t b = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_brick(b)];
@@ -147,7 +148,9 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
     srec[NT].r2 = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   float Wa[4] = {0.f, 0.f, 0.f, 0.f}, Sa[4] = {0.f, 0.f, 0.f, 0.f};
-  uint32_t npairs = 0;
+  // COUNT: useful pairs, evaluated voxel slots of real list entries inside the grid, issued slots
+  uint32_t npairs = 0, nevals = 0, nissued = 0;
+  const uint32_t row_vox = rowin ? (uint32_t)max(0, min(4, bg.nx - qx0)) : 0u;
   for (uint32_t c0 = start; c0 < end; c0 += NT) {
     const int cnt = (int)min((uint32_t)NT, end - c0);
     if (t < cnt) {
@@ -183,6 +186,10 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
     __syncthreads();
     const uint16_t *mylist = wlist[w][grp];
     for (int j0 = 0; j0 < n4; j0 += 4) {
+      if (COUNT) {
+        nevals += mylist[j0 + sub] != kPad ? row_vox : 0u;
+        nissued += 4u;
+      }
       const EvalRec R = *reinterpret_cast<const EvalRec *>(reinterpret_cast<const char *>(srec) + mylist[j0 + sub]);
       const float thr = R.r1.w;
       float dy, dz, bq, cq;
@@ -204,15 +211,19 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
     __syncthreads();
   }
   if (COUNT) {
-    unsigned long long v = npairs;
+    unsigned long long v[3] = {npairs, nevals, nissued};
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
-    if (l == 0) scount[w] = v;
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) v[c] += __shfl_down(v[c], d, 64);
+      if (l == 0) scount[w][c] = v[c];
+    }
     __syncthreads();
-    if (t == 0) {
+    if (t < 3) {
       unsigned long long tot = 0;
-      for (int k = 0; k < NW; ++k) tot += scount[k];
-      atomicAdd(pair_count, tot);
+      for (int k = 0; k < NW; ++k) tot += scount[k][t];
+      if (t == 0) atomicAdd(pair_count, tot);
+      else if (eval_count) atomicAdd(eval_count + (t - 1), tot);
     }
     return;
   }
@@ -244,7 +255,8 @@ __global__ void k_zero_u64(unsigned long long *p) {
 
 template <bool COUNT>
 static hipError_t fwd_dispatch(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
-                               float *I, float *W, unsigned long long *cnt, hipStream_t s) {
+                               float *I, float *W, unsigned long long *cnt, hipStream_t s,
+                               unsigned long long *evals = nullptr) {
   const char *b = (const char *)ws;
   const unsigned nb = (unsigned)T.nbricks_total;
   if (nb == 0) return hipSuccess;
@@ -253,9 +265,9 @@ static hipError_t fwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
   const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *bo = (const uint32_t *)(b + L.brick_off);
   const DevStatus *st = (const DevStatus *)(b + L.status);
   switch (bx) {
-    case 4: k_fwd<4, COUNT><<<nb, 128, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt); break;
-    case 8: k_fwd<8, COUNT><<<nb, 256, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt); break;
-    default: k_fwd<16, COUNT><<<nb, 512, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt); break;
+    case 4: k_fwd<4, COUNT><<<nb, 128, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt, evals); break;
+    case 8: k_fwd<8, COUNT><<<nb, 256, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt, evals); break;
+    default: k_fwd<16, COUNT><<<nb, 512, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt, evals); break;
   }
   return hipGetLastError();
 }
@@ -361,7 +373,11 @@ __device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0,
   }
 }
 
-template <int BX, bool FIT>
+// Backward modes: plain (dL/dI given), fit (loss fused into the staging), count (the ordering and
+// the row tests only, counting evaluated and issued voxel slots; nothing is written but the counts).
+constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
+
+template <int BX, int MODE>
 __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cutoff, float eps,
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                      const uint32_t *__restrict__ list_gid,
@@ -370,7 +386,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
                                                      const float *__restrict__ gI, const float *__restrict__ obs,
                                                      float *__restrict__ loss_part, int64_t cap,
-                                                     float4 *__restrict__ part) {
+                                                     float4 *__restrict__ part,
+                                                     unsigned long long *__restrict__ eval_count) {
+  constexpr bool FIT = MODE == kBwdFit, COUNT = MODE == kBwdCount;
   constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
   // LDS voxels per brick, padded so that the same row of different bricks falls into different banks
   // (keys of similar boxes in the bricks read the same row index at the same time)
@@ -418,7 +436,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     if (t % 8 < 4) spz[t / 8][t % 8] = centre(bg.oz, bg.hz, zb + t % 8);
   }
   const uint32_t start = boff[0], end = boff[G];
-  if (FIT || start != end) {
+  // COUNT: voxel slots of rows passing the row test, issued lane-voxel slots, rows in the boxes
+  uint32_t c_eval = 0, c_issued = 0, c_rows = 0;
+  if (!COUNT && (FIT || start != end)) {
 #pragma unroll
     for (int j = 0; j < G; ++j)
       if (j < nbk)
@@ -426,6 +446,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   }
   __syncthreads();
   if (start == end) return;
+  (void)c_eval;
+  (void)c_issued;
+  (void)c_rows;
   int xe[G], ye[G], ze[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
@@ -512,6 +535,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       const int ny_k = yh - yl + 1;
       const int nrows = (box >> 12) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
+      if (COUNT) c_rows += (uint32_t)nrows;
       for (int r = 0; r < nrows; ++r) {
         const float py = sPy[iy], pz = sPz[iz];
         float dy, dz, bq, cq;
@@ -519,7 +543,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
         // the row's maximum of q (at dx* = -b / (2a)) is c - b^2 / (4a); rows whose maximum is
         // clearly below the cutoff hold no pair
         const float qmax = fmaf(-(bq * bq), inv4a, cq);
-        if (qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo)) {
+        const bool live = qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo);
+        if (COUNT) {
+          c_eval += live ? (uint32_t)BX : 0u;
+          c_issued += __ballot(live) != 0ull && lane_id() == __builtin_amdgcn_readfirstlane(lane_id())
+                          ? (uint32_t)(64 * BX)
+                          : 0u;
+        } else if (live) {
           const int rb = (iz * 8 + iy) * RP;
           // dx of voxel kk is dxc + ck h with ck = kk - (BX - 1) / 2 (offset from the row's centre):
           // the row sums of k dx and k dx^2 follow from m1 = sum ck k and m2 = sum ck^2 k
@@ -565,6 +595,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
           ++iz;
         }
       }
+      if (COUNT) continue;
       // back from row-centre offsets to dx: sum k dx = dxc sum k + h sum ck k, sum k dx^2 =
       // dxc^2 sum k + 2 dxc h sum ck k + h^2 sum ck^2 k, sum k dx d = dxc sum k d + h sum ck k d
       const float hx = bg.hx, dxc = fmaf(0.5f * (BX - 1), hx, px[0] - mx);
@@ -579,12 +610,25 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     }
     __syncthreads();
   }
+  if (COUNT) {
+    unsigned long long v[3] = {c_eval, c_issued, c_rows};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) v[c] += __shfl_down(v[c], d, 64);
+    }
+    if (t == 0) {
+      atomicAdd(eval_count + 0, v[0]);
+      atomicAdd(eval_count + 1, v[1]);
+      atomicAdd(eval_count + 2, v[2]);
+    }
+  }
 }
 
-template <bool FIT>
-static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+template <int MODE>
+static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
                                const float *I, const float *W, const float *gI, const float *obs, float *loss_part,
-                               hipStream_t s) {
+                               hipStream_t s, unsigned long long *evals = nullptr) {
   char *b = (char *)ws;
   const unsigned nb = (unsigned)T.ngroups_total;  // one wave per group of bricks
   if (nb == 0) return hipSuccess;
@@ -593,19 +637,19 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
   const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *ls = (const uint32_t *)(b + L.list_slot);
   const uint32_t *bo = (const uint32_t *)(b + L.brick_off);
   const DevStatus *st = (const DevStatus *)(b + L.status);
-  float4 *part = (float4 *)(b + L.partials);
+  float4 *part = MODE == kBwdCount ? nullptr : (float4 *)(b + L.partials);
   switch (bx) {
     case 4:
-      k_bwd<4, FIT><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
-                                               part);
+      k_bwd<4, MODE><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
+                                                part, evals);
       break;
     case 8:
-      k_bwd<8, FIT><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
-                                               part);
+      k_bwd<8, MODE><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
+                                                part, evals);
       break;
     default:
-      k_bwd<16, FIT><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part,
-                                                L.cap, part);
+      k_bwd<16, MODE><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part,
+                                                 L.cap, part, evals);
       break;
   }
   return hipGetLastError();
@@ -614,7 +658,7 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
 hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
                       const float *I, const float *W, const float *dLdI, hipStream_t s) {
   prof_begin(s);
-  hipError_t e = bwd_dispatch<false>(T, bx, cutoff, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
+  hipError_t e = bwd_dispatch<kBwdPlain>(T, bx, cutoff, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
   prof_end(s, "render_bwd");
   return e;
 }
@@ -622,8 +666,25 @@ hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void 
 hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
                           const float *I, const float *W, const float *obs, float *loss_part, hipStream_t s) {
   prof_begin(s);
-  hipError_t e = bwd_dispatch<true>(T, bx, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
+  hipError_t e = bwd_dispatch<kBwdFit>(T, bx, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
   prof_end(s, "render_bwd");
+  return e;
+}
+
+__global__ void k_zero_u64_n(unsigned long long *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_count_evals(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
+                              int64_t *d_counts, hipStream_t s) {
+  prof_begin(s);
+  unsigned long long *c = (unsigned long long *)d_counts;
+  k_zero_u64_n<<<1, 64, 0, s>>>(c, kEvalCounts);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = fwd_dispatch<true>(T, bx, cutoff, 0.f, ws, L, nullptr, nullptr, c, s, c + 1);
+  if (e == hipSuccess)
+    e = bwd_dispatch<kBwdCount>(T, bx, cutoff, 0.f, ws, L, nullptr, nullptr, nullptr, nullptr, nullptr, s, c + 3);
+  prof_end(s, "count_evals");
   return e;
 }
 

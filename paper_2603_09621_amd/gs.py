@@ -103,6 +103,7 @@ _sigs = {
     "gs_bin": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp],
     "gs_render_fwd": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp, _vp],
     "gs_count_pairs": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp],
+    "gs_count_evals": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp],
     "gs_render_bwd": [_P(gs_gaussians_t), _P(gs_grid_t), _P(gs_opts_t), _P(gs_bins_t), _vp, _vp, _vp,
                       _P(gs_grads_t), _vp],
     "gs_loss_mse": [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_size_t, _vp],
@@ -374,6 +375,17 @@ def gs_render_fwd(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, I: torch.Ten
                               ctypes.byref(bins.c()), _ptr(_f32(I)), _ptr(_f32(W)), _stream(stream)))
 
 
+EVAL_COUNTS = ("useful_pairs", "fwd_evals", "fwd_issued", "bwd_evals", "bwd_issued", "bwd_box_rows")
+
+
+def gs_count_evals(g: Gaussians, grid: Grid, opts: Opts, bins: Bins, out: torch.Tensor, stream=None) -> None:
+    """The six evaluation counts (``EVAL_COUNTS``) into a device int64 tensor of 6 entries."""
+    if out.dtype != torch.int64 or out.numel() < len(EVAL_COUNTS) or not out.is_contiguous():
+        raise ValueError("contiguous int64 tensor of 6 entries expected")
+    _check(_lib.gs_count_evals(ctypes.byref(g.c()), ctypes.byref(grid.c()), ctypes.byref(opts.c()),
+                               ctypes.byref(bins.c()), _ptr(out), _stream(stream)))
+
+
 def gs_render_fwd_noalloc(g: Gaussians, grid: Grid, opts: Opts, I: torch.Tensor, W: Optional[torch.Tensor] = None,
                           status: Optional[torch.Tensor] = None, stream=None) -> None:
     """Bin + forward with the binning workspace in the library's static device scratch.  status: an
@@ -532,7 +544,7 @@ def plan_bins_batch(g: Optional[Gaussians], batch: Batch, opts: Opts, headroom: 
 
 def concat(gs_: Sequence[Gaussians]) -> Gaussians:
     """One Gaussian set holding the given sets in order (the batch layout)."""
-    cat = lambda k: torch.cat([getattr(x, k) for x in gs_]).contiguous()  # noqa: E731
+    cat = lambda k: torch.cat([getattr(x, k).contiguous() for x in gs_])  # noqa: E731
     relax = None
     if any(x.relax is not None for x in gs_):
         relax = torch.cat([x.relax if x.relax is not None else torch.ones_like(x.amp) for x in gs_]).contiguous()

@@ -178,23 +178,32 @@ class Server:
         return ws + 4 * grid.size + _SLACK
 
     def prepare_fit(self, req: FitRequest) -> None:
-        """Key count and HBM footprint of a fit request (one synchronising count pass)."""
+        """Key count and HBM footprint of a fit request (one synchronising count pass).
+
+        A fit holds, for its whole life, its own parameters and Adam moments (12 + 24 floats per
+        Gaussian) and observation; while it runs, its share of the packed batch: a second copy of
+        parameters and moments, its gradients (48 floats per Gaussian), observation, I and W (and
+        dL/dI when the loss is not fused), the fit scratch, the binning workspace at its key count
+        times the headroom, and the count pass's probe workspace taken when the batch is planned."""
         g = gs.Gaussians.from_numpy(req.params, device=self.device)
         grid = gs.Grid(*req.dims)
         probe = gs.Bins(g.n, grid, self.fo.opts, 0, device=self.device)
         req.keys = gs.gs_bin_query(g, grid, self.fo.opts, probe)
         cap = max(1024, int(math.ceil(req.keys * self.fit_headroom)))
         ws = gs.gs_workspace_size(g.n, grid, self.fo.opts, cap)
-        per_gauss = 4 * 12 * 4  # parameters, two moments, gradients
-        vol = 8 * grid.size + 4 * req.lr_obs.size  # I, W, observation
-        req.footprint = ws + per_gauss * g.n + vol + gs.gs_fit_scratch_bytes(grid) + _SLACK
+        own = 4 * 36 * g.n + 4 * req.lr_obs.size
+        per_vox = 4 * (3 if self.fo.zdown != self.fo.opts.bz else 2)
+        packed = 4 * 48 * g.n + 4 * req.lr_obs.size + per_vox * grid.size + gs.gs_fit_scratch_bytes(grid)
+        req.footprint = own + packed + ws + probe.ws_bytes + _SLACK
 
     # ---- request loop ---------------------------------------------------------------------------
 
     def run(self, requests: Sequence, realtime: bool = True, clock: Callable[[], float] = time.perf_counter,
-            on_done: Optional[Callable] = None) -> dict:
+            on_done: Optional[Callable] = None, log: Optional[Callable[[str], None]] = None,
+            log_every: float = 15.0) -> dict:
         """Serve the requests (sorted by arrival time, in seconds from the start).  With realtime
-        False every request is queued at once (arrival times are then only the order)."""
+        False every request is queued at once (arrival times are then only the order).  log, if
+        given, receives a progress line every log_every seconds."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for i, r in enumerate(reqs):
             if r.rid < 0:
@@ -225,6 +234,8 @@ class Server:
         def now():
             return clock() - t0
 
+        next_log = log_every
+
         def finish(r):
             self.done.append(r)
             if on_done is not None:
@@ -234,6 +245,9 @@ class Server:
 
         while pending or queue or admitted_renders or fits or joining or rflight or fflight:
             t = now()
+            if log is not None and t >= next_log:
+                log(f"{t:.0f}s: {len(self.done)} done, {len(queue)} queued, {len(pending)} not yet arrived")
+                next_log += log_every
             while pending and pending[0].arrival <= t:
                 queue.append(pending.popleft())
             progressed = False
@@ -258,6 +272,9 @@ class Server:
                         r.t_done = tdone
                         self.used -= r.footprint
                         finish(r)
+                    views = v = None
+                # the batch's workspace and volume go now, not when these names are next rebound
+                del ev, batch_reqs, keep, st_host
                 progressed = True
             if fflight is not None and fflight[0].query():
                 ev, steps_host, chunk = fflight
@@ -283,6 +300,7 @@ class Server:
                             finish(f.req)
                     fits = [f for f in fits if f not in finished]
                     packed = None
+                    finished = f = None  # the finished fits' own tensors go now
                 progressed = True
 
             # ---- admit in arrival order while slots and memory allow
@@ -312,6 +330,7 @@ class Server:
                 if packed is None or repack or joining:
                     if packed is not None:
                         self._unpack(fits, packed)
+                        packed = None  # released before the new batch is built: never two at once
                     fits = fits + joining
                     joining = []
                     packed = self._pack(fits)
@@ -355,9 +374,15 @@ class Server:
             batch = gs.Batch([f.n for f in fits], [f.grid for f in fits])
             g = gs.concat([f.g for f in fits])
             st = gs.FitState(g, nscans=len(fits))
-            st.m.copy_(torch.cat([f.m[c * f.n:(c + w) * f.n] for c, w in GROUP_SLICES for f in fits]))
-            st.v.copy_(torch.cat([f.v[c * f.n:(c + w) * f.n] for c, w in GROUP_SLICES for f in fits]))
-            st.step.copy_(torch.cat([f.step for f in fits]))
+            off = batch.g_offsets
+            ntot = g.n
+            # slice by slice into the packed moments (no concatenated temporaries)
+            for k, f in enumerate(fits):
+                a, b = off[k], off[k + 1]
+                for c, w in GROUP_SLICES:
+                    st.m[c * ntot + w * a:c * ntot + w * b].copy_(f.m[c * f.n:(c + w) * f.n])
+                    st.v[c * ntot + w * a:c * ntot + w * b].copy_(f.v[c * f.n:(c + w) * f.n])
+                st.step[k:k + 1].copy_(f.step)
             obs = torch.cat([f.obs for f in fits])
             bins = gs.plan_bins_batch(g, batch, self.fo.opts, headroom=self.fit_headroom, stream=self.fstream)
             buf = gs.FitBuffers(g.n, batch, relax=True, device=self.device,
@@ -397,12 +422,20 @@ class Server:
     def report(self, wall: float) -> dict:
         out = {"completed": len(self.done), "wall_s": wall, "requests_per_s": len(self.done) / max(wall, 1e-9),
                "peak_hbm_bytes": self.peak_used, "budget_bytes": self.budget}
+        def stats(lat):
+            lat = np.asarray(lat)
+            return {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                    "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+                    "max_ms": float(lat.max() * 1e3)}
+
         for kind in ("render", "fit"):
-            lat = np.array([r.latency for r in self.done if r.kind == kind])
-            if lat.size:
-                out[kind] = {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-                             "max_ms": float(lat.max() * 1e3)}
+            lat = [r.latency for r in self.done if r.kind == kind]
+            if lat:
+                out[kind] = stats(lat)
+        scales = sorted({r.scale for r in self.done if r.kind == "render"})
+        if scales:
+            out["render_by_scale"] = {f"{sc:g}": stats([r.latency for r in self.done if r.kind == "render"
+                                                        and r.scale == sc]) for sc in scales}
         return out
 
 
@@ -440,7 +473,7 @@ def run_workload(duration: float = 120.0, rate: float = 50.0, budget_gib: float 
             reqs.append(FitRequest(p, lr, d, steps=fit_steps, arrival=t, footprint=fit_fp[a][0], keys=fit_fp[a][1]))
     torch.cuda.synchronize()
     say(f"serving {len(reqs)} requests over {duration:.0f}s")
-    rep = server.run(reqs, realtime=True)
+    rep = server.run(reqs, realtime=True, log=log)
     rep["workload"] = (f"{nsets} resident sets ({sum(s.n for s in sets)} Gaussians), Poisson arrivals at {rate:g}/s "
                        f"for {duration:g}s: 90% renders at scales 2, 2.5, 3, 4; 10% fits of {fit_steps} steps "
                        f"(scans of <= 200k Gaussians); HBM budget {budget_gib:g} GiB")

@@ -44,7 +44,17 @@ def test_brick_width_matches_oracle(bx):
         assert_fwd_close(np64(I), Io, f"bx{bx} I")
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
         gs.gs_count_pairs(g, ggrid, opts, bins, cnt)
-        assert int(cnt.item()) == oracle.count_pairs(p, grid)
+        U = oracle.count_pairs(p, grid)
+        assert int(cnt.item()) == U
+        # evaluation counts: the useful pairs again, and each kernel's evaluations between the
+        # useful pairs and what it issues
+        ev = torch.zeros(6, dtype=torch.int64, device="cuda")
+        gs.gs_count_evals(g, ggrid, opts, bins, ev)
+        u, fe, fi, be, bi, rows = (int(x) for x in ev.cpu())
+        K = gs.gs_status(bins)["n_keys"]
+        assert u == U
+        assert U <= fe <= fi and fe <= K * bx * 32
+        assert U <= be <= bi and be <= bx * rows and rows <= K * 32
         T = synth.uniform_volume(seed, dims)
         _, go = oracle.mse_loss(Io, T)
         I32, W32, g32 = (x.astype(np.float32) for x in (Io, Wo, go))

@@ -60,16 +60,19 @@ def _alone_fit(gs, p, lr, d, steps):
     return g, float(buf.loss.item())
 
 
-def _check(gs, server, reqs, sets):
+def _check(gs, server, reqs, sets, results=None):
+    """Every result (on the device, or copied to the host by the loop's on_done) bitwise equal to the
+    same request run alone."""
     assert len(server.done) == len(reqs)
     for r in reqs:
+        res = r.result if results is None else results[r.rid]
         if r.kind == "render":
             want = _alone_render(gs, sets[r.set_id], r.grid)
-            assert torch.equal(r.result.reshape(-1), want), f"render {r.rid} differs from the same render alone"
+            assert torch.equal(res.reshape(-1), want.to(res.device)), f"render {r.rid} differs from the same render alone"
         else:
             g, loss = _alone_fit(gs, r.params, r.lr_obs, r.dims, r.steps)
             for k in gs.GROUPS:
-                assert torch.equal(r.result[k], getattr(g, k)), f"fit {r.rid}: {k} differs from the fit alone"
+                assert torch.equal(res[k], getattr(g, k).to(res[k].device)), f"fit {r.rid}: {k} differs from the fit alone"
             assert r.loss == loss
 
 
@@ -104,11 +107,22 @@ def test_low_hbm_budget_forces_queueing():
             probe.prepare_fit(r)
             fps.append(r.footprint)
     budget = max(fps) + min(fps) // 2  # the largest request plus a little: requests must queue
-    server = serve.Server(sets, dims, hbm_budget=budget, fit_chunk=2)
+    server = serve.Server(sets, dims, hbm_budget=budget, fit_chunk=2, keep_results=False)
     say("serve low budget", budget, len(reqs))
-    rep = server.run(reqs, realtime=False)
-    say(rep)
+    results = {}
+
+    def to_host(r):  # results leave the device as they complete, so device memory is the loop's own
+        results[r.rid] = r.result.cpu() if r.kind == "render" else {k: v.cpu() for k, v in r.result.items()}
+
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    rep = server.run(reqs, realtime=False, on_done=to_host)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
+    say(rep, "device peak above the resident sets", peak)
     assert server.peak_used <= budget
+    assert peak <= budget, f"the loop held {peak} bytes of device memory at once, over its budget {budget}"
     waited = sum(1 for r in reqs if r.t_admit > 0.0005)
     assert waited >= len(reqs) // 2, "a low budget should hold most requests in the queue"
-    _check(gs, server, reqs, sets)
+    _check(gs, server, reqs, sets, results)
