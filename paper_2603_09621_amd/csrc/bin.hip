@@ -67,49 +67,103 @@ __device__ __forceinline__ bool make_records(int64_t i, const float *__restrict_
 // y-extent of the ellipsoid inside that slab; for each brick row the x-extent inside the row's y-slab
 // intersected with the x-extent inside the z-slab.  Every brick whose voxel centres fall in these
 // conservative ranges receives a key.  The keys come in runs of consecutive bricks along x (one run
-// per brick row): visit(first brick, length, index of the run's first key among the Gaussian's keys).
+// per brick row), numbered z-slab by z-slab and row by row.  The same three functions below serve the
+// per-lane enumeration of a Gaussian and the wave-wide one of a large Gaussian, so both give the
+// same runs.
 
-template <class Visit>
-__device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
-                                     Visit visit) {
-  if (c.c1.z == 0.f) return 0;  // invalid Gaussian: no keys
+// A Gaussian's voxel box and the slab-independent parts of its three projections.
+struct GaussBox {
+  int xl, xh, yl, yh, zl, zh;
+  SlabAxes kyz, kxz, kxy;
+  float tx, ty;
+};
+
+__device__ __forceinline__ bool gauss_box(const BrickGrid &bg, const EvalRec &e, const CullRec &c, float cutoff,
+                                          GaussBox &B) {
+  if (c.c1.z == 0.f) return false;  // invalid Gaussian: no keys
   const float mx = e.r0.x, my = e.r0.y, mz = e.r0.z;
   const float sxx = c.c0.x, syy = c.c0.y, szz = c.c0.z, sxy = c.c0.w, sxz = c.c1.x, syz = c.c1.y;
   const float ex = cutoff * __builtin_amdgcn_sqrtf(sxx), ey = cutoff * __builtin_amdgcn_sqrtf(syy),
               ez = cutoff * __builtin_amdgcn_sqrtf(szz);
-  const float tx = extent_tol(mx, ex, bg.hx), ty = extent_tol(my, ey, bg.hy), tz = extent_tol(mz, ez, bg.hz);
-  int xl, xh, yl, yh, zl, zh;
-  world_to_index(mx - ex - tx, mx + ex + tx, bg.ox, bg.ihx, bg.nx, xl, xh);
-  world_to_index(my - ey - ty, my + ey + ty, bg.oy, bg.ihy, bg.ny, yl, yh);
-  world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.ihz, bg.nz, zl, zh);
-  if (xl > xh || yl > yh || zl > zh) return 0;
-  // the slab-independent part of the three projections, shared by all slabs
-  const SlabAxes kyz = slab_axes(syy, szz, syz, cutoff), kxz = slab_axes(sxx, szz, sxz, cutoff),
-                 kxy = slab_axes(sxx, syy, sxy, cutoff);
+  B.tx = extent_tol(mx, ex, bg.hx);
+  B.ty = extent_tol(my, ey, bg.hy);
+  const float tz = extent_tol(mz, ez, bg.hz);
+  world_to_index(mx - ex - B.tx, mx + ex + B.tx, bg.ox, bg.ihx, bg.nx, B.xl, B.xh);
+  world_to_index(my - ey - B.ty, my + ey + B.ty, bg.oy, bg.ihy, bg.ny, B.yl, B.yh);
+  world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.ihz, bg.nz, B.zl, B.zh);
+  if (B.xl > B.xh || B.yl > B.yh || B.zl > B.zh) return false;
+  B.kyz = slab_axes(syy, szz, syz, cutoff);
+  B.kxz = slab_axes(sxx, szz, sxz, cutoff);
+  B.kxy = slab_axes(sxx, syy, sxy, cutoff);
+  return true;
+}
+
+// Brick z-slab kz of the box: the ellipsoid's voxel rows (y index range) and x extent inside it.
+__device__ __forceinline__ bool slab_part(const BrickGrid &bg, const EvalRec &e, const GaussBox &B, float cutoff,
+                                          int kz, int &yl2, int &yh2, float &xzlo, float &xzhi) {
+  const int za = max(B.zl, kz << bg.lbz), zb = min(B.zh, ((kz + 1) << bg.lbz) - 1);
+  const float Z0 = centre(bg.oz, bg.hz, za), Z1 = centre(bg.oz, bg.hz, zb);
+  float ylo, yhi;
+  if (!slab_extent(B.kyz, e.r0.y, e.r0.z, cutoff, Z0, Z1, B.ty, ylo, yhi)) return false;
+  if (!slab_extent(B.kxz, e.r0.x, e.r0.z, cutoff, Z0, Z1, B.tx, xzlo, xzhi)) return false;
+  world_to_index(ylo, yhi, bg.oy, bg.ihy, bg.ny, yl2, yh2);
+  yl2 = max(yl2, B.yl);
+  yh2 = min(yh2, B.yh);
+  return yl2 <= yh2;
+}
+
+// Brick row ky of that slab (ky within [yl2 >> lby, yh2 >> lby]): its run of bricks [kx0, kx1].
+__device__ __forceinline__ bool row_part(const BrickGrid &bg, const EvalRec &e, const GaussBox &B, float cutoff,
+                                         int ky, int yl2, int yh2, float xzlo, float xzhi, int &kx0, int &kx1) {
+  const int ya = max(yl2, ky << bg.lby), yb = min(yh2, ((ky + 1) << bg.lby) - 1);
+  const float Y0 = centre(bg.oy, bg.hy, ya), Y1 = centre(bg.oy, bg.hy, yb);
+  float xylo, xyhi;
+  if (!slab_extent(B.kxy, e.r0.x, e.r0.y, cutoff, Y0, Y1, B.tx, xylo, xyhi)) return false;
+  int xl2, xh2;
+  world_to_index(fmaxf(xzlo, xylo), fminf(xzhi, xyhi), bg.ox, bg.ihx, bg.nx, xl2, xh2);
+  xl2 = max(xl2, B.xl);
+  xh2 = min(xh2, B.xh);
+  if (xl2 > xh2) return false;
+  kx0 = xl2 >> bg.lbx;
+  kx1 = xh2 >> bg.lbx;
+  return true;
+}
+
+// Brick rows (z-slab, y-row pairs) of the box: the work items of the wave-wide enumeration.
+__device__ __forceinline__ uint32_t box_rows(const BrickGrid &bg, const GaussBox &B, uint32_t &nky) {
+  nky = (uint32_t)((B.yh >> bg.lby) - (B.yl >> bg.lby) + 1);
+  return nky * (uint32_t)((B.zh >> bg.lbz) - (B.zl >> bg.lbz) + 1);
+}
+
+// Run of box row r (row-major over (z-slab, y-row), the order of the per-lane enumeration); 0 keys
+// if the ellipsoid misses the row.
+__device__ __forceinline__ uint32_t box_row_run(const BrickGrid &bg, const EvalRec &e, const GaussBox &B, float cutoff,
+                                                uint32_t r, uint32_t nky, uint32_t &first) {
+  const uint32_t dz = r / nky;
+  const int kz = (B.zl >> bg.lbz) + (int)dz, ky = (B.yl >> bg.lby) + (int)(r - dz * nky);
+  int yl2, yh2, kx0, kx1;
+  float xzlo, xzhi;
+  if (!slab_part(bg, e, B, cutoff, kz, yl2, yh2, xzlo, xzhi)) return 0u;
+  if (ky < (yl2 >> bg.lby) || ky > (yh2 >> bg.lby)) return 0u;
+  if (!row_part(bg, e, B, cutoff, ky, yl2, yh2, xzlo, xzhi, kx0, kx1)) return 0u;
+  first = (uint32_t)((kz * bg.nby + ky) * bg.nbx + kx0);
+  return (uint32_t)(kx1 - kx0 + 1);
+}
+
+// Per-lane enumeration: visit(first brick, length, index of the run's first key among the Gaussian's
+// keys) for every run; returns the key count.
+template <class Visit>
+__device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, const GaussBox &B, float cutoff,
+                                     Visit visit) {
   uint32_t count = 0;
   // index ranges are non-negative, so shifts divide by the (power-of-two) brick shape
-  for (int kz = zl >> bg.lbz; kz <= zh >> bg.lbz; ++kz) {
-    int za = max(zl, kz << bg.lbz), zb = min(zh, ((kz + 1) << bg.lbz) - 1);
-    const float Z0 = centre(bg.oz, bg.hz, za), Z1 = centre(bg.oz, bg.hz, zb);
-    float ylo, yhi, xzlo, xzhi;
-    if (!slab_extent(kyz, my, mz, cutoff, Z0, Z1, ty, ylo, yhi)) continue;
-    if (!slab_extent(kxz, mx, mz, cutoff, Z0, Z1, tx, xzlo, xzhi)) continue;
+  for (int kz = B.zl >> bg.lbz; kz <= B.zh >> bg.lbz; ++kz) {
     int yl2, yh2;
-    world_to_index(ylo, yhi, bg.oy, bg.ihy, bg.ny, yl2, yh2);
-    yl2 = max(yl2, yl);
-    yh2 = min(yh2, yh);
-    if (yl2 > yh2) continue;
+    float xzlo, xzhi;
+    if (!slab_part(bg, e, B, cutoff, kz, yl2, yh2, xzlo, xzhi)) continue;
     for (int ky = yl2 >> bg.lby; ky <= yh2 >> bg.lby; ++ky) {
-      int ya = max(yl2, ky << bg.lby), yb = min(yh2, ((ky + 1) << bg.lby) - 1);
-      const float Y0 = centre(bg.oy, bg.hy, ya), Y1 = centre(bg.oy, bg.hy, yb);
-      float xylo, xyhi;
-      if (!slab_extent(kxy, mx, my, cutoff, Y0, Y1, tx, xylo, xyhi)) continue;
-      int xl2, xh2;
-      world_to_index(fmaxf(xzlo, xylo), fminf(xzhi, xyhi), bg.ox, bg.ihx, bg.nx, xl2, xh2);
-      xl2 = max(xl2, xl);
-      xh2 = min(xh2, xh);
-      if (xl2 > xh2) continue;
-      const int kx0 = xl2 >> bg.lbx, kx1 = xh2 >> bg.lbx;
+      int kx0, kx1;
+      if (!row_part(bg, e, B, cutoff, ky, yl2, yh2, xzlo, xzhi, kx0, kx1)) continue;
       const uint32_t row = (uint32_t)((kz * bg.nby + ky) * bg.nbx);
       visit(row + (uint32_t)kx0, (uint32_t)(kx1 - kx0 + 1), count);
       count += (uint32_t)(kx1 - kx0 + 1);
@@ -118,17 +172,46 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
   return count;
 }
 
+// Gaussians with more box rows than this are enumerated by the whole wave (one box row per lane)
+// in the count and the emit pass instead of by their own lane.
+constexpr uint32_t kWaveRows = 32;
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// The geometry of lane src's Gaussian, broadcast to the wave (only what the enumeration reads).
+__device__ __forceinline__ void broadcast_geometry(const EvalRec &e, const CullRec &c, int src, EvalRec &eb,
+                                                   CullRec &cb) {
+  eb.r0 = make_float4(readlane_f(e.r0.x, src), readlane_f(e.r0.y, src), readlane_f(e.r0.z, src), 0.f);
+  eb.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+  eb.r2 = eb.r1;
+  cb.c0 = make_float4(readlane_f(c.c0.x, src), readlane_f(c.c0.y, src), readlane_f(c.c0.z, src),
+                      readlane_f(c.c0.w, src));
+  cb.c1 = make_float4(readlane_f(c.c1.x, src), readlane_f(c.c1.y, src), readlane_f(c.c1.z, src), 0.f);
+}
+
 // Run cache: the count pass records each Gaussian's runs (up to kRuns of them, each a 32-bit word
 // (first scan-local brick << 4) | (length - 1) for runs of at most 16 bricks starting below 2^28 - 1),
 // ended by kRunEnd; a Gaussian whose runs do not fit is marked kRunRedo and the emit pass enumerates
 // it again.  The emit pass then expands the recorded runs instead of repeating the enumeration.
-constexpr uint32_t kRunEnd = 0xFFFFFFFFu, kRunRedo = 0xFFFFFFFEu;
+// A Gaussian with more than kWaveRows box rows is marked kRunWave instead: the emit pass enumerates it
+// with the whole wave.
+constexpr uint32_t kRunEnd = 0xFFFFFFFFu, kRunRedo = 0xFFFFFFFEu, kRunWave = 0xFFFFFFFDu;
 
 // Fused prep + count: records of Gaussian i (of the concatenated numbering; its parameters are
 // entry i - g0 of its scan's arrays), its key count cnt[i], its run cache entry and, per block of
 // kPrepThreads Gaussians, the block's key total bsum[block] (the first level of the count scan),
 // with bit 63 set if the block holds an invalid Gaussian.
-__global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, float cutoff,
+// (register use capped for 6 waves per SIMD: the wave-wide count keeps the records live)
+__global__ __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_prep_count(
+    const ScanTable T, float cutoff,
                                                              EvalRec *__restrict__ er, CullRec *__restrict__ cr,
                                                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
                                                              uint64_t *__restrict__ bsum,
@@ -141,10 +224,13 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, 
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   uint32_t c = 0;
+  bool wide = false;
+  int kscan = 0;
+  EvalRec e;
+  CullRec r;
   if (i < T.n_total) {
-    const ScanDesc &sd = T.s[T.of_gauss(i)];
-    EvalRec e;
-    CullRec r;
+    kscan = T.of_gauss(i);
+    const ScanDesc &sd = T.s[kscan];
     if (!make_records(i - sd.g0, sd.mu, sd.ls, sd.quat, sd.amp, sd.relax, cutoff, e, r)) sbad = 1;
     er[i] = e;
     cr[i] = r;
@@ -155,22 +241,48 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(const ScanTable T, 
     for (int k = 0; k < kRuns; ++k) rr[k] = kRunEnd;
     int nr = 0;
     bool redo = false;
-    c = enumerate_bricks(sd.bg, e, r, cutoff, [&](uint32_t first, uint32_t len, uint32_t) {
-      if (nr < kRuns && len <= 16u && first < 0x0FFFFFFFu) {
-        const uint32_t word = (first << 4) | (len - 1u);
+    GaussBox B;
+    if (gauss_box(sd.bg, e, r, cutoff, B)) {
+      uint32_t nky;
+      wide = box_rows(sd.bg, B, nky) > kWaveRows;
+      if (!wide)
+        c = enumerate_bricks(sd.bg, e, B, cutoff, [&](uint32_t first, uint32_t len, uint32_t) {
+          if (nr < kRuns && len <= 16u && first < 0x0FFFFFFFu) {
+            const uint32_t word = (first << 4) | (len - 1u);
 #pragma unroll
-        for (int k = 0; k < kRuns; ++k) rr[k] = nr == k ? word : rr[k];
-        ++nr;
-      } else {
-        redo = true;
-      }
-    });
-    if (redo) rr[0] = kRunRedo;
+            for (int k = 0; k < kRuns; ++k) rr[k] = nr == k ? word : rr[k];
+            ++nr;
+          } else {
+            redo = true;
+          }
+        });
+    }
+    if (wide) rr[0] = kRunWave;
+    else if (redo) rr[0] = kRunRedo;
     uint4 *rc = reinterpret_cast<uint4 *>(runs + (int64_t)kRuns * i);
 #pragma unroll
     for (int q = 0; q < kRuns / 4; ++q) rc[q] = make_uint4(rr[4 * q], rr[4 * q + 1], rr[4 * q + 2], rr[4 * q + 3]);
-    cnt[i] = c;
   }
+  // the wave's wide Gaussians, one after the other, counted by all lanes (a box row per lane)
+  for (uint64_t m = __ballot(wide); m; m &= m - 1) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    const BrickGrid &bg = T.s[__builtin_amdgcn_readlane(kscan, src)].bg;
+    EvalRec eb;
+    CullRec cb;
+    broadcast_geometry(e, r, src, eb, cb);
+    GaussBox B;
+    gauss_box(bg, eb, cb, cutoff, B);  // as on lane src: not empty
+    uint32_t nky;
+    const uint32_t nrows = box_rows(bg, B, nky);
+    uint32_t tot = 0;
+    for (uint32_t q = (uint32_t)lane_id(); q < nrows; q += 64) {
+      uint32_t first;
+      tot += box_row_run(bg, eb, B, cutoff, q, nky, first);
+    }
+    tot = wave_sum_u32(tot);
+    if (lane_id() == src) c = tot;
+  }
+  if (i < T.n_total) cnt[i] = c;
   uint64_t v = c;
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
@@ -277,9 +389,23 @@ hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns
 // Emit: the j-th key of Gaussian i is written at slot off[i] + j, with its scan's global brick id
 // (the last level of the count scan is done here: off[i] becomes the Gaussian's first slot).  A
 // block's Gaussians own a contiguous slot range; when it fits, the block assembles its keys in LDS
-// and writes the range out with consecutive threads on consecutive slots.
+// and writes the range out with consecutive threads on consecutive slots.  Wide Gaussians (kRunWave)
+// are expanded by the whole wave: each lane takes a box row, a wave prefix sum of the rows' run
+// lengths places the runs in row order.  The first radix pass's digit counts per sort tile come from
+// LDS counters (for a block whose range is not staged, from a second read of the range it wrote).
 
 constexpr int kEmitStage = 4096;  // keys staged per block (32 KB of LDS)
+
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, 64);
+    if (lane_id() >= d) incl += t;
+  }
+  total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  return incl - v;
+}
 
 __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float cutoff,
                                                        const EvalRec *__restrict__ er,
@@ -291,7 +417,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
                                                        int ntiles) {
   __shared__ uint32_t sbrick[kEmitStage], sgid[kEmitStage];
   __shared__ uint32_t wtot[kPrepThreads / 64];
-  __shared__ uint32_t tcnt[2][kRadix];  // digit counts of the (at most two) sort tiles the range meets
+  __shared__ uint32_t tcnt[2][kRadix];  // digit counts of (at most two) sort tiles
   if (st->overflow) return;
   const int64_t n = T.n_total;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
@@ -312,73 +438,114 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
   const uint32_t base = blk0 + woff + incl - c;
   if (i < n) off[i] = base;
   const bool staged = btot <= (uint32_t)kEmitStage;
-  if (i < n) {
-    const ScanDesc &sd = T.s[T.of_gauss(i)];
-    const uint32_t b0 = (uint32_t)sd.b0;
-    // the Gaussian's runs: from the run cache, or enumerated again if they did not fit there
-    auto for_runs = [&](auto &&visit) {
-      const uint4 *rc = reinterpret_cast<const uint4 *>(runs + (int64_t)kRuns * i);
-      uint32_t rr[kRuns];
-#pragma unroll
-      for (int q = 0; q < kRuns / 4; ++q) {
-        const uint4 v = rc[q];
-        rr[4 * q] = v.x;
-        rr[4 * q + 1] = v.y;
-        rr[4 * q + 2] = v.z;
-        rr[4 * q + 3] = v.w;
-      }
-      if (rr[0] == kRunRedo) {
-        enumerate_bricks(sd.bg, er[i], cr[i], cutoff, visit);
-      } else {
-        uint32_t j = 0;
-#pragma unroll
-        for (int k = 0; k < kRuns; ++k) {
-          if (rr[k] == kRunEnd) break;
-          const uint32_t len = (rr[k] & 15u) + 1u;
-          visit(rr[k] >> 4, len, j);
-          j += len;
-        }
-      }
-    };
+  // a run of keys of one Gaussian: to LDS when the block's range is staged, else straight to the slots
+  auto put_run = [&](uint32_t slot, uint32_t brick, uint32_t len, uint32_t gid) {
     if (staged) {
-      for_runs([&](uint32_t first, uint32_t len, uint32_t j0) {
-        for (uint32_t q = 0; q < len; ++q) {
-          sbrick[base - blk0 + j0 + q] = b0 + first + q;
-          sgid[base - blk0 + j0 + q] = (uint32_t)i;
-        }
-      });
+      for (uint32_t q = 0; q < len; ++q) {
+        sbrick[slot - blk0 + q] = brick + q;
+        sgid[slot - blk0 + q] = gid;
+      }
     } else {
-      for_runs([&](uint32_t first, uint32_t len, uint32_t j0) {
-        for (uint32_t q = 0; q < len; ++q) {
-          const int64_t slot = (int64_t)base + j0 + q;
-          if (slot < cap) {
-            key_brick[slot] = b0 + first + q;
-            key_gid[slot] = (uint32_t)i;
-            atomicAdd(&hist[(int64_t)((b0 + first + q) & (kRadix - 1)) * ntiles + slot / kSortTile], 1u);
-          }
+      for (uint32_t q = 0; q < len; ++q) {
+        if ((int64_t)(slot + q) < cap) {
+          key_brick[slot + q] = brick + q;
+          key_gid[slot + q] = gid;
         }
-      });
+      }
+    }
+  };
+  bool wide = false;
+  int kscan = 0;
+  if (i < n) {
+    kscan = T.of_gauss(i);
+    const ScanDesc &sd = T.s[kscan];
+    const uint32_t b0 = (uint32_t)sd.b0;
+    const uint4 *rc = reinterpret_cast<const uint4 *>(runs + (int64_t)kRuns * i);
+    uint32_t rr[kRuns];
+#pragma unroll
+    for (int q = 0; q < kRuns / 4; ++q) {
+      const uint4 v = rc[q];
+      rr[4 * q] = v.x;
+      rr[4 * q + 1] = v.y;
+      rr[4 * q + 2] = v.z;
+      rr[4 * q + 3] = v.w;
+    }
+    auto visit = [&](uint32_t first, uint32_t len, uint32_t j0) { put_run(base + j0, b0 + first, len, (uint32_t)i); };
+    if (rr[0] == kRunWave) {
+      wide = true;
+    } else if (rr[0] == kRunRedo) {  // runs that did not fit the cache: enumerated again
+      GaussBox B;
+      const EvalRec e = er[i];
+      if (gauss_box(sd.bg, e, cr[i], cutoff, B)) enumerate_bricks(sd.bg, e, B, cutoff, visit);
+    } else {
+      uint32_t j = 0;
+#pragma unroll
+      for (int k = 0; k < kRuns; ++k) {
+        if (rr[k] == kRunEnd) break;
+        const uint32_t len = (rr[k] & 15u) + 1u;
+        visit(rr[k] >> 4, len, j);
+        j += len;
+      }
     }
   }
-  if (!staged) return;  // uniform per block
-  tcnt[0][threadIdx.x] = 0u;
-  tcnt[1][threadIdx.x] = 0u;
+  // the wave's wide Gaussians, one after the other, expanded by all lanes
+  for (uint64_t m = __ballot(wide); m; m &= m - 1) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    const uint32_t gi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)i, src);
+    const uint32_t gbase = (uint32_t)__builtin_amdgcn_readlane((int)base, src);
+    const ScanDesc &sd = T.s[__builtin_amdgcn_readlane(kscan, src)];
+    const BrickGrid &bg = sd.bg;
+    const uint32_t b0 = (uint32_t)sd.b0;
+    const EvalRec e = er[gi];
+    GaussBox B;
+    gauss_box(bg, e, cr[gi], cutoff, B);  // as in the count pass: not empty
+    uint32_t nky;
+    const uint32_t nrows = box_rows(bg, B, nky);
+    uint32_t done = 0;
+    for (uint32_t q0 = 0; q0 < nrows; q0 += 64) {
+      const uint32_t q = q0 + (uint32_t)lane_id();
+      uint32_t first = 0, len = 0, tot;
+      if (q < nrows) len = box_row_run(bg, e, B, cutoff, q, nky, first);
+      const uint32_t j0 = done + wave_excl_scan_u32(len, tot);
+      put_run(gbase + j0, b0 + first, len, gi);
+      done += tot;
+    }
+  }
   __syncthreads();
   const uint32_t tile0 = blk0 / kSortTile;
-  for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kPrepThreads) {
-    const int64_t slot = (int64_t)blk0 + k;
-    if (slot < cap) {
-      const uint32_t key = sbrick[k];
-      key_brick[slot] = key;
-      key_gid[slot] = sgid[k];
-      atomicAdd(&tcnt[(uint32_t)(slot / kSortTile) - tile0][key & (kRadix - 1)], 1u);
+  if (staged) {
+    tcnt[0][threadIdx.x] = 0u;
+    tcnt[1][threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kPrepThreads) {
+      const int64_t slot = (int64_t)blk0 + k;
+      if (slot < cap) {
+        const uint32_t key = sbrick[k];
+        key_brick[slot] = key;
+        key_gid[slot] = sgid[k];
+        atomicAdd(&tcnt[(uint32_t)(slot / kSortTile) - tile0][key & (kRadix - 1)], 1u);
+      }
     }
+    __syncthreads();
+    // integer sums: the histogram does not depend on the order of the additions
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t cq = tcnt[q][threadIdx.x];
+      if (cq) atomicAdd(&hist[(int64_t)threadIdx.x * ntiles + tile0 + q], cq);
+    }
+    return;
   }
-  __syncthreads();
-  // integer sums: the histogram does not depend on the order of the additions
-  for (int q = 0; q < 2; ++q) {
-    const uint32_t c = tcnt[q][threadIdx.x];
-    if (c) atomicAdd(&hist[(int64_t)threadIdx.x * ntiles + tile0 + q], c);
+  // not staged: the block's keys are in global memory (written by this block's threads before the
+  // barrier); count their digits tile by tile
+  const uint32_t end = (uint32_t)min((int64_t)blk1, cap);
+  for (uint32_t t0 = tile0 * (uint32_t)kSortTile; t0 < end; t0 += (uint32_t)kSortTile) {
+    tcnt[0][threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t lo = max(t0, blk0), hi = min(t0 + (uint32_t)kSortTile, end);
+    for (uint32_t k = lo + threadIdx.x; k < hi; k += kPrepThreads) atomicAdd(&tcnt[0][key_brick[k] & (kRadix - 1)], 1u);
+    __syncthreads();
+    const uint32_t cq = tcnt[0][threadIdx.x];
+    if (cq) atomicAdd(&hist[(int64_t)threadIdx.x * ntiles + t0 / kSortTile], cq);
+    __syncthreads();
   }
 }
 

@@ -244,7 +244,8 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
   const float Sv = sub == 0 ? Sa[0] : (sub == 1 ? Sa[1] : (sub == 2 ? Sa[2] : Sa[3]));
   if (rowin && qx0 + sub < bg.nx) {
     const int64_t v = sd.v0 + ((int64_t)iz * bg.ny + iy) * bg.nx + qx0 + sub;
-    I[v] = Sv / (Wv + eps);
+    // hardware reciprocal (1 ulp): I within 2 ulp of S / (W + eps)
+    I[v] = Sv * __builtin_amdgcn_rcpf(Wv + eps);
     if (W) W[v] = Wv;
   }
 }

@@ -433,3 +433,43 @@ def test_long_brick_runs_are_enumerated_again():
         Io, Wo, _ = oracle.render(p, grid)
         assert_fwd_close(np64(W), Wo, f"long runs W bx={bx}")
         assert_fwd_close(np64(I), Io, f"long runs I bx={bx}")
+
+
+@pytest.mark.parametrize("n_wide,n_small", [(12, 200), (300, 300)])
+def test_wide_gaussians_enumerated_by_the_wave(n_wide, n_small):
+    """Gaussians whose voxel box spans more than 32 brick rows ((z-slab, y-row) pairs of bricks) are
+    counted and their keys emitted by the whole wave, a box row per lane.  With a few of them among
+    small ones a block's keys are staged in LDS; with many, the block writes its keys straight out
+    and reads them back for the first sort pass's digit counts.  Useful pairs, forward and backward
+    match the oracle."""
+    dims = (64, 48, 40)
+    grid = oracle.Grid(*dims)
+    pw = synth.gaussians_uniform(61 + n_wide, n_wide, dims, ls_mean=math.log(5.0), ls_std=0.2)
+    ps = synth.gaussians_uniform(62 + n_wide, n_small, dims, ls_std=0.3)
+    order = np.random.default_rng(63).permutation(n_wide + n_small)  # wide ones spread over the waves
+    p = {k: np.concatenate([pw[k], ps[k]])[order] for k in pw}
+    p = cases.condition(p, grid, seed=64)
+    say("wide Gaussians", dims, n_wide, n_small)
+    gs = gs_mod()
+    T = synth.uniform_volume(65, dims)
+    Io, Wo, _ = oracle.render(p, grid)
+    _, go = oracle.mse_loss(Io, T)
+    I32, W32, g32 = (x.astype(np.float32) for x in (Io, Wo, go))
+    ref = oracle.grad(p, grid, I32.astype(np.float64), W32.astype(np.float64), g32.astype(np.float64))
+    U = oracle.count_pairs(p, grid)
+    d = torch.device("cuda")
+    for bx in (8, 4):
+        g = gs.Gaussians.from_numpy(p)
+        ggrid = to_grid(grid)
+        opts = gs.Opts(bx=bx)
+        I, W, bins = gs.render(g, ggrid, opts)
+        say("  bx", bx, "keys", gs.gs_status(bins)["n_keys"])
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gs.gs_count_pairs(g, ggrid, opts, bins, cnt)
+        assert int(cnt.item()) == U
+        assert_fwd_close(np64(W), Wo, f"wide W bx={bx}")
+        assert_fwd_close(np64(I), Io, f"wide I bx={bx}")
+        gg = gpu_grads(g, ggrid, opts, bins, torch.from_numpy(I32).to(d), torch.from_numpy(W32).to(d),
+                       torch.from_numpy(g32).to(d))
+        for k in oracle.GROUPS:
+            assert_grad_close(gg[k], ref[k], f"wide d_{k} bx={bx}")
