@@ -135,7 +135,7 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
   L.vals_b = take(sizeof(uint32_t) * (size_t)cap);
   L.list_gid = take(sizeof(uint32_t) * (size_t)cap);
   L.list_slot = take(sizeof(uint32_t) * (size_t)cap);
-  L.brick_off = take(sizeof(uint32_t) * (size_t)(nbricks + 1));
+  L.brick_se = take(sizeof(uint32_t) * 2 * (size_t)nbricks);
   L.hist = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.sort_blocks);
   // scan scratch: per-block key totals of the count scan, later the radix digit totals
   L.scan_tmp = take(std::max(sizeof(uint64_t) * (size_t)((n + kPrepThreads - 1) / kPrepThreads + 1),

@@ -174,7 +174,10 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
 
 // Gaussians with more box rows than this are enumerated by the whole wave (one box row per lane)
 // in the count and the emit pass instead of by their own lane.
-constexpr uint32_t kWaveRows = 32;
+#ifndef GS_WAVE_ROWS
+#define GS_WAVE_ROWS 32
+#endif
+constexpr uint32_t kWaveRows = GS_WAVE_ROWS;
 
 __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -214,13 +217,15 @@ __global__ __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_eu(6)
     const ScanTable T, float cutoff,
                                                              EvalRec *__restrict__ er, CullRec *__restrict__ cr,
                                                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
-                                                             uint64_t *__restrict__ bsum,
-                                                             uint32_t *__restrict__ hist, int64_t hist_len) {
+uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
+    uint32_t *__restrict__ brick_se, int64_t se_len) {
   __shared__ uint64_t wsum[kPrepThreads / 64];
   __shared__ int sbad;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
   // the first radix pass's histogram is accumulated by the emit kernel: clear it here
   for (int64_t k = i; k < hist_len; k += (int64_t)gridDim.x * kPrepThreads) hist[k] = 0u;
+  // bricks without keys keep (0, 0) as their list bounds
+  for (int64_t k = i; k < se_len; k += (int64_t)gridDim.x * kPrepThreads) brick_se[k] = 0u;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   uint32_t c = 0;
@@ -297,13 +302,15 @@ __global__ __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_eu(6)
 
 hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
   char *b = (char *)ws;
-  const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
-  if (blocks == 0) return hipSuccess;
+  // at least one block: the kernel also clears the first sort pass's histogram and the brick list
+  // bounds, which the later kernels read even when there are no Gaussians
+  const int blocks = (int)std::max<int64_t>((T.n_total + kPrepThreads - 1) / kPrepThreads, 1);
   prof_begin(s);
   k_prep_count<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (EvalRec *)(b + L.evalrec), (CullRec *)(b + L.cullrec),
                                                (uint32_t *)(b + L.off), (uint32_t *)(b + L.runs),
                                                (uint64_t *)(b + L.scan_tmp),
-                                               (uint32_t *)(b + L.hist), (int64_t)kRadix * L.sort_blocks);
+                                               (uint32_t *)(b + L.hist), (int64_t)kRadix * L.sort_blocks,
+                                               (uint32_t *)(b + L.brick_se), 2 * L.nbricks);
   prof_end(s, "prep_count");
   return hipGetLastError();
 }
@@ -394,7 +401,9 @@ hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns
 // lengths places the runs in row order.  The first radix pass's digit counts per sort tile come from
 // LDS counters (for a block whose range is not staged, from a second read of the range it wrote).
 
-constexpr int kEmitStage = 4096;  // keys staged per block (32 KB of LDS)
+// Keys staged per block: 4096 (32 KB of LDS), or 6144 (48 KB, fewer blocks per CU) when the key
+// capacity per block suggests that most blocks would not fit 4096 (long-tailed sets).
+constexpr int kEmitStageSmall = 4096, kEmitStageLarge = 6144;
 
 __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
   uint32_t incl = v;
@@ -407,6 +416,7 @@ __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &tot
   return incl - v;
 }
 
+template <int kEmitStage>
 __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float cutoff,
                                                        const EvalRec *__restrict__ er,
                                                        const CullRec *__restrict__ cr,
@@ -417,7 +427,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
                                                        int ntiles) {
   __shared__ uint32_t sbrick[kEmitStage], sgid[kEmitStage];
   __shared__ uint32_t wtot[kPrepThreads / 64];
-  __shared__ uint32_t tcnt[2][kRadix];  // digit counts of (at most two) sort tiles
+  // digit counts of the sort tiles a staged range meets (a range of kEmitStage keys meets at most
+  // kEmitTiles tiles)
+  constexpr int kEmitTiles = (kEmitStage + kSortTile - 2) / kSortTile + 1;
+  __shared__ uint32_t tcnt[kEmitTiles][kRadix];
   if (st->overflow) return;
   const int64_t n = T.n_total;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
@@ -514,8 +527,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
   __syncthreads();
   const uint32_t tile0 = blk0 / kSortTile;
   if (staged) {
-    tcnt[0][threadIdx.x] = 0u;
-    tcnt[1][threadIdx.x] = 0u;
+#pragma unroll
+    for (int q = 0; q < kEmitTiles; ++q) tcnt[q][threadIdx.x] = 0u;
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < blk1 - blk0; k += kPrepThreads) {
       const int64_t slot = (int64_t)blk0 + k;
@@ -528,7 +541,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
     }
     __syncthreads();
     // integer sums: the histogram does not depend on the order of the additions
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < kEmitTiles; ++q) {
       const uint32_t cq = tcnt[q][threadIdx.x];
       if (cq) atomicAdd(&hist[(int64_t)threadIdx.x * ntiles + tile0 + q], cq);
     }
@@ -553,11 +566,16 @@ hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayou
   if (T.n_total == 0) return hipSuccess;
   char *b = (char *)ws;
   const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
+  // the capacity is sized from the exact key count (times a headroom): its share per block tells
+  // whether blocks typically hold more keys than the small stage (the results do not depend on it)
+  const bool large = L.cap / blocks > (int64_t)(7 * kEmitStageSmall / 8);
+  auto emit = large ? k_emit<kEmitStageLarge> : k_emit<kEmitStageSmall>;
   prof_begin(s);
-  k_emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
-                                         (const uint32_t *)(b + L.runs), (uint32_t *)(b + L.off), (const uint64_t *)(b + L.scan_tmp), L.cap,
-                                         (const DevStatus *)(b + L.status), (uint32_t *)(b + L.key_brick),
-                                         (uint32_t *)(b + L.key_gid), (uint32_t *)(b + L.hist), L.sort_blocks);
+  emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
+                                       (const uint32_t *)(b + L.runs), (uint32_t *)(b + L.off),
+                                       (const uint64_t *)(b + L.scan_tmp), L.cap, (const DevStatus *)(b + L.status),
+                                       (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid),
+                                       (uint32_t *)(b + L.hist), L.sort_blocks);
   prof_end(s, "emit");
   return hipGetLastError();
 }
@@ -738,20 +756,35 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
 }
 
-__global__ void k_brick_offsets(const uint32_t *__restrict__ sorted_brick, const DevStatus *st, int64_t cap,
-                                uint32_t *__restrict__ brick_off, int64_t nbricks) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b > nbricks) return;
-  int64_t K = live_keys(st, cap);
-  int64_t lo = 0, hi = K;  // first k with sorted_brick[k] >= b
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)sorted_brick[mid] < b)
-      lo = mid + 1;
-    else
-      hi = mid;
+// Brick lists in the sorted keys: every brick with keys gets (first position, end) from the positions
+// where the sorted brick id changes (each entry is written by exactly one thread: the one at its
+// list's first key, or at the next list's first key / the end).  Bricks without keys keep the
+// (0, 0) the prep kernel wrote.
+__global__ __launch_bounds__(256) void k_brick_bounds(const uint32_t *__restrict__ sorted_brick, const DevStatus *st,
+                                                      int64_t cap, uint32_t *__restrict__ brick_se) {
+  const int64_t K = live_keys(st, cap);
+  // four consecutive positions per thread (one 16-byte load) and the key before them
+  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (k0 > K) return;
+  uint32_t v[5];
+  v[0] = k0 > 0 ? sorted_brick[k0 - 1] : 0xFFFFFFFFu;
+  if (k0 + 4 <= K) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(sorted_brick + k0);
+    v[1] = q.x;
+    v[2] = q.y;
+    v[3] = q.z;
+    v[4] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[1 + j] = k0 + j < K ? sorted_brick[k0 + j] : 0xFFFFFFFFu;
   }
-  brick_off[b] = (uint32_t)lo;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t k = k0 + j;
+    const uint32_t cur = v[1 + j], prev = v[j];
+    if (k < K && (k == 0 || cur != prev)) brick_se[2 * (int64_t)cur] = (uint32_t)k;
+    if (k > 0 && k <= K && (k == K || cur != prev)) brick_se[2 * (int64_t)prev + 1] = (uint32_t)k;
+  }
 }
 
 hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s) {
@@ -789,10 +822,9 @@ hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStrea
       vin = vout;
     }
   }
-  const int ob = (int)((T.nbricks_total + 1 + 255) / 256);
+  const int ob = (int)((L.cap + 1 + 1023) / 1024);
   prof_begin(s);
-  k_brick_offsets<<<ob, 256, 0, s>>>((const uint32_t *)(b + L.sorted_keys), st, L.cap, (uint32_t *)(b + L.brick_off),
-                                     T.nbricks_total);
+  k_brick_bounds<<<ob, 256, 0, s>>>((const uint32_t *)(b + L.sorted_keys), st, L.cap, (uint32_t *)(b + L.brick_se));
   prof_end(s, "brick_offsets");
   return hipGetLastError();
 }

@@ -115,14 +115,15 @@ constexpr uint64_t kBadBlock = 1ull << 63;
 //   scan_tmp: per-block key totals of the count scan (uint64), later the radix digit totals.
 //   key_brick, key_gid: uint32 [cap] keys in slot order; keys_alt, vals_a, vals_b: radix ping-pong.
 //   list_gid, list_slot: uint32 [cap] the keys sorted by brick: Gaussian index and key slot.
-//   brick_off: uint32 [B + 1] brick list offsets.  partials: 48 B per key slot (backward; absent in a
-//   forward-only workspace).
+//   brick_se: uint32 [B][2] each brick's list bounds (first position, end) in the sorted keys, (0, 0)
+//   for a brick without keys.  partials: 48 B per key slot (backward; absent in a forward-only
+//   workspace).
 struct WsLayout {
   int64_t n = 0, cap = 0, nbricks = 0;
   int sort_blocks = 0;  // tiles per radix pass (covers cap keys)
   int sort_passes = 0;  // ceil(bits(nbricks) / 8), at least 1
   size_t status = 0, evalrec = 0, cullrec = 0, off = 0, runs = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
-         vals_b = 0, list_gid = 0, list_slot = 0, brick_off = 0, hist = 0, scan_tmp = 0, partials = 0, total = 0;
+         vals_b = 0, list_gid = 0, list_slot = 0, brick_se = 0, hist = 0, scan_tmp = 0, partials = 0, total = 0;
   size_t sorted_keys = 0;  // where the brick ids end up after the last pass
 };
 

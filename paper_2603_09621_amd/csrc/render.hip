@@ -108,7 +108,7 @@ template <int BX, bool COUNT>
 __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff, float eps,
                                                  const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                  const uint32_t *__restrict__ list_gid,
-                                                 const uint32_t *__restrict__ brick_off, const DevStatus *st,
+                                                 const uint2 *__restrict__ brick_se, const DevStatus *st,
                                                  float *__restrict__ I, float *__restrict__ W,
                                                  unsigned long long *__restrict__ pair_count,
                                                  unsigned long long *__restrict__ eval_count) {
@@ -139,7 +139,8 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
 #pragma unroll
   for (int k = 0; k < 4; ++k) px[k] = centre(bg.ox, bg.hx, qx0 + k);
   const bool rowin = iy < bg.ny && iz < bg.nz;
-  const uint32_t start = brick_off[b], end = brick_off[b + 1];
+  const uint2 se = brick_se[b];
+  const uint32_t start = se.x, end = se.y;
   const uint64_t lt = lanemask_lt();
 
   if (t == 0) {
@@ -263,7 +264,8 @@ static hipError_t fwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
   if (nb == 0) return hipSuccess;
   const EvalRec *er = (const EvalRec *)(b + L.evalrec);
   const CullRec *cr = (const CullRec *)(b + L.cullrec);
-  const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *bo = (const uint32_t *)(b + L.brick_off);
+  const uint32_t *lg = (const uint32_t *)(b + L.list_gid);
+  const uint2 *bo = (const uint2 *)(b + L.brick_se);
   const DevStatus *st = (const DevStatus *)(b + L.status);
   switch (bx) {
     case 4: k_fwd<4, COUNT><<<nb, 128, 0, s>>>(T, cutoff, eps, er, cr, lg, bo, st, I, W, cnt, evals); break;
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                      const uint32_t *__restrict__ list_gid,
                                                      const uint32_t *__restrict__ list_slot,
-                                                     const uint32_t *__restrict__ brick_off, const DevStatus *st,
+                                                     const uint2 *__restrict__ brick_se, const DevStatus *st,
                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
                                                      const float *__restrict__ gI, const float *__restrict__ obs,
                                                      float *__restrict__ loss_part, int64_t cap,
@@ -413,13 +415,21 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   const int64_t b = sd.b0 + lb;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   int x0[G], y0[G], z0[G];
-  uint32_t boff[G + 1];
+  // boff[j]: where brick j's keys start in the group's contiguous key range (for a brick without
+  // keys, where the next brick's start), boff[G]: the range's end
+  uint32_t boff[G + 1], bs[G], be[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
     brick_coords(bg, lb + min(j, nbk - 1), x0[j], y0[j], z0[j]);
-    boff[j] = brick_off[b + min(j, nbk)];
+    const uint2 se = j < nbk ? brick_se[b + j] : make_uint2(0u, 0u);
+    bs[j] = se.x;
+    be[j] = se.y;
   }
-  boff[G] = brick_off[b + nbk];
+  boff[G] = 0u;
+#pragma unroll
+  for (int j = 0; j < G; ++j) boff[G] = max(boff[G], be[j]);
+#pragma unroll
+  for (int j = G - 1; j >= 0; --j) boff[j] = be[j] > bs[j] ? bs[j] : boff[j + 1];
   if (t < G) {
     sorg[t][0] = x0[t];
     sorg[t][1] = y0[t];
@@ -636,7 +646,7 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float e
   const EvalRec *er = (const EvalRec *)(b + L.evalrec);
   const CullRec *cr = (const CullRec *)(b + L.cullrec);
   const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *ls = (const uint32_t *)(b + L.list_slot);
-  const uint32_t *bo = (const uint32_t *)(b + L.brick_off);
+  const uint2 *bo = (const uint2 *)(b + L.brick_se);
   const DevStatus *st = (const DevStatus *)(b + L.status);
   float4 *part = MODE == kBwdCount ? nullptr : (float4 *)(b + L.partials);
   switch (bx) {
