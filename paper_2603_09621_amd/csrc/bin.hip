@@ -172,40 +172,76 @@ __device__ uint32_t enumerate_bricks(const BrickGrid &bg, const EvalRec &e, cons
   return count;
 }
 
-// Gaussians with more box rows than this are enumerated by the whole wave (one box row per lane)
-// in the count and the emit pass instead of by their own lane.
-#ifndef GS_WAVE_ROWS
-#define GS_WAVE_ROWS 32
-#endif
-constexpr uint32_t kWaveRows = GS_WAVE_ROWS;
+// Gaussians with more box rows than this are counted by the whole wave, together with the other such
+// Gaussians of the wave (a listed box row per lane), instead of by their own lane; the emit pass
+// expands them, and those whose runs did not fit the run cache, the same way.
+constexpr uint32_t kWaveRows = 16;
 
-__device__ __forceinline__ float readlane_f(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
+// Flattened wave enumeration.  Each lane lists nr rows (the box rows of its Gaussian, or 0); the
+// listed rows of the wave are numbered Gaussian by Gaussian in lane order (R: a lane's exclusive
+// prefix of nr) and taken 64 at a time, a row per lane.  All shuffles run with every lane active.
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
+  uint32_t incl = v;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, 64);
+    if (lane_id() >= d) incl += t;
+  }
+  total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  return incl - v;
 }
 
-// The geometry of lane src's Gaussian, broadcast to the wave (only what the enumeration reads).
-__device__ __forceinline__ void broadcast_geometry(const EvalRec &e, const CullRec &c, int src, EvalRec &eb,
-                                                   CullRec &cb) {
-  eb.r0 = make_float4(readlane_f(e.r0.x, src), readlane_f(e.r0.y, src), readlane_f(e.r0.z, src), 0.f);
+__device__ __forceinline__ float shfl_f(float v, int l) { return __shfl(v, l, 64); }
+
+// The lane listing row q (q below the wave's total): the last lane whose prefix R is <= q.
+__device__ __forceinline__ int row_owner(uint32_t q, uint32_t R) {
+  int lo = 0, hi = 63;
+#pragma unroll
+  for (int step = 0; step < 6; ++step) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint32_t)__shfl((int)R, mid, 64) <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The geometry of lane o's Gaussian (only what the enumeration reads).
+__device__ __forceinline__ void fetch_geometry(const EvalRec &e, const CullRec &c, int o, EvalRec &eb, CullRec &cb) {
+  eb.r0 = make_float4(shfl_f(e.r0.x, o), shfl_f(e.r0.y, o), shfl_f(e.r0.z, o), 0.f);
   eb.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
   eb.r2 = eb.r1;
-  cb.c0 = make_float4(readlane_f(c.c0.x, src), readlane_f(c.c0.y, src), readlane_f(c.c0.z, src),
-                      readlane_f(c.c0.w, src));
-  cb.c1 = make_float4(readlane_f(c.c1.x, src), readlane_f(c.c1.y, src), readlane_f(c.c1.z, src), 0.f);
+  cb.c0 = make_float4(shfl_f(c.c0.x, o), shfl_f(c.c0.y, o), shfl_f(c.c0.z, o), shfl_f(c.c0.w, o));
+  cb.c1 = make_float4(shfl_f(c.c1.x, o), shfl_f(c.c1.y, o), shfl_f(c.c1.z, o), 0.f);
+}
+
+// Row item q of the wave's list (valid: q below the total): its owner lane o, and the run of the
+// owner's box row q - R_o (0 keys if invalid or the ellipsoid misses the row).
+__device__ __forceinline__ uint32_t flat_row_run(const ScanTable &T, float cutoff, const EvalRec &e, const CullRec &c,
+                                                 int kscan, uint32_t R, uint32_t q, bool valid, int &o,
+                                                 uint32_t &first) {
+  o = row_owner(q, R);
+  EvalRec eb;
+  CullRec cb;
+  fetch_geometry(e, c, o, eb, cb);
+  const uint32_t Ro = (uint32_t)__shfl((int)R, o, 64);
+  const int ko = __shfl(kscan, o, 64);
+  first = 0;
+  if (!valid) return 0u;
+  const BrickGrid &bg = T.s[ko].bg;
+  GaussBox B;
+  if (!gauss_box(bg, eb, cb, cutoff, B)) return 0u;  // not reached: listed Gaussians have a box
+  uint32_t nky;
+  box_rows(bg, B, nky);
+  return box_row_run(bg, eb, B, cutoff, q - Ro, nky, first);
 }
 
 // Run cache: the count pass records each Gaussian's runs (up to kRuns of them, each a 32-bit word
 // (first scan-local brick << 4) | (length - 1) for runs of at most 16 bricks starting below 2^28 - 1),
 // ended by kRunEnd; a Gaussian whose runs do not fit is marked kRunRedo and the emit pass enumerates
-// it again.  The emit pass then expands the recorded runs instead of repeating the enumeration.
-// A Gaussian with more than kWaveRows box rows is marked kRunWave instead: the emit pass enumerates it
-// with the whole wave.
+// it again (with the wave).  The emit pass then expands the recorded runs instead of repeating the
+// enumeration.  A Gaussian with more than kWaveRows box rows is marked kRunWave instead: it is counted
+// and emitted with the wave.
 constexpr uint32_t kRunEnd = 0xFFFFFFFFu, kRunRedo = 0xFFFFFFFEu, kRunWave = 0xFFFFFFFDu;
 
 // Fused prep + count: records of Gaussian i (of the concatenated numbering; its parameters are
@@ -228,11 +264,12 @@ uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
   for (int64_t k = i; k < se_len; k += (int64_t)gridDim.x * kPrepThreads) brick_se[k] = 0u;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
-  uint32_t c = 0;
+  __shared__ uint32_t wcount[kPrepThreads];  // key counts of the wide Gaussians, by lane
+  uint32_t c = 0, wide_rows = 0;
   bool wide = false;
   int kscan = 0;
-  EvalRec e;
-  CullRec r;
+  EvalRec e = {};
+  CullRec r = {};
   if (i < T.n_total) {
     kscan = T.of_gauss(i);
     const ScanDesc &sd = T.s[kscan];
@@ -249,7 +286,8 @@ uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
     GaussBox B;
     if (gauss_box(sd.bg, e, r, cutoff, B)) {
       uint32_t nky;
-      wide = box_rows(sd.bg, B, nky) > kWaveRows;
+      wide_rows = box_rows(sd.bg, B, nky);
+      wide = wide_rows > kWaveRows;
       if (!wide)
         c = enumerate_bricks(sd.bg, e, B, cutoff, [&](uint32_t first, uint32_t len, uint32_t) {
           if (nr < kRuns && len <= 16u && first < 0x0FFFFFFFu) {
@@ -268,24 +306,21 @@ uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
 #pragma unroll
     for (int q = 0; q < kRuns / 4; ++q) rc[q] = make_uint4(rr[4 * q], rr[4 * q + 1], rr[4 * q + 2], rr[4 * q + 3]);
   }
-  // the wave's wide Gaussians, one after the other, counted by all lanes (a box row per lane)
-  for (uint64_t m = __ballot(wide); m; m &= m - 1) {
-    const int src = __ffsll((unsigned long long)m) - 1;
-    const BrickGrid &bg = T.s[__builtin_amdgcn_readlane(kscan, src)].bg;
-    EvalRec eb;
-    CullRec cb;
-    broadcast_geometry(e, r, src, eb, cb);
-    GaussBox B;
-    gauss_box(bg, eb, cb, cutoff, B);  // as on lane src: not empty
-    uint32_t nky;
-    const uint32_t nrows = box_rows(bg, B, nky);
-    uint32_t tot = 0;
-    for (uint32_t q = (uint32_t)lane_id(); q < nrows; q += 64) {
+  // the wave's wide Gaussians, counted together: a listed box row per lane, each row's run length
+  // added to its owner's LDS counter (integer sums: the order does not matter)
+  uint32_t tot;
+  const uint32_t R = wave_excl_scan_u32(wide ? wide_rows : 0u, tot);
+  if (tot) {
+    wcount[threadIdx.x] = 0u;
+    for (uint32_t t0 = 0; t0 < tot; t0 += 64) {
+      const uint32_t q = t0 + (uint32_t)lane_id();
+      int o;
       uint32_t first;
-      tot += box_row_run(bg, eb, B, cutoff, q, nky, first);
+      const uint32_t len = flat_row_run(T, cutoff, e, r, kscan, R, min(q, tot - 1), q < tot, o, first);
+      if (len) atomicAdd(&wcount[(threadIdx.x & ~63u) + o], len);
     }
-    tot = wave_sum_u32(tot);
-    if (lane_id() == src) c = tot;
+    __builtin_amdgcn_wave_barrier();
+    if (wide) c = wcount[threadIdx.x];
   }
   if (i < T.n_total) cnt[i] = c;
   uint64_t v = c;
@@ -397,24 +432,16 @@ hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns
 // (the last level of the count scan is done here: off[i] becomes the Gaussian's first slot).  A
 // block's Gaussians own a contiguous slot range; when it fits, the block assembles its keys in LDS
 // and writes the range out with consecutive threads on consecutive slots.  Wide Gaussians (kRunWave)
-// are expanded by the whole wave: each lane takes a box row, a wave prefix sum of the rows' run
-// lengths places the runs in row order.  The first radix pass's digit counts per sort tile come from
-// LDS counters (for a block whose range is not staged, from a second read of the range it wrote).
+// and those whose runs did not fit the cache are expanded by the whole wave: their box rows are
+// listed Gaussian by Gaussian, each lane takes a row, and a wave prefix sum of the rows' run lengths
+// places each run among its Gaussian's keys in row order.  The first radix pass's digit counts per
+// sort tile come from LDS counters (for a block whose range is not staged, from a second read of the
+// range it wrote).
 
 // Keys staged per block: 4096 (32 KB of LDS), or 6144 (48 KB, fewer blocks per CU) when the key
 // capacity per block suggests that most blocks would not fit 4096 (long-tailed sets).
 constexpr int kEmitStageSmall = 4096, kEmitStageLarge = 6144;
 
-__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
-  uint32_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(incl, d, 64);
-    if (lane_id() >= d) incl += t;
-  }
-  total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-  return incl - v;
-}
 
 template <int kEmitStage>
 __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float cutoff,
@@ -467,8 +494,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
       }
     }
   };
-  bool wide = false;
+  // Gaussians listed for the flattened wave enumeration: those marked wide by the count pass and
+  // those whose runs did not fit the cache
+  uint32_t nlist = 0;
   int kscan = 0;
+  EvalRec e = {};
+  CullRec cg = {};
   if (i < n) {
     kscan = T.of_gauss(i);
     const ScanDesc &sd = T.s[kscan];
@@ -484,12 +515,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
       rr[4 * q + 3] = v.w;
     }
     auto visit = [&](uint32_t first, uint32_t len, uint32_t j0) { put_run(base + j0, b0 + first, len, (uint32_t)i); };
-    if (rr[0] == kRunWave) {
-      wide = true;
-    } else if (rr[0] == kRunRedo) {  // runs that did not fit the cache: enumerated again
+    if (rr[0] == kRunWave || rr[0] == kRunRedo) {
+      e = er[i];
+      cg = cr[i];
       GaussBox B;
-      const EvalRec e = er[i];
-      if (gauss_box(sd.bg, e, cr[i], cutoff, B)) enumerate_bricks(sd.bg, e, B, cutoff, visit);
+      uint32_t nky;
+      if (gauss_box(sd.bg, e, cg, cutoff, B)) nlist = box_rows(sd.bg, B, nky);
     } else {
       uint32_t j = 0;
 #pragma unroll
@@ -501,28 +532,31 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
       }
     }
   }
-  // the wave's wide Gaussians, one after the other, expanded by all lanes
-  for (uint64_t m = __ballot(wide); m; m &= m - 1) {
-    const int src = __ffsll((unsigned long long)m) - 1;
-    const uint32_t gi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)i, src);
-    const uint32_t gbase = (uint32_t)__builtin_amdgcn_readlane((int)base, src);
-    const ScanDesc &sd = T.s[__builtin_amdgcn_readlane(kscan, src)];
-    const BrickGrid &bg = sd.bg;
-    const uint32_t b0 = (uint32_t)sd.b0;
-    const EvalRec e = er[gi];
-    GaussBox B;
-    gauss_box(bg, e, cr[gi], cutoff, B);  // as in the count pass: not empty
-    uint32_t nky;
-    const uint32_t nrows = box_rows(bg, B, nky);
-    uint32_t done = 0;
-    for (uint32_t q0 = 0; q0 < nrows; q0 += 64) {
-      const uint32_t q = q0 + (uint32_t)lane_id();
-      uint32_t first = 0, len = 0, tot;
-      if (q < nrows) len = box_row_run(bg, e, B, cutoff, q, nky, first);
-      const uint32_t j0 = done + wave_excl_scan_u32(len, tot);
-      put_run(gbase + j0, b0 + first, len, gi);
-      done += tot;
-    }
+  // the listed Gaussians' keys, a box row per lane: within a 64-row batch an inclusive scan of the
+  // run lengths gives each run's place among its owner's keys of the batch; `done` (kept by the
+  // owner lane) counts the owner's keys of the earlier batches
+  uint32_t tot;
+  const uint32_t R = wave_excl_scan_u32(nlist, tot);
+  uint32_t done = 0;
+  for (uint32_t t0 = 0; t0 < tot; t0 += 64) {
+    const uint32_t q = t0 + (uint32_t)lane_id();
+    int o;
+    uint32_t first;
+    const uint32_t len = flat_row_run(T, cutoff, e, cg, kscan, R, min(q, tot - 1), q < tot, o, first);
+    uint32_t btot;
+    const uint32_t ex = wave_excl_scan_u32(len, btot);
+    const uint32_t Ro = (uint32_t)__shfl((int)R, o, 64);
+    const int fo = Ro > t0 ? (int)(Ro - t0) : 0;  // the owner's first lane in this batch
+    const uint32_t j0 = (uint32_t)__shfl((int)done, o, 64) + ex - (uint32_t)__shfl((int)ex, fo, 64);
+    const uint32_t gbase = (uint32_t)__shfl((int)base, o, 64);
+    const uint32_t gi = (uint32_t)__shfl((int)(uint32_t)i, o, 64);
+    const uint32_t b0 = (uint32_t)T.s[__shfl(kscan, o, 64)].b0;
+    if (len) put_run(gbase + j0, b0 + first, len, gi);
+    // this lane's own Gaussian: its keys in this batch are those of lanes [a, b)
+    const int a = (int)min(R > t0 ? R - t0 : 0u, 64u), b = (int)min(R + nlist > t0 ? R + nlist - t0 : 0u, 64u);
+    const uint32_t eb = (uint32_t)__shfl((int)(ex + len), max(b - 1, 0), 64);
+    const uint32_t ea = (uint32_t)__shfl((int)ex, min(a, 63), 64);
+    done += b > a ? eb - ea : 0u;
   }
   __syncthreads();
   const uint32_t tile0 = blk0 / kSortTile;
