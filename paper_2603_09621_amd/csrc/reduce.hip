@@ -17,20 +17,28 @@ namespace gs {
 
 // Per-Gaussian sums of the brick partials, for the 256 consecutive Gaussians of a block: the
 // block's partials (contiguous, since keys are numbered Gaussian-major) are loaded cooperatively
-// through LDS in chunks, and each thread adds its own Gaussian's partials in slot order.  The next
+// through LDS in chunks, and each thread adds its own Gaussian's partials in slot order (a Gaussian
+// with more than kLongKeys partials is left to block_long_sums, so that one long list does not
+// hold the block).  The next
 // chunk's loads are issued into registers before the current chunk is summed.
 constexpr int kRedThreads = 256;
 constexpr int kRedChunk = 768;                         // partials per LDS chunk (36 KB)
 constexpr int kRedPer = 3 * kRedChunk / kRedThreads;  // float4 loads per thread per chunk
 
+// A Gaussian with more partials than this is summed by a wave (block_long_sums) instead of its
+// own thread.
+constexpr uint32_t kLongKeys = 64;
+
 __device__ __forceinline__ void block_partial_sums(int64_t i0, int64_t n, const uint32_t *__restrict__ off,
                                                    const float4 *__restrict__ part, float4 *sp, float4 &a0,
-                                                   float4 &a1, float4 &a2) {
+                                                   float4 &a1, float4 &a2, uint32_t &count) {
   const int t = threadIdx.x;
   const int64_t i = i0 + t;
   const int64_t iend = min(i0 + (int64_t)kRedThreads, n);
   const uint32_t sb = off[i0], se = off[iend];
-  const uint32_t my0 = i < n ? off[i] : se, my1 = i < n ? off[i + 1] : se;
+  uint32_t my0 = i < n ? off[i] : se, my1 = i < n ? off[i + 1] : se;
+  count = my1 - my0;
+  if (count > kLongKeys) my1 = my0;  // summed by block_long_sums
   a0 = make_float4(0, 0, 0, 0);
   a1 = a0;
   a2 = a0;
@@ -66,6 +74,58 @@ __device__ __forceinline__ void block_partial_sums(int64_t i0, int64_t n, const 
       a1.x += p1.x; a1.y += p1.y; a1.z += p1.z; a1.w += p1.w;
       a2.x += p2.x; a2.y += p2.y; a2.z += p2.z;
     }
+  }
+}
+
+// Sums of the long partial lists of a block's Gaussians: each wave takes the block's long Gaussians
+// in turn (w, w + 4, ... of them in index order); lane l adds the Gaussian's partials l, l + 64, ...
+// in order, and a fixed butterfly adds the 64 lane sums.  The order depends only on the Gaussian's own
+// partials, so the result is the same whatever block or batch the Gaussian falls in.  The owner
+// thread's (a0, a1, a2) receive the sums.
+__device__ __forceinline__ float bfly_sum(float v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__device__ __forceinline__ void block_long_sums(int64_t i0, const uint32_t *__restrict__ off,
+                                                const float4 *__restrict__ part, float4 *sp, uint32_t c,
+                                                float4 &a0, float4 &a1, float4 &a2) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  // (a barrier: the partial sums' use of sp is over)
+  if (!__syncthreads_or(c > kLongKeys ? 1 : 0)) return;  // no long list in the block
+  __shared__ uint64_t slong[kRedThreads / 64];
+  const uint64_t m = __ballot(c > kLongKeys);
+  if (l == 0) slong[w] = m;
+  __syncthreads();
+  int k = 0;  // running index over the block's long Gaussians
+  for (int ww = 0; ww < kRedThreads / 64; ++ww) {
+    for (uint64_t mm = slong[ww]; mm; mm &= mm - 1, ++k) {
+      if ((k & (kRedThreads / 64 - 1)) != w) continue;  // uniform per wave
+      const int src = ww * 64 + __ffsll((unsigned long long)mm) - 1;
+      const uint32_t s0 = off[i0 + src], s1 = off[i0 + src + 1];
+      float v[11] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (uint32_t s = s0 + (uint32_t)l; s < s1; s += 64) {
+        const float4 p0 = part[(int64_t)s * 3], p1 = part[(int64_t)s * 3 + 1], p2 = part[(int64_t)s * 3 + 2];
+        v[0] += p0.x; v[1] += p0.y; v[2] += p0.z; v[3] += p0.w;
+        v[4] += p1.x; v[5] += p1.y; v[6] += p1.z; v[7] += p1.w;
+        v[8] += p2.x; v[9] += p2.y; v[10] += p2.z;
+      }
+#pragma unroll
+      for (int q = 0; q < 11; ++q) v[q] = bfly_sum(v[q]);
+      // hand the sums to the owner thread through LDS (it may sit in another wave)
+      if (l == 0) {
+        sp[3 * src] = make_float4(v[0], v[1], v[2], v[3]);
+        sp[3 * src + 1] = make_float4(v[4], v[5], v[6], v[7]);
+        sp[3 * src + 2] = make_float4(v[8], v[9], v[10], 0.f);
+      }
+    }
+  }
+  __syncthreads();
+  if (c > kLongKeys) {
+    a0 = sp[3 * t];
+    a1 = sp[3 * t + 1];
+    a2 = sp[3 * t + 2];
   }
 }
 
@@ -142,7 +202,9 @@ __global__ void k_reduce_chain(int64_t n, const float *__restrict__ quat, const 
   __shared__ float4 sp[3 * kRedChunk];
   const int64_t i0 = (int64_t)blockIdx.x * kRedThreads, i = i0 + threadIdx.x;
   float4 a0, a1, a2;
-  block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
+  uint32_t cnt;
+  block_partial_sums(i0, n, off, part, sp, a0, a1, a2, cnt);
+  block_long_sums(i0, off, part, sp, cnt, a0, a1, a2);
   if (i >= n) return;
   float g[12];
   gauss_grad(i, quat, ls, relax, a0, a1, a2, g);
@@ -265,7 +327,9 @@ __global__ void k_reduce_adam(const ScanTable T, int64_t n, float *__restrict__ 
       }
   }
   float4 a0, a1, a2;
-  block_partial_sums(i0, n, off, part, sp, a0, a1, a2);
+  uint32_t cnt;
+  block_partial_sums(i0, n, off, part, sp, a0, a1, a2, cnt);
+  block_long_sums(i0, off, part, sp, cnt, a0, a1, a2);
   if (i >= n) return;
   float g[12];
   gauss_grad_v(pv[6], pv[7], pv[8], pv[9], pv[3], pv[4], pv[5], pv[11], a0, a1, a2, g);
