@@ -146,8 +146,10 @@ def batch_section(args, dev):
     batch = gs.Batch([x.n for x in sets], grids)
     g_all = gs.concat(sets)
     obs_all = torch.cat([o.reshape(-1) for o in obs])
-    opts = autotune.Tuner().fit_opts(g_all, batch, obs_all, zdown=4, steps=2)
-    print(f"[bench] autotuned brick width {opts.bx}", file=sys.stderr, flush=True)
+    tuner = autotune.Tuner()
+    opts = tuner.fit_opts(g_all, batch, obs_all, zdown=4, steps=2)
+    tuned = next(iter(tuner.cache.values()))
+    print(f"[bench] autotuned {opts.tuning}", file=sys.stderr, flush=True)
     fo = gs.FitOpts(None, opts=opts, zdown=4)
     stream = torch.cuda.current_stream()
     K, W = args.batch_steps, 2
@@ -212,6 +214,8 @@ def batch_section(args, dev):
                     f" in x/y, {min(d[2] for d in dims)}..{max(d[2] for d in dims)} in z; {g_all.n} Gaussians, "
                     f"{batch.v_offsets[-1]} HR voxels in total), z-mean-of-4 L1 + Adam",
         "brick": [opts.bx, opts.by, opts.bz],
+        "tuning": opts.tuning,
+        "tuner_ms_per_step": tuned["ms"],
         "steps": K,
         "ms_per_batched_step": ms_batched / K,
         "ms_per_plain_round": ms_plain / K,

@@ -169,7 +169,11 @@ static int check_opts(const gs_opts_t *opts) {
     return fail(GS_ERR_UNSUPPORTED, "brick %dx%dx%d not supported by this library", opts->bx, opts->by, opts->bz);
   if (!(opts->cutoff > 0.f) || !std::isfinite(opts->cutoff)) return fail(GS_ERR_INVALID_ARG, "cutoff must be > 0");
   if (!(opts->eps > 0.f) || !std::isfinite(opts->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be > 0 and finite");
-  if ((opts->flags & ~(uint32_t)GS_FLAG_FORWARD_ONLY) != 0) return fail(GS_ERR_INVALID_ARG, "unknown flags");
+  const uint32_t known = GS_FLAG_FORWARD_ONLY | GS_FLAG_BWD_ONE_BRICK | GS_FLAG_BWD_WINDOW_256 | GS_FLAG_EMIT_STAGE_4K |
+                        GS_FLAG_EMIT_STAGE_6K;
+  if ((opts->flags & ~known) != 0) return fail(GS_ERR_INVALID_ARG, "unknown flags");
+  if ((opts->flags & GS_FLAG_EMIT_STAGE_4K) && (opts->flags & GS_FLAG_EMIT_STAGE_6K))
+    return fail(GS_ERR_INVALID_ARG, "choose one emit stage flag");
   return GS_OK;
 }
 
@@ -193,6 +197,7 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
   if ((rc = check_opts(opts))) return rc;
   std::memset(T, 0, sizeof *T);
   T->ns = bt->ns;
+  T->bwd_bricks = bwd_bricks_of(opts->flags);
   int64_t g0 = 0, b0 = 0, p0 = 0, v0 = 0, o0 = 0;
   for (int k = 0; k < bt->ns; ++k) {
     const gs_grid_t *gr = &bt->grid[k];
@@ -217,7 +222,7 @@ static int make_table(const gs_batch_t *bt, const gs_opts_t *opts, int32_t zdown
     }
     g0 += bt->n[k];
     b0 += sd.bg.nbricks;
-    p0 += (sd.bg.nbricks + kBwdBricks - 1) / kBwdBricks;
+    p0 += (sd.bg.nbricks + T->bwd_bricks - 1) / T->bwd_bricks;
     v0 += nvox;
   }
   T->n_total = g0;
@@ -415,7 +420,7 @@ static int bin_all(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t 
   int rc;
   if ((rc = bin_front(g, T, opts, bins, L, s, step))) return rc;
   hipError_t e;
-  if ((e = launch_emit(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
+  if ((e = launch_emit(T, opts->cutoff, opts->flags, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
   if ((e = launch_sort(T, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
   return GS_OK;
 }
@@ -477,7 +482,7 @@ int gs_count_evals(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts
   int rc = check_common(g, &one.b, opts, bins, 0, &T, &L);
   if (rc) return rc;
   if (!d_counts) return fail(GS_ERR_INVALID_ARG, "d_counts is NULL");
-  hipError_t e = launch_count_evals(T, opts->bx, opts->cutoff, bins->ws, L, d_counts, (hipStream_t)stream);
+  hipError_t e = launch_count_evals(T, opts->bx, opts->flags, opts->cutoff, bins->ws, L, d_counts, (hipStream_t)stream);
   return e == hipSuccess ? GS_OK : hip_fail(e, "count_evals");
 }
 
@@ -491,7 +496,7 @@ int gs_render_bwd_batch(const gs_gaussians_t *g, const gs_batch_t *batch, const 
   if (opts->flags & GS_FLAG_FORWARD_ONLY) return fail(GS_ERR_INVALID_ARG, "forward-only workspace: no backward");
   if (!I || !W || !dL_dI || !grads) return fail(GS_ERR_INVALID_ARG, "I, W, dL_dI and grads are required");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_bwd(T, opts->bx, opts->cutoff, opts->eps, bins->ws, L, I, W, dL_dI, s);
+  hipError_t e = launch_bwd(T, opts->bx, opts->flags, opts->cutoff, opts->eps, bins->ws, L, I, W, dL_dI, s);
   if (e != hipSuccess) return hip_fail(e, "render_bwd");
   e = launch_reduce_chain(*g, bins->ws, L, *grads, s);
   return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_chain");
@@ -595,7 +600,7 @@ int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_ba
     // the z-mean groups coincide with the brick's z extent: loss fused into the backward's staging,
     // gradient reduction fused with Adam
     float *loss_part = (float *)buf->scratch;
-    e = launch_bwd_fit(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, lr_obs, loss_part, s);
+    e = launch_bwd_fit(T, o.bx, o.flags, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, lr_obs, loss_part, s);
     if (e != hipSuccess) return hip_fail(e, "render_bwd");
     e = launch_reduce_adam(T, *st, bins->ws, L, buf->grads, fo->adam, loss_part, buf->loss, s);
     return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_adam");
@@ -606,7 +611,7 @@ int gs_fit_step_batch(const gs_fit_state_t *st, const float *lr_obs, const gs_ba
                         buf->loss + k, buf->scratch, s, (const DevStatus *)((char *)bins->ws + L.status));
     if (e != hipSuccess) return hip_fail(e, "loss_l1z");
   }
-  e = launch_bwd(T, o.bx, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, buf->dL_dI, s);
+  e = launch_bwd(T, o.bx, o.flags, o.cutoff, o.eps, bins->ws, L, buf->I, buf->W, buf->dL_dI, s);
   if (e != hipSuccess) return hip_fail(e, "render_bwd");
   e = launch_reduce_adam(T, *st, bins->ws, L, buf->grads, fo->adam, nullptr, buf->loss, s);
   return e == hipSuccess ? GS_OK : hip_fail(e, "reduce_adam");

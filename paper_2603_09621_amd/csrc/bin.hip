@@ -596,13 +596,14 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
   }
 }
 
-hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s) {
+hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *ws, const WsLayout &L, hipStream_t s) {
   if (T.n_total == 0) return hipSuccess;
   char *b = (char *)ws;
   const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
   // the capacity is sized from the exact key count (times a headroom): its share per block tells
   // whether blocks typically hold more keys than the small stage (the results do not depend on it)
-  const bool large = L.cap / blocks > (int64_t)(7 * kEmitStageSmall / 8);
+  const bool large = (flags & GS_FLAG_EMIT_STAGE_6K) ||
+                     (!(flags & GS_FLAG_EMIT_STAGE_4K) && L.cap / blocks > (int64_t)(7 * kEmitStageSmall / 8));
   auto emit = large ? k_emit<kEmitStageLarge> : k_emit<kEmitStageSmall>;
   prof_begin(s);
   emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),

@@ -53,8 +53,9 @@ struct BrickGrid {
 // small table passed by value as a kernel argument.  A single scan is the one-entry table.
 constexpr int kMaxScans = 16;
 
-// Bricks per backward wave: consecutive bricks of a scan whose keys are ordered together.
-constexpr int kBwdBricks = 2;
+// Bricks per backward wave (consecutive bricks of a scan whose keys are ordered together): 2, or 1
+// with GS_FLAG_BWD_ONE_BRICK.
+__host__ __device__ inline int bwd_bricks_of(uint32_t flags) { return (flags & GS_FLAG_BWD_ONE_BRICK) ? 1 : 2; }
 
 struct ScanDesc {
   BrickGrid bg;
@@ -63,7 +64,7 @@ struct ScanDesc {
   const float *mu, *ls, *quat, *amp, *relax;
   int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated numbering
   int64_t b0;     // first (global) brick of the scan
-  int64_t p0;     // first (global) brick group of the scan (the backward takes kBwdBricks bricks per wave)
+  int64_t p0;     // first (global) brick group of the scan (the backward takes bwd_bricks bricks per wave)
   int64_t v0;     // first voxel of the scan's volume in the concatenated volumes
   int64_t o0;     // first LR voxel of the scan's observation in the concatenated observations
   float gscale;   // fit loss: dL/dI magnitude 1 / (zdown * nLR)
@@ -72,6 +73,7 @@ struct ScanDesc {
 
 struct ScanTable {
   int32_t ns;
+  int32_t bwd_bricks;  // bricks per backward group (bwd_bricks_of the options' flags)
   int64_t n_total, nbricks_total, ngroups_total;
   ScanDesc s[kMaxScans];
   __host__ __device__ __forceinline__ int of_gauss(int64_t i) const {
@@ -139,7 +141,7 @@ void prof_end(hipStream_t s, const char *name);
 // launches.  `g` / `st` hold the concatenated Gaussians of all scans of T.
 hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns, hipStream_t s);
-hipError_t launch_emit(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
+hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_fwd(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
                       float *I, float *W, hipStream_t s);
@@ -147,12 +149,13 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
                               int64_t *d_count, hipStream_t s);
 // Evaluation counts (gs_count_evals): kEvalCounts int64 entries.
 constexpr int kEvalCounts = 6;
-hipError_t launch_count_evals(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
-                              int64_t *d_counts, hipStream_t s);
-hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+hipError_t launch_count_evals(const ScanTable &T, int bx, uint32_t flags, float cutoff, const void *ws,
+                              const WsLayout &L, int64_t *d_counts, hipStream_t s);
+hipError_t launch_bwd(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, void *ws, const WsLayout &L,
                       const float *I, const float *W, const float *dLdI, hipStream_t s);
-hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
-                          const float *I, const float *W, const float *obs, float *loss_part, hipStream_t s);
+hipError_t launch_bwd_fit(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, void *ws,
+                          const WsLayout &L, const float *I, const float *W, const float *obs, float *loss_part,
+                          hipStream_t s);
 hipError_t launch_reduce_chain(const gs_gaussians_t &g, const void *ws, const WsLayout &L, const gs_grads_t &gr,
                                hipStream_t s);
 hipError_t launch_reduce_adam(const ScanTable &T, const gs_fit_state_t &g, const void *ws, const WsLayout &L,

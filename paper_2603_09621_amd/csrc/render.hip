@@ -2,7 +2,7 @@
 //
 // Bricks are BX x 8 x 4 voxels (BX in {4, 8, 16}; the paper uses 8 x 8 x 4).  Every launch covers
 // the bricks of all scans of a scan table (the forward: one workgroup per brick; the backward: one
-// per group of kBwdBricks consecutive bricks of a scan).
+// per group of G consecutive bricks of a scan).
 //
 // Forward: BX/2 waves per brick; each wave owns a 4x4x4 quarter of the brick, split into four
 // 4x2x2 cells.  The brick's Gaussian list is staged through LDS in chunks; while staging, each
@@ -14,7 +14,7 @@
 // (numerator S, denominator W).  The four slots' partial sums of a voxel are added in a fixed order
 // at the end, so the result is bitwise deterministic.
 //
-// Backward: one wave per group of kBwdBricks (two) consecutive bricks, one Gaussian (key) per lane.
+// Backward: one wave per group of G (two, or one) consecutive bricks, one Gaussian (key) per lane.
 // The bricks' per-voxel factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of
 // the group's bricks are ordered together by their number of rows in their brick so that the lanes of
 // a wave run similar numbers of iterations (two bricks give the ordering twice as many keys to
@@ -298,8 +298,8 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
-constexpr int kBwdThreads = 64;  // one wave per group of kBwdBricks consecutive bricks
-constexpr int kBwdWindow = 512;  // keys ordered by work per pass over the group's lists
+constexpr int kBwdThreads = 64;  // one wave per group of G (two, or one) consecutive bricks
+// keys ordered by work per pass over the group's lists: WIN = 512 (or 256) at a time
 constexpr int kBwdBuckets = 34;  // rows per key in its brick: 32 .. 0 (bucket 0 = 32 rows), then empty
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
@@ -380,7 +380,7 @@ __device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0,
 // the row tests only, counting evaluated and issued voxel slots; nothing is written but the counts).
 constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 
-template <int BX, int MODE>
+template <int BX, int MODE, int G, int WIN>
 __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cutoff, float eps,
                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                      const uint32_t *__restrict__ list_gid,
@@ -396,14 +396,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   // LDS voxels per brick, padded so that the same row of different bricks falls into different banks
   // (keys of similar boxes in the bricks read the same row index at the same time)
   constexpr int BV = 32 * RP + 4;
-  constexpr int G = kBwdBricks;
   if (st->overflow) return;
   __shared__ float2 sCI[G * BV];
-  __shared__ uint16_t sorder[kBwdWindow];
-  __shared__ uint8_t sbucket[kBwdWindow];
+  __shared__ uint16_t sorder[WIN];
+  __shared__ uint8_t sbucket[WIN];
   // key's row box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the group
   // (bits 10-11), empty (bit 12)
-  __shared__ uint16_t sbox[kBwdWindow];
+  __shared__ uint16_t sbox[WIN];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   __shared__ int sorg[G][3];  // brick origins (voxel indices)
   __shared__ float spy[G][8], spz[G][4];  // voxel-centre coordinates of the bricks' rows and slices
@@ -467,8 +466,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     ye[j] = min(y0[j] + 7, bg.ny - 1);
     ze[j] = min(z0[j] + 3, bg.nz - 1);
   }
-  for (uint32_t w0 = start; w0 < end; w0 += kBwdWindow) {
-    const int L = (int)min((uint32_t)kBwdWindow, end - w0);
+  for (uint32_t w0 = start; w0 < end; w0 += WIN) {
+    const int L = (int)min((uint32_t)WIN, end - w0);
     // order the window's keys (of all bricks of the group) by their number of rows in their brick,
     // most first, so that the lanes of a wave run similar numbers of row iterations (each key's
     // result is independent of where it runs, so the order does not change any result)
@@ -636,48 +635,65 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   }
 }
 
-template <int MODE>
-static hipError_t bwd_dispatch(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
-                               const float *I, const float *W, const float *gI, const float *obs, float *loss_part,
-                               hipStream_t s, unsigned long long *evals = nullptr) {
-  char *b = (char *)ws;
+template <int MODE, int G, int WIN>
+static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, const EvalRec *er, const CullRec *cr,
+                       const uint32_t *lg, const uint32_t *ls, const uint2 *bo, const DevStatus *st, const float *I,
+                       const float *W, const float *gI, const float *obs, float *loss_part, int64_t cap, float4 *part,
+                       unsigned long long *evals, hipStream_t s) {
   const unsigned nb = (unsigned)T.ngroups_total;  // one wave per group of bricks
-  if (nb == 0) return hipSuccess;
+  switch (bx) {
+    case 4:
+      k_bwd<4, MODE, G, WIN><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+                                                        loss_part, cap, part, evals);
+      break;
+    case 8:
+      k_bwd<8, MODE, G, WIN><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+                                                        loss_part, cap, part, evals);
+      break;
+    default:
+      k_bwd<16, MODE, G, WIN><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+                                                         loss_part, cap, part, evals);
+      break;
+  }
+}
+
+template <int MODE>
+static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, const void *ws,
+                               const WsLayout &L, const float *I, const float *W, const float *gI, const float *obs,
+                               float *loss_part, hipStream_t s, unsigned long long *evals = nullptr) {
+  char *b = (char *)ws;
+  if (T.ngroups_total == 0) return hipSuccess;
   const EvalRec *er = (const EvalRec *)(b + L.evalrec);
   const CullRec *cr = (const CullRec *)(b + L.cullrec);
   const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *ls = (const uint32_t *)(b + L.list_slot);
   const uint2 *bo = (const uint2 *)(b + L.brick_se);
   const DevStatus *st = (const DevStatus *)(b + L.status);
   float4 *part = MODE == kBwdCount ? nullptr : (float4 *)(b + L.partials);
-  switch (bx) {
-    case 4:
-      k_bwd<4, MODE><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
-                                                part, evals);
-      break;
-    case 8:
-      k_bwd<8, MODE><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap,
-                                                part, evals);
-      break;
-    default:
-      k_bwd<16, MODE><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part,
-                                                 L.cap, part, evals);
-      break;
-  }
+  const bool one = T.bwd_bricks == 1, w256 = (flags & GS_FLAG_BWD_WINDOW_256) != 0;
+  if (one && w256)
+    bwd_launch<MODE, 1, 256>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
+  else if (one)
+    bwd_launch<MODE, 1, 512>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
+  else if (w256)
+    bwd_launch<MODE, 2, 256>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
+  else
+    bwd_launch<MODE, 2, 512>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
   return hipGetLastError();
 }
 
-hipError_t launch_bwd(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
+hipError_t launch_bwd(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, void *ws, const WsLayout &L,
                       const float *I, const float *W, const float *dLdI, hipStream_t s) {
   prof_begin(s);
-  hipError_t e = bwd_dispatch<kBwdPlain>(T, bx, cutoff, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
+  hipError_t e = bwd_dispatch<kBwdPlain>(T, bx, flags, cutoff, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
   prof_end(s, "render_bwd");
   return e;
 }
 
-hipError_t launch_bwd_fit(const ScanTable &T, int bx, float cutoff, float eps, void *ws, const WsLayout &L,
-                          const float *I, const float *W, const float *obs, float *loss_part, hipStream_t s) {
+hipError_t launch_bwd_fit(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, void *ws,
+                          const WsLayout &L, const float *I, const float *W, const float *obs, float *loss_part,
+                          hipStream_t s) {
   prof_begin(s);
-  hipError_t e = bwd_dispatch<kBwdFit>(T, bx, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
+  hipError_t e = bwd_dispatch<kBwdFit>(T, bx, flags, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
   prof_end(s, "render_bwd");
   return e;
 }
@@ -686,15 +702,16 @@ __global__ void k_zero_u64_n(unsigned long long *p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
-hipError_t launch_count_evals(const ScanTable &T, int bx, float cutoff, const void *ws, const WsLayout &L,
-                              int64_t *d_counts, hipStream_t s) {
+hipError_t launch_count_evals(const ScanTable &T, int bx, uint32_t flags, float cutoff, const void *ws,
+                              const WsLayout &L, int64_t *d_counts, hipStream_t s) {
   prof_begin(s);
   unsigned long long *c = (unsigned long long *)d_counts;
   k_zero_u64_n<<<1, 64, 0, s>>>(c, kEvalCounts);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = fwd_dispatch<true>(T, bx, cutoff, 0.f, ws, L, nullptr, nullptr, c, s, c + 1);
   if (e == hipSuccess)
-    e = bwd_dispatch<kBwdCount>(T, bx, cutoff, 0.f, ws, L, nullptr, nullptr, nullptr, nullptr, nullptr, s, c + 3);
+    e = bwd_dispatch<kBwdCount>(T, bx, flags, cutoff, 0.f, ws, L, nullptr, nullptr, nullptr, nullptr, nullptr, s,
+                                c + 3);
   prof_end(s, "count_evals");
   return e;
 }

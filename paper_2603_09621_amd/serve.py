@@ -113,7 +113,7 @@ class Server:
         self.lr_dims = [tuple(int(x) for x in d) for d in lr_dims]
         self.budget = int(hbm_budget)
         o = opts or gs.Opts()
-        self.ropts = gs.Opts(bx=o.bx, by=o.by, bz=o.bz, cutoff=o.cutoff, eps=o.eps, forward_only=True)
+        self.ropts = o.with_(forward_only=True)
         self.fo = fit_opts or gs.FitOpts(None)
         self.max_batch = max(1, min(max_batch, MAX_SCANS))
         self.max_fits = max(1, min(max_fits, MAX_SCANS))

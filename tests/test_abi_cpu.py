@@ -138,3 +138,21 @@ def test_noalloc_rejects_sets_beyond_the_static_scratch():
     assert m and gs.GS_STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
     rc = gs._lib.gs_render_fwd_noalloc(ctypes.byref(g), ctypes.byref(grid), ctypes.byref(opts), None, None, None, None)
     assert rc == gs.GS_ERR_INVALID_ARG
+
+
+def test_tuning_flags_are_checked():
+    """The tuning bits are accepted (one emit stage at most); other bits are rejected."""
+    g = gs.Grid(16, 16, 8)
+    for o in (gs.Opts(bwd_bricks=1), gs.Opts(bwd_window=256), gs.Opts(emit_stage=4096), gs.Opts(emit_stage=6144),
+              gs.Opts(bwd_bricks=1, bwd_window=256, emit_stage=6144, forward_only=True)):
+        assert gs.gs_workspace_size(10, g, o, 10) > 0
+    out = ctypes.c_size_t(0)
+    both = gs.gs_opts_t(8, 8, 4, 3.0, 1e-8, gs.FLAG_EMIT_STAGE_4K | gs.FLAG_EMIT_STAGE_6K)
+    assert gs._lib.gs_workspace_size(10, ctypes.byref(g.c()), ctypes.byref(both), 10, ctypes.byref(out)) == \
+        gs.GS_ERR_INVALID_ARG
+    for bit in (1 << 1, 1 << 8, 1 << 31):
+        bad = gs.gs_opts_t(8, 8, 4, 3.0, 1e-8, bit)
+        assert gs._lib.gs_workspace_size(10, ctypes.byref(g.c()), ctypes.byref(bad), 10, ctypes.byref(out)) == \
+            gs.GS_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        gs.Opts(bwd_bricks=3).c()

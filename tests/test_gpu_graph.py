@@ -82,10 +82,47 @@ def test_autotuner_picks_and_caches(tmp_path):
     rec = json.load(open(path))
     assert len(rec) == 1
     (entry,) = rec.values()
-    assert entry["bx"] == opts.bx and set(entry["ms"]) == {str(b) for b in autotune.CANDIDATES}
+    assert entry["opts"] == opts.tuning
+    # every width was timed, and every value of each result-invariant knob at the chosen width
+    widths = {k.split("/")[0] for k in entry["ms"]}
+    assert widths == {f"bx{b}" for b in autotune.CANDIDATES}
+    assert {k for k in entry["ms"] if k.startswith(f"bx{opts.bx}/")} >= {
+        f"bx{opts.bx}/g{g_}/w512/e0" for g_ in (1, 2)}
+    assert opts.bwd_bricks in (1, 2) and opts.bwd_window in (256, 512) and opts.emit_stage in (0, 4096, 6144)
     # a second tuner reads the cache and measures nothing
     t2 = autotune.Tuner(path)
     t2._time = None  # would raise if called
-    assert t2.fit_opts(g, batch, obs, zdown=4).bx == opts.bx
+    assert t2.fit_opts(g, batch, obs, zdown=4).tuning == opts.tuning
     ropts = t.render_opts(g, batch, steps=2)
     assert ropts.bx in autotune.CANDIDATES
+
+
+def test_tuning_knobs_leave_results_bitwise_equal():
+    """Bricks per backward wave, the backward's ordering window and the emit's stage change speed
+    only: renders, gradients and fit steps are bitwise those of the defaults, at every width."""
+    gs = gs_mod()
+    data, batch, obs = _batch(4)
+    variants = [dict(), dict(bwd_bricks=1), dict(bwd_window=256), dict(bwd_bricks=1, bwd_window=256),
+                dict(emit_stage=4096), dict(emit_stage=6144)]
+    for bx in (4, 8, 16):
+        ref = None
+        for kw in variants:
+            opts = gs.Opts(bx=bx, **kw)
+            g = gs.concat([gs.Gaussians.from_numpy(p) for p, _, _ in data])
+            bins = gs.plan_bins_batch(g, batch, opts, headroom=1.5)
+            st = gs.FitState(g, nscans=len(batch))
+            buf = gs.FitBuffers(g.n, batch, relax=g.relax is not None, device="cuda", need_dL_dI=False)
+            fo = gs.FitOpts(None, opts=opts, zdown=4)
+            for _ in range(2):
+                gs.gs_fit_step_batch(st, obs, batch, fo, bins, buf)
+            gs.gs_status(bins)
+            ev = torch.zeros(6, dtype=torch.int64, device="cuda")
+            gs.gs_count_pairs_batch(g, batch, opts, bins, ev[:1])
+            out = {k: getattr(g, k).clone() for k in gs.GROUPS if getattr(g, k) is not None}
+            out.update(I=buf.I.clone(), W=buf.W.clone(), loss=buf.loss.clone(), pairs=ev[:1].clone(),
+                       **{f"d_{k}": v.clone() for k, v in buf.grads.as_dict().items() if v is not None})
+            if ref is None:
+                ref = out
+                continue
+            for k in ref:
+                assert torch.equal(out[k], ref[k]), f"bx {bx} {kw}: {k} differs from the default options"
