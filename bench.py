@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--n", type=int, default=500000)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--bx", type=int, default=8, help="brick width along x (4, 8 or 16)")
+    ap.add_argument("--bwd-bricks", type=int, default=2, help="bricks per backward wave (2 or 1)")
+    ap.add_argument("--bwd-window", type=int, default=512, help="backward ordering window (512 or 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-scan comparison")
@@ -317,7 +319,7 @@ def aniso_section(args, dev):
     dims = (320, 320, 256)
     print(f"[bench] anisotropic workload in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     grid = gs.Grid(*dims)
-    opts = gs.Opts(bx=args.bx)
+    opts = gs.Opts(bx=args.bx, bwd_bricks=args.bwd_bricks, bwd_window=args.bwd_window)
     g = gs.Gaussians.from_numpy(p, device=dev)
     T = torch.from_numpy(T_np).to(dev)
     bins = gs.plan_bins(g, grid, opts, headroom=1.1)
@@ -402,7 +404,7 @@ def main():
 
     grid = gs.Grid(*dims)
     g = gs.Gaussians.from_numpy(p, device=dev)
-    fo = gs.FitOpts(grid, opts=gs.Opts(bx=args.bx))
+    fo = gs.FitOpts(grid, opts=gs.Opts(bx=args.bx, bwd_bricks=args.bwd_bricks, bwd_window=args.bwd_window))
     obs = torch.from_numpy(lr_obs).to(dev)
     bins = gs.plan_bins(g, grid, fo.opts, headroom=1.5)
     st = gs.FitState(g)
@@ -598,7 +600,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single-scan zero-shot fit: HR {dims[0]}x{dims[1]}x{dims[2]} phantom, LR = z-mean "
                                f"of 4, {args.n} Gaussians on the LR lattice, L1 + Adam",
-                   "global_batch": 1, "brick": [fo.opts.bx, fo.opts.by, fo.opts.bz]},
+                   "global_batch": 1, "brick": [fo.opts.bx, fo.opts.by, fo.opts.bz], "tuning": fo.opts.tuning},
         "fit_iters_per_s": 1.0 / t_step,
         "ms_per_step_hip_graph": ms_graph,
         "useful_pairs_per_step": U_step,
