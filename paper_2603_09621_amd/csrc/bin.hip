@@ -638,46 +638,94 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
   __syncthreads();
   const int64_t K = live_keys(st, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
-  for (int j = 0; j < kSortItems; ++j) {
-    const int64_t idx = base + j * kSortThreads + t;
-    if (idx < K) atomicAdd(&cnt[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+  // thread t counts the tile's keys 16 t .. 16 t + 15 as runs of equal digits: after the previous
+  // passes neighbouring keys mostly share this digit, and one LDS atomic per run instead of one per
+  // key avoids the lanes of a wave queueing on the same counter
+  static_assert(kSortItems == 16, "the histogram reads 16 consecutive keys per thread");
+  const int64_t k0 = base + (int64_t)kSortItems * t;
+  const int nv = (int)max((int64_t)0, min((int64_t)kSortItems, K - k0));
+  if (nv > 0) {
+    uint32_t kv[kSortItems];
+    if (nv == kSortItems) {
+      const uint4 *q = reinterpret_cast<const uint4 *>(keys + k0);  // 64-B aligned
+#pragma unroll
+      for (int j = 0; j < kSortItems / 4; ++j) {
+        const uint4 v = q[j];
+        kv[4 * j] = v.x;
+        kv[4 * j + 1] = v.y;
+        kv[4 * j + 2] = v.z;
+        kv[4 * j + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kSortItems; ++j) kv[j] = keys[k0 + min(j, nv - 1)];
+    }
+    uint32_t prev = (kv[0] >> shift) & (kRadix - 1), run = 1;
+#pragma unroll
+    for (int j = 1; j < kSortItems; ++j) {
+      if (j < nv) {
+        const uint32_t d = (kv[j] >> shift) & (kRadix - 1);
+        if (d != prev) {
+          atomicAdd(&cnt[prev], run);
+          prev = d;
+          run = 0;
+        }
+        ++run;
+      }
+    }
+    atomicAdd(&cnt[prev], run);
   }
   __syncthreads();
   hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
 }
 
 // Per digit (one block each): exclusive scan of the digit's tile counts along the tiles, in place,
-// and the digit's total.  The digits' own offsets (an exclusive scan of the 256 totals) are formed by
-// every scatter block from the totals.
+// and the digit's total.  Thread t owns a contiguous segment of the row (its loads issued eight at a
+// time); one block-wide scan of the segment sums gives each segment's start.  The digits' own
+// offsets (an exclusive scan of the 256 totals) are formed by every scatter block from the totals.
 __global__ __launch_bounds__(kSortThreads) void k_radix_colscan(uint32_t *__restrict__ hist, int ntiles,
                                                                  uint32_t *__restrict__ dtot) {
   __shared__ uint32_t wsum[kSortThreads / 64];
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
-  uint32_t carry = 0;
-  for (int c0 = 0; c0 < ntiles; c0 += kSortThreads) {
-    const int i = c0 + t;
-    const uint32_t v = i < ntiles ? row[i] : 0u;
-    uint32_t incl = v;
+  const int m = (ntiles + kSortThreads - 1) / kSortThreads;
+  const int lo = min(t * m, ntiles), hi = min(lo + m, ntiles);
+  constexpr int G = 8;
+  uint32_t s = 0;
+  for (int j0 = lo; j0 < hi; j0 += G) {
+    uint32_t v[G];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t o = __shfl_up(incl, d, 64);
-      if (l >= d) incl += o;
-    }
-    if (l == 63) wsum[w] = incl;
-    __syncthreads();
-    uint32_t off = carry, tot = 0;
+    for (int k = 0; k < G; ++k) v[k] = row[min(j0 + k, hi - 1)];
 #pragma unroll
-    for (int k = 0; k < kSortThreads / 64; ++k) {
-      off += k < w ? wsum[k] : 0u;
-      tot += wsum[k];
-    }
-    if (i < ntiles) row[i] = off + incl - v;
-    carry += tot;
-    __syncthreads();
+    for (int k = 0; k < G; ++k) s += j0 + k < hi ? v[k] : 0u;
   }
-  if (t == 0) dtot[blockIdx.x] = carry;
+  uint32_t incl = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, 64);
+    if (l >= d) incl += o;
+  }
+  if (l == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - s, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kSortThreads / 64; ++k) {
+    run += k < w ? wsum[k] : 0u;
+    tot += wsum[k];
+  }
+  for (int j0 = lo; j0 < hi; j0 += G) {
+    uint32_t v[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) v[k] = row[min(j0 + k, hi - 1)];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (j0 + k < hi) {
+        row[j0 + k] = run;
+        run += v[k];
+      }
+    }
+  }
+  if (t == 0) dtot[blockIdx.x] = tot;
 }
 
 template <bool LAST>
@@ -695,6 +743,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= K) return;  // uniform per block
   const int n_tile = (int)min((int64_t)kSortTile, K - base);
+  // all of the thread's loads (its keys, its digit's tile offset, the digit totals) are issued first,
+  // so the tile pays one memory latency (the ranking's LDS accesses would otherwise hold each key's
+  // load until the previous key is ranked)
+  // (loads unconditional, at positions clamped to the tile's last key; lanes past the end are masked
+  // in the ranking)
+  const uint64_t lt = lanemask_lt();
+  const int tw = w * (64 * kSortItems) + l;  // position in the tile of the thread's first key
+  uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) keys[r] = kin[base + min(tw + r * 64, n_tile - 1)];
+  if (vin) {
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) vals[r] = vin[base + min(tw + r * 64, n_tile - 1)];
+  } else {
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) vals[r] = (uint32_t)(base + tw + r * 64);
+  }
+  const uint32_t toff = offsets[(int64_t)t * ntiles + blockIdx.x];
 #pragma unroll
   for (int v = 0; v < kSortThreads / 64; ++v) wcnt[v][t] = 0;
   {  // digit base = exclusive scan of the digit totals (one wave, 4 digits per lane)
@@ -714,17 +780,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       tdo[4 * t + 3] = ex + a0 + a1 + a2;
     }
     __syncthreads();
-    goff[t] = tdo[t] + offsets[(int64_t)t * ntiles + blockIdx.x];
+    goff[t] = tdo[t] + toff;
   }
   __syncthreads();
-  const uint64_t lt = lanemask_lt();
-  uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int li = w * (64 * kSortItems) + r * 64 + l;  // position in the tile, wave-contiguous
-    const bool valid = li < n_tile;
-    const uint32_t key = valid ? kin[base + li] : 0u;
-    const uint32_t val = valid ? (vin ? vin[base + li] : (uint32_t)(base + li)) : 0u;
+    const bool valid = tw + r * 64 < n_tile;  // position in the tile, wave-contiguous
+    const uint32_t key = keys[r];
     const uint32_t d = (key >> shift) & (kRadix - 1);
     uint64_t m = __ballot(valid);
 #pragma unroll
@@ -740,8 +802,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __builtin_amdgcn_wave_barrier();
     if (valid && before == 0) wc[d] = prev + (uint32_t)__popcll(m);
     __builtin_amdgcn_wave_barrier();
-    keys[r] = key;
-    vals[r] = val;
     rank[r] = valid ? prev + before : 0xFFFFFFFFu;
   }
   __syncthreads();
@@ -781,13 +841,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
   }
   __syncthreads();
-  for (int i = t; i < n_tile; i += kSortThreads) {
-    const uint32_t key = skey[i], val = sval[i];
-    const uint32_t d = (key >> shift) & (kRadix - 1);
-    const uint32_t pos = goff[d] + ((uint32_t)i - tdo[d]);
-    kout[pos] = key;
-    vout[pos] = val;
-    if (LAST) gout[pos] = key_gid[val];
+  // the tile in digit order: positions t, t + 256, ... per thread; in the last pass every Gaussian-index
+  // lookup of the thread is issued before the first store
+  uint32_t gid[kSortItems];
+  if (LAST) {
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) gid[j] = key_gid[sval[min(t + j * kSortThreads, n_tile - 1)]];
+  }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int i = t + j * kSortThreads;
+    if (i < n_tile) {
+      const uint32_t key = skey[i], val = sval[i];
+      const uint32_t d = (key >> shift) & (kRadix - 1);
+      const uint32_t pos = goff[d] + ((uint32_t)i - tdo[d]);
+      kout[pos] = key;
+      vout[pos] = val;
+      if (LAST) gout[pos] = gid[j];
+    }
   }
 }
 
