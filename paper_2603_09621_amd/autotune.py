@@ -2,15 +2,16 @@
 
 The knobs change speed, not the method: the brick width along x (4, 8 or 16 voxels, 8 x 4 in y x z;
 §3.3 uses 8 x 8 x 4), which changes results only by FP32 summation order, and three choices that
-leave every result bitwise the same: the number of consecutive bricks whose keys one backward wave
-orders together (2 or 1), the size of the backward's ordering window (512 or 256 keys) and the
-emit's LDS stage (4096 or 6144 keys per workgroup, or chosen from the key capacity).  Which setting
-is fastest depends on the Gaussians' extent relative to the brick, on the key counts and on how
-long-tailed they are, so the tuner measures: it runs a few fit steps (or renders) of the caller's
-own workload, on copies of the parameters, timed with HIP events on the launch stream, and searches
-the knobs one at a time (coordinate descent: brick width first, then the others at the best width).
-Choices are cached per workload signature (grid sizes, Gaussian count and mean extent, bucketed) in
-memory and, if a path is given, in a JSON file.
+leave every result bitwise the same: the number of consecutive bricks whose keys one backward
+workgroup orders together (8 with four waves, or 2 or 1 with one wave), the size of the backward's
+ordering window (512 or 256 keys per wave) and the emit's LDS stage (4096 or 6144 keys per
+workgroup, or chosen from the key capacity).  Which setting is fastest depends on the Gaussians'
+extent relative to the brick, on the key counts and on how long-tailed they are, so the tuner
+measures: it runs a few fit steps (or renders) of the caller's own workload, on copies of the
+parameters, timed with HIP events on the launch stream, and searches the knobs one at a time
+(coordinate descent: brick width first, then the others at the best width).  Choices are cached per
+workload signature (grid sizes, Gaussian count and mean extent, bucketed) in memory and, if a path
+is given, in a JSON file.
 """
 from __future__ import annotations
 
@@ -25,7 +26,7 @@ from . import gs
 
 CANDIDATES = (4, 8, 16)
 # the result-invariant knobs, searched after the brick width, with their default first
-KNOBS = (("bwd_bricks", (2, 1)), ("bwd_window", (512, 256)), ("emit_stage", (0, 4096, 6144)))
+KNOBS = (("bwd_bricks", (8, 2, 1)), ("bwd_window", (512, 256)), ("emit_stage", (0, 4096, 6144)))
 FIT_KNOBS = ("bwd_bricks", "bwd_window", "emit_stage")
 RENDER_KNOBS = ("emit_stage",)
 

@@ -169,11 +169,13 @@ static int check_opts(const gs_opts_t *opts) {
     return fail(GS_ERR_UNSUPPORTED, "brick %dx%dx%d not supported by this library", opts->bx, opts->by, opts->bz);
   if (!(opts->cutoff > 0.f) || !std::isfinite(opts->cutoff)) return fail(GS_ERR_INVALID_ARG, "cutoff must be > 0");
   if (!(opts->eps > 0.f) || !std::isfinite(opts->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be > 0 and finite");
-  const uint32_t known = GS_FLAG_FORWARD_ONLY | GS_FLAG_BWD_ONE_BRICK | GS_FLAG_BWD_WINDOW_256 | GS_FLAG_EMIT_STAGE_4K |
-                        GS_FLAG_EMIT_STAGE_6K;
+  const uint32_t known = GS_FLAG_FORWARD_ONLY | GS_FLAG_BWD_ONE_BRICK | GS_FLAG_BWD_TWO_BRICKS |
+                        GS_FLAG_BWD_WINDOW_256 | GS_FLAG_EMIT_STAGE_4K | GS_FLAG_EMIT_STAGE_6K;
   if ((opts->flags & ~known) != 0) return fail(GS_ERR_INVALID_ARG, "unknown flags");
   if ((opts->flags & GS_FLAG_EMIT_STAGE_4K) && (opts->flags & GS_FLAG_EMIT_STAGE_6K))
     return fail(GS_ERR_INVALID_ARG, "choose one emit stage flag");
+  if ((opts->flags & GS_FLAG_BWD_ONE_BRICK) && (opts->flags & GS_FLAG_BWD_TWO_BRICKS))
+    return fail(GS_ERR_INVALID_ARG, "choose one backward group flag");
   return GS_OK;
 }
 

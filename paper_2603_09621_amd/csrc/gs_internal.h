@@ -53,9 +53,11 @@ struct BrickGrid {
 // small table passed by value as a kernel argument.  A single scan is the one-entry table.
 constexpr int kMaxScans = 16;
 
-// Bricks per backward wave (consecutive bricks of a scan whose keys are ordered together): 2, or 1
-// with GS_FLAG_BWD_ONE_BRICK.
-__host__ __device__ inline int bwd_bricks_of(uint32_t flags) { return (flags & GS_FLAG_BWD_ONE_BRICK) ? 1 : 2; }
+// Bricks per backward workgroup (consecutive bricks of a scan whose keys are ordered together): 8
+// (four waves), or 2 or 1 (one wave) with GS_FLAG_BWD_TWO_BRICKS or GS_FLAG_BWD_ONE_BRICK.
+__host__ __device__ inline int bwd_bricks_of(uint32_t flags) {
+  return (flags & GS_FLAG_BWD_ONE_BRICK) ? 1 : (flags & GS_FLAG_BWD_TWO_BRICKS) ? 2 : 8;
+}
 
 struct ScanDesc {
   BrickGrid bg;
@@ -64,7 +66,7 @@ struct ScanDesc {
   const float *mu, *ls, *quat, *amp, *relax;
   int64_t g0, n;  // Gaussians [g0, g0 + n) of the concatenated numbering
   int64_t b0;     // first (global) brick of the scan
-  int64_t p0;     // first (global) brick group of the scan (the backward takes bwd_bricks bricks per wave)
+  int64_t p0;     // first (global) brick group of the scan (the backward takes bwd_bricks bricks per workgroup)
   int64_t v0;     // first voxel of the scan's volume in the concatenated volumes
   int64_t o0;     // first LR voxel of the scan's observation in the concatenated observations
   float gscale;   // fit loss: dL/dI magnitude 1 / (zdown * nLR)

@@ -14,11 +14,13 @@
 // (numerator S, denominator W).  The four slots' partial sums of a voxel are added in a fixed order
 // at the end, so the result is bitwise deterministic.
 //
-// Backward: one wave per group of G (two, or one) consecutive bricks, one Gaussian (key) per lane.
-// The bricks' per-voxel factors c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of
-// the group's bricks are ordered together by their number of rows in their brick so that the lanes of
-// a wave run similar numbers of iterations (two bricks give the ordering twice as many keys to
-// balance as one); each lane walks the rows of its Gaussian's box inside its brick in one flat loop, skips
+// Backward: one workgroup per group of G consecutive bricks (eight bricks and four waves, or two or
+// one brick and one wave), one Gaussian (key) per lane.  The bricks' per-voxel factors
+// c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of the group's bricks are ordered
+// together by their number of rows in their brick so that the lanes of a wave run similar numbers of
+// iterations (more bricks give the ordering more keys to balance: 64-key batches cut from the keys of
+// eight bricks are far more uniform than from two); each lane walks the rows of its Gaussian's box
+// inside its brick in one flat loop, skips
 // rows whose maximum exponent is below the cutoff, evaluates the BX voxels of a row unrolled, and
 // accumulates per row the moments sum(k), sum(k ck), sum(k ck^2) and sum(c w) of k = dL/dw * w
 // (ck: the voxel's x offset from the row's centre, so that dx = dxc + ck h with one dxc per key),
@@ -298,8 +300,7 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 //   p2 = (sum k dx dy, sum k dx dz, sum k dy dz, 0)
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
-constexpr int kBwdThreads = 64;  // one wave per group of G (two, or one) consecutive bricks
-// keys ordered by work per pass over the group's lists: WIN = 512 (or 256) at a time
+constexpr int kBwdWave = 64;  // lanes per wave; a backward workgroup has NW waves
 constexpr int kBwdBuckets = 34;  // rows per key in its brick: 32 .. 0 (bucket 0 = 32 rows), then empty
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
@@ -335,7 +336,7 @@ __device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0,
   if (FIT) {
     // BX * 8 columns of 4 voxels, one per thread and pass
     float absd = 0.f;
-    for (int col = t; col < BX * 8; col += kBwdThreads) {
+    for (int col = t; col < BX * 8; col += kBwdWave) {
       const int lx = col % BX, ly = col / BX;
       const int gx = x0 + lx, gy = y0 + ly;
       float c4[4] = {0.f, 0.f, 0.f, 0.f}, i4[4] = {0.f, 0.f, 0.f, 0.f};
@@ -362,7 +363,7 @@ __device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0,
   } else {
     // per voxel of the brick: c = dL/dI / (W + eps) and I; zero outside the grid, so that voxels
     // beyond the grid's edge contribute nothing
-    for (int v = t; v < BX * 32; v += kBwdThreads) {
+    for (int v = t; v < BX * 32; v += kBwdWave) {
       const int lx = v % BX, ly = (v / BX) & 7, lz = v / (BX * 8);
       const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
       float c = 0.f, iv = 0.f;
@@ -380,32 +381,43 @@ __device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0,
 // the row tests only, counting evaluated and issued voxel slots; nothing is written but the counts).
 constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 
-template <int BX, int MODE, int G, int WIN>
-__global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cutoff, float eps,
-                                                     const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
-                                                     const uint32_t *__restrict__ list_gid,
-                                                     const uint32_t *__restrict__ list_slot,
-                                                     const uint2 *__restrict__ brick_se, const DevStatus *st,
-                                                     const float *__restrict__ Iv, const float *__restrict__ Wv,
-                                                     const float *__restrict__ gI, const float *__restrict__ obs,
-                                                     float *__restrict__ loss_part, int64_t cap,
-                                                     float4 *__restrict__ part,
-                                                     unsigned long long *__restrict__ eval_count) {
+// One workgroup of NW waves per group of G consecutive bricks of a scan.  Wave w stages the bricks
+// j = w, w + NW, ... of the group (as a single wave: the fit's per-brick loss sums do not depend on the
+// workgroup shape).  The keys of all G bricks are ordered together, WIN at a time, by their number of
+// rows; the waves take the ordered keys 64 at a time, in a snake order over the waves (batch r NW + w,
+// then (r + 1) NW + NW - 1 - w, ...) so that the heaviest and the lightest batches are shared out.
+template <int BX, int MODE, int G, int WIN, int NW>
+__global__ __launch_bounds__(kBwdWave *NW) void k_bwd(const ScanTable T, float cutoff, float eps,
+                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
+                                                      const uint32_t *__restrict__ list_gid,
+                                                      const uint32_t *__restrict__ list_slot,
+                                                      const uint2 *__restrict__ brick_se, const DevStatus *st,
+                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
+                                                      const float *__restrict__ gI, const float *__restrict__ obs,
+                                                      float *__restrict__ loss_part, int64_t cap,
+                                                      float4 *__restrict__ part,
+                                                      unsigned long long *__restrict__ eval_count) {
   constexpr bool FIT = MODE == kBwdFit, COUNT = MODE == kBwdCount;
+  constexpr int NT = kBwdWave * NW;
   constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
   // LDS voxels per brick, padded so that the same row of different bricks falls into different banks
   // (keys of similar boxes in the bricks read the same row index at the same time)
   constexpr int BV = 32 * RP + 4;
+  static_assert(G <= 8, "the brick of a key takes 3 bits of its box word");
   if (st->overflow) return;
   __shared__ float2 sCI[G * BV];
   __shared__ uint16_t sorder[WIN];
   __shared__ uint8_t sbucket[WIN];
   // key's row box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the group
-  // (bits 10-11), empty (bit 12)
+  // (bits 10-12), empty (bit 13)
   __shared__ uint16_t sbox[WIN];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   __shared__ int sorg[G][3];  // brick origins (voxel indices)
   __shared__ float spy[G][8], spz[G][4];  // voxel-centre coordinates of the bricks' rows and slices
+  // boff[j]: where brick j's keys start in the group's contiguous key range (for a brick without
+  // keys, where the next brick's start), boff[G]: the range's end
+  __shared__ uint32_t sboff[G + 1];
+  __shared__ uint2 sse[G];
   const int64_t q = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_group(q)];
   const BrickGrid &bg = sd.bg;
@@ -413,59 +425,43 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   const int nbk = (int)min((int64_t)G, bg.nbricks - lb);
   const int64_t b = sd.b0 + lb;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  int x0[G], y0[G], z0[G];
-  // boff[j]: where brick j's keys start in the group's contiguous key range (for a brick without
-  // keys, where the next brick's start), boff[G]: the range's end
-  uint32_t boff[G + 1], bs[G], be[G];
-#pragma unroll
-  for (int j = 0; j < G; ++j) {
-    brick_coords(bg, lb + min(j, nbk - 1), x0[j], y0[j], z0[j]);
-    const uint2 se = j < nbk ? brick_se[b + j] : make_uint2(0u, 0u);
-    bs[j] = se.x;
-    be[j] = se.y;
-  }
-  boff[G] = 0u;
-#pragma unroll
-  for (int j = 0; j < G; ++j) boff[G] = max(boff[G], be[j]);
-#pragma unroll
-  for (int j = G - 1; j >= 0; --j) boff[j] = be[j] > bs[j] ? bs[j] : boff[j + 1];
   if (t < G) {
-    sorg[t][0] = x0[t];
-    sorg[t][1] = y0[t];
-    sorg[t][2] = z0[t];
+    int x0, y0, z0;
+    brick_coords(bg, lb + min(t, nbk - 1), x0, y0, z0);
+    sorg[t][0] = x0;
+    sorg[t][1] = y0;
+    sorg[t][2] = z0;
+    sse[t] = t < nbk ? brick_se[b + t] : make_uint2(0u, 0u);
   }
   if (t < 8 * G) {
-    int yb = y0[0], zb = z0[0];
-#pragma unroll
-    for (int j = 1; j < G; ++j)
-      if (t / 8 == j) {
-        yb = y0[j];
-        zb = z0[j];
-      }
-    spy[t / 8][t % 8] = centre(bg.oy, bg.hy, yb + t % 8);
-    if (t % 8 < 4) spz[t / 8][t % 8] = centre(bg.oz, bg.hz, zb + t % 8);
-  }
-  const uint32_t start = boff[0], end = boff[G];
-  // COUNT: voxel slots of rows passing the row test, issued lane-voxel slots, rows in the boxes
-  uint32_t c_eval = 0, c_issued = 0, c_rows = 0;
-  if (!COUNT && (FIT || start != end)) {
-#pragma unroll
-    for (int j = 0; j < G; ++j)
-      if (j < nbk)
-        bwd_stage<BX, FIT>(sd, b + j, x0[j], y0[j], z0[j], t, Iv, Wv, gI, obs, eps, loss_part, sCI + j * BV);
+    const int j = t / 8;
+    int x0, y0, z0;
+    brick_coords(bg, lb + min(j, nbk - 1), x0, y0, z0);
+    spy[j][t % 8] = centre(bg.oy, bg.hy, y0 + t % 8);
+    if (t % 8 < 4) spz[j][t % 8] = centre(bg.oz, bg.hz, z0 + t % 8);
   }
   __syncthreads();
+  if (t == 0) {
+    uint32_t e = 0u;
+    for (int j = 0; j < G; ++j) e = max(e, sse[j].y);
+    sboff[G] = e;
+    for (int j = G - 1; j >= 0; --j) sboff[j] = sse[j].y > sse[j].x ? sse[j].x : sboff[j + 1];
+  }
+  // COUNT: voxel slots of rows passing the row test, issued lane-voxel slots, rows in the boxes
+  uint32_t c_eval = 0, c_issued = 0, c_rows = 0;
+  if (!COUNT) {
+    for (int j = w; j < nbk; j += NW) {
+      if (FIT || sse[j].y > sse[j].x)
+        bwd_stage<BX, FIT>(sd, b + j, sorg[j][0], sorg[j][1], sorg[j][2], l, Iv, Wv, gI, obs, eps, loss_part,
+                           sCI + j * BV);
+    }
+  }
+  __syncthreads();
+  const uint32_t start = sboff[0], end = sboff[G];
   if (start == end) return;
   (void)c_eval;
   (void)c_issued;
   (void)c_rows;
-  int xe[G], ye[G], ze[G];
-#pragma unroll
-  for (int j = 0; j < G; ++j) {
-    xe[j] = min(x0[j] + BX - 1, bg.nx - 1);
-    ye[j] = min(y0[j] + 7, bg.ny - 1);
-    ze[j] = min(z0[j] + 3, bg.nz - 1);
-  }
   for (uint32_t w0 = start; w0 < end; w0 += WIN) {
     const int L = (int)min((uint32_t)WIN, end - w0);
     // order the window's keys (of all bricks of the group) by their number of rows in their brick,
@@ -473,25 +469,16 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
     // result is independent of where it runs, so the order does not change any result)
     if (t < kBwdBuckets) bcount[t] = 0u;
     __syncthreads();
-    for (int j = t; j < L; j += kBwdThreads) {
+    for (int j = t; j < L; j += NT) {
       const uint32_t k = w0 + j;
       const uint32_t gid = list_gid[k];
       int kb = 0;
 #pragma unroll
-      for (int g = 1; g < G; ++g) kb += k >= boff[g] ? 1 : 0;
-      int xb = x0[0], yb = y0[0], zb = z0[0], xeb = xe[0], yeb = ye[0], zeb = ze[0];
-#pragma unroll
-      for (int g = 1; g < G; ++g)
-        if (kb == g) {
-          xb = x0[g];
-          yb = y0[g];
-          zb = z0[g];
-          xeb = xe[g];
-          yeb = ye[g];
-          zeb = ze[g];
-        }
+      for (int g = 1; g < G; ++g) kb += k >= sboff[g] ? 1 : 0;
+      const int xb = sorg[kb][0], yb = sorg[kb][1], zb = sorg[kb][2];
+      const int xeb = min(xb + BX - 1, bg.nx - 1), yeb = min(yb + 7, bg.ny - 1), zeb = min(zb + 3, bg.nz - 1);
       int bk = kBwdBuckets - 1;
-      uint16_t box = (uint16_t)((1u << 12) | (kb << 10));  // empty
+      uint16_t box = (uint16_t)((1u << 13) | (kb << 10));  // empty
       if (gid < T.n_total) {
         int xl, xh, yl, yh, zl, zh;
         key_box(bg, er[gid], cr[gid], cutoff, xb, yb, zb, xeb, yeb, zeb, xl, xh, yl, yh, zl, zh);
@@ -513,9 +500,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       }
     }
     __syncthreads();
-    for (int j = t; j < L; j += kBwdThreads) sorder[atomicAdd(&bcursor[sbucket[j]], 1u)] = (uint16_t)j;
+    for (int j = t; j < L; j += NT) sorder[atomicAdd(&bcursor[sbucket[j]], 1u)] = (uint16_t)j;
     __syncthreads();
-    for (int c0 = w * 64; c0 < L; c0 += kBwdThreads) {
+    for (int r = 0;; ++r) {
+      const int c0 = kBwdWave * (r * NW + ((r & 1) ? NW - 1 - w : w));
+      if (c0 >= L) break;  // uniform per wave
       const int p = c0 + l;
       if (p >= L) continue;
       const int jj = sorder[p];
@@ -527,7 +516,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       const float mx = R.r0.x, A = R.r0.w;
       const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
       const uint32_t box = sbox[jj];
-      const int kb = (box >> 10) & 3;
+      const int kb = (box >> 10) & 7;
       const int bx0 = sorg[kb][0];
       const float2 *sC = sCI + kb * BV;
       const float *sPy = spy[kb], *sPz = spz[kb];
@@ -543,7 +532,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
       const float inv4a = 0.25f * __builtin_amdgcn_rcpf(a);
       const float thr_lo = thr - 1e-5f * (1.f + fabsf(thr));  // the row test's allowance, key part
       const int ny_k = yh - yl + 1;
-      const int nrows = (box >> 12) ? 0 : ny_k * (zh - zl + 1);
+      const int nrows = (box >> 13) ? 0 : ny_k * (zh - zl + 1);
       int iy = yl, iz = zl;
       if (COUNT) c_rows += (uint32_t)nrows;
       for (int r = 0; r < nrows; ++r) {
@@ -627,7 +616,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
 #pragma unroll
       for (int d = 32; d > 0; d >>= 1) v[c] += __shfl_down(v[c], d, 64);
     }
-    if (t == 0) {
+    if (l == 0) {
       atomicAdd(eval_count + 0, v[0]);
       atomicAdd(eval_count + 1, v[1]);
       atomicAdd(eval_count + 2, v[2]);
@@ -635,28 +624,30 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const ScanTable T, float cu
   }
 }
 
-template <int MODE, int G, int WIN>
+template <int MODE, int G, int WIN, int NW>
 static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, const EvalRec *er, const CullRec *cr,
                        const uint32_t *lg, const uint32_t *ls, const uint2 *bo, const DevStatus *st, const float *I,
                        const float *W, const float *gI, const float *obs, float *loss_part, int64_t cap, float4 *part,
                        unsigned long long *evals, hipStream_t s) {
-  const unsigned nb = (unsigned)T.ngroups_total;  // one wave per group of bricks
+  const unsigned nb = (unsigned)T.ngroups_total;  // one workgroup per group of bricks
   switch (bx) {
     case 4:
-      k_bwd<4, MODE, G, WIN><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
-                                                        loss_part, cap, part, evals);
+      k_bwd<4, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+                                                               loss_part, cap, part, evals);
       break;
     case 8:
-      k_bwd<8, MODE, G, WIN><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
-                                                        loss_part, cap, part, evals);
+      k_bwd<8, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+                                                               loss_part, cap, part, evals);
       break;
     default:
-      k_bwd<16, MODE, G, WIN><<<nb, kBwdThreads, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
-                                                         loss_part, cap, part, evals);
+      k_bwd<16, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+                                                                loss_part, cap, part, evals);
       break;
   }
 }
 
+// Group shapes: (G bricks, NW waves) = (8, 4) by default, (2, 1) or (1, 1) by flag; the ordering
+// window is 512 (or 256) keys per wave.
 template <int MODE>
 static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, const void *ws,
                                const WsLayout &L, const float *I, const float *W, const float *gI, const float *obs,
@@ -669,15 +660,23 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float
   const uint2 *bo = (const uint2 *)(b + L.brick_se);
   const DevStatus *st = (const DevStatus *)(b + L.status);
   float4 *part = MODE == kBwdCount ? nullptr : (float4 *)(b + L.partials);
-  const bool one = T.bwd_bricks == 1, w256 = (flags & GS_FLAG_BWD_WINDOW_256) != 0;
-  if (one && w256)
-    bwd_launch<MODE, 1, 256>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
-  else if (one)
-    bwd_launch<MODE, 1, 512>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
-  else if (w256)
-    bwd_launch<MODE, 2, 256>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
-  else
-    bwd_launch<MODE, 2, 512>(T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s);
+  const bool w256 = (flags & GS_FLAG_BWD_WINDOW_256) != 0;
+#define GS_BWD_ARGS T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s
+  switch (T.bwd_bricks) {
+    case 1:
+      if (w256) bwd_launch<MODE, 1, 256, 1>(GS_BWD_ARGS);
+      else bwd_launch<MODE, 1, 512, 1>(GS_BWD_ARGS);
+      break;
+    case 2:
+      if (w256) bwd_launch<MODE, 2, 256, 1>(GS_BWD_ARGS);
+      else bwd_launch<MODE, 2, 512, 1>(GS_BWD_ARGS);
+      break;
+    default:
+      if (w256) bwd_launch<MODE, 8, 1024, 4>(GS_BWD_ARGS);
+      else bwd_launch<MODE, 8, 2048, 4>(GS_BWD_ARGS);
+      break;
+  }
+#undef GS_BWD_ARGS
   return hipGetLastError();
 }
 

@@ -216,6 +216,7 @@ FLAG_FORWARD_ONLY = 1
 # tuning bits (speed only; results are bitwise the same)
 FLAG_BWD_ONE_BRICK = 1 << 4
 FLAG_BWD_WINDOW_256 = 1 << 5
+FLAG_BWD_TWO_BRICKS = 1 << 8
 FLAG_EMIT_STAGE_4K = 1 << 6
 FLAG_EMIT_STAGE_6K = 1 << 7
 
@@ -228,18 +229,19 @@ class Opts:
     cutoff: float = 3.0
     eps: float = 1e-8
     forward_only: bool = False  # workspace without the backward's partial sums
-    # tuning (speed only): bricks per backward wave (2 or 1), the backward's ordering window (512 or
-    # 256 keys), the emit's LDS stage (0: chosen from the key capacity, else 4096 or 6144 keys)
-    bwd_bricks: int = 2
+    # tuning (speed only): bricks per backward workgroup (8: four waves; 2 or 1: one wave), the
+    # backward's ordering window per wave (512 or 256 keys), the emit's LDS stage (0: chosen from the
+    # key capacity, else 4096 or 6144 keys)
+    bwd_bricks: int = 8
     bwd_window: int = 512
     emit_stage: int = 0
 
     @property
     def flags(self) -> int:
-        if self.bwd_bricks not in (1, 2) or self.bwd_window not in (256, 512) or self.emit_stage not in (0, 4096, 6144):
+        if self.bwd_bricks not in (1, 2, 8) or self.bwd_window not in (256, 512) or self.emit_stage not in (0, 4096, 6144):
             raise ValueError(f"unsupported tuning {self.tuning}")
         f = FLAG_FORWARD_ONLY if self.forward_only else 0
-        f |= FLAG_BWD_ONE_BRICK if self.bwd_bricks == 1 else 0
+        f |= {1: FLAG_BWD_ONE_BRICK, 2: FLAG_BWD_TWO_BRICKS, 8: 0}[self.bwd_bricks]
         f |= FLAG_BWD_WINDOW_256 if self.bwd_window == 256 else 0
         f |= {0: 0, 4096: FLAG_EMIT_STAGE_4K, 6144: FLAG_EMIT_STAGE_6K}[self.emit_stage]
         return f

@@ -141,16 +141,18 @@ def test_noalloc_rejects_sets_beyond_the_static_scratch():
 
 
 def test_tuning_flags_are_checked():
-    """The tuning bits are accepted (one emit stage at most); other bits are rejected."""
+    """The tuning bits are accepted (one emit stage and one backward group size at most); other bits
+    are rejected."""
     g = gs.Grid(16, 16, 8)
-    for o in (gs.Opts(bwd_bricks=1), gs.Opts(bwd_window=256), gs.Opts(emit_stage=4096), gs.Opts(emit_stage=6144),
-              gs.Opts(bwd_bricks=1, bwd_window=256, emit_stage=6144, forward_only=True)):
+    for o in (gs.Opts(bwd_bricks=1), gs.Opts(bwd_bricks=2), gs.Opts(bwd_window=256), gs.Opts(emit_stage=4096),
+              gs.Opts(emit_stage=6144), gs.Opts(bwd_bricks=1, bwd_window=256, emit_stage=6144, forward_only=True)):
         assert gs.gs_workspace_size(10, g, o, 10) > 0
     out = ctypes.c_size_t(0)
-    both = gs.gs_opts_t(8, 8, 4, 3.0, 1e-8, gs.FLAG_EMIT_STAGE_4K | gs.FLAG_EMIT_STAGE_6K)
-    assert gs._lib.gs_workspace_size(10, ctypes.byref(g.c()), ctypes.byref(both), 10, ctypes.byref(out)) == \
-        gs.GS_ERR_INVALID_ARG
-    for bit in (1 << 1, 1 << 8, 1 << 31):
+    for both in (gs.FLAG_EMIT_STAGE_4K | gs.FLAG_EMIT_STAGE_6K, gs.FLAG_BWD_ONE_BRICK | gs.FLAG_BWD_TWO_BRICKS):
+        bad = gs.gs_opts_t(8, 8, 4, 3.0, 1e-8, both)
+        assert gs._lib.gs_workspace_size(10, ctypes.byref(g.c()), ctypes.byref(bad), 10, ctypes.byref(out)) == \
+            gs.GS_ERR_INVALID_ARG
+    for bit in (1 << 1, 1 << 9, 1 << 31):
         bad = gs.gs_opts_t(8, 8, 4, 3.0, 1e-8, bit)
         assert gs._lib.gs_workspace_size(10, ctypes.byref(g.c()), ctypes.byref(bad), 10, ctypes.byref(out)) == \
             gs.GS_ERR_INVALID_ARG

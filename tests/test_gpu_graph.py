@@ -87,8 +87,8 @@ def test_autotuner_picks_and_caches(tmp_path):
     widths = {k.split("/")[0] for k in entry["ms"]}
     assert widths == {f"bx{b}" for b in autotune.CANDIDATES}
     assert {k for k in entry["ms"] if k.startswith(f"bx{opts.bx}/")} >= {
-        f"bx{opts.bx}/g{g_}/w512/e0" for g_ in (1, 2)}
-    assert opts.bwd_bricks in (1, 2) and opts.bwd_window in (256, 512) and opts.emit_stage in (0, 4096, 6144)
+        f"bx{opts.bx}/g{g_}/w512/e0" for g_ in (8, 2, 1)}
+    assert opts.bwd_bricks in (8, 2, 1) and opts.bwd_window in (256, 512) and opts.emit_stage in (0, 4096, 6144)
     # a second tuner reads the cache and measures nothing
     t2 = autotune.Tuner(path)
     t2._time = None  # would raise if called
@@ -98,12 +98,12 @@ def test_autotuner_picks_and_caches(tmp_path):
 
 
 def test_tuning_knobs_leave_results_bitwise_equal():
-    """Bricks per backward wave, the backward's ordering window and the emit's stage change speed
+    """Bricks per backward workgroup, the backward's ordering window and the emit's stage change speed
     only: renders, gradients and fit steps are bitwise those of the defaults, at every width."""
     gs = gs_mod()
     data, batch, obs = _batch(4)
-    variants = [dict(), dict(bwd_bricks=1), dict(bwd_window=256), dict(bwd_bricks=1, bwd_window=256),
-                dict(emit_stage=4096), dict(emit_stage=6144)]
+    variants = [dict(), dict(bwd_bricks=2), dict(bwd_bricks=1), dict(bwd_window=256), dict(bwd_bricks=2, bwd_window=256),
+                dict(bwd_bricks=1, bwd_window=256), dict(emit_stage=4096), dict(emit_stage=6144)]
     for bx in (4, 8, 16):
         ref = None
         for kw in variants:
