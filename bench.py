@@ -90,8 +90,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--bx", type=int, default=8, help="brick width along x (4, 8 or 16)")
     ap.add_argument("--bwd-bricks", type=int, default=8,
-                    help="bricks per backward workgroup (8: four waves; 2 or 1: one wave)")
-    ap.add_argument("--bwd-window", type=int, default=512, help="backward ordering window (512 or 256)")
+                    help="bricks per backward workgroup (8: eight waves; 2 or 1: one wave)")
+    ap.add_argument("--bwd-window", type=int, default=512,
+                    help="backward ordering window: 512 (the default size) or 256 (half of it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle fit steps timed for the CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-scan comparison")

@@ -74,11 +74,11 @@ typedef struct {
 /* Tuning bits: they change speed only; every result is bitwise the same with or without them. */
 #define GS_FLAG_BWD_ONE_BRICK (1u << 4)  /* backward: one brick per one-wave workgroup (default: eight
                                             consecutive bricks whose keys are ordered together, per
-                                            four-wave workgroup) */
+                                            eight-wave workgroup) */
 #define GS_FLAG_BWD_TWO_BRICKS (1u << 8) /* backward: two consecutive bricks per one-wave workgroup (not
                                             with GS_FLAG_BWD_ONE_BRICK) */
-#define GS_FLAG_BWD_WINDOW_256 (1u << 5) /* backward: keys ordered in windows of 256 per wave (default
-                                            512) */
+#define GS_FLAG_BWD_WINDOW_256 (1u << 5) /* backward: keys ordered in windows of half the default size
+                                            (default: 2048 keys for eight bricks, 512 for one or two) */
 #define GS_FLAG_EMIT_STAGE_4K (1u << 6)  /* key emission stages up to 4096 keys per workgroup in LDS ... */
 #define GS_FLAG_EMIT_STAGE_6K (1u << 7)  /* ... or up to 6144 (neither: chosen from the key capacity per
                                             workgroup; not both) */

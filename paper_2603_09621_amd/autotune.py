@@ -3,8 +3,8 @@
 The knobs change speed, not the method: the brick width along x (4, 8 or 16 voxels, 8 x 4 in y x z;
 §3.3 uses 8 x 8 x 4), which changes results only by FP32 summation order, and three choices that
 leave every result bitwise the same: the number of consecutive bricks whose keys one backward
-workgroup orders together (8 with four waves, or 2 or 1 with one wave), the size of the backward's
-ordering window (512 or 256 keys per wave) and the emit's LDS stage (4096 or 6144 keys per
+workgroup orders together (8 with eight waves, or 2 or 1 with one wave), the size of the
+backward's ordering window (the default or half of it) and the emit's LDS stage (4096 or 6144 keys per
 workgroup, or chosen from the key capacity).  Which setting is fastest depends on the Gaussians'
 extent relative to the brick, on the key counts and on how long-tailed they are, so the tuner
 measures: it runs a few fit steps (or renders) of the caller's own workload, on copies of the

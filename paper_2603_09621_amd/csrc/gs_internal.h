@@ -54,7 +54,7 @@ struct BrickGrid {
 constexpr int kMaxScans = 16;
 
 // Bricks per backward workgroup (consecutive bricks of a scan whose keys are ordered together): 8
-// (four waves), or 2 or 1 (one wave) with GS_FLAG_BWD_TWO_BRICKS or GS_FLAG_BWD_ONE_BRICK.
+// (eight waves), or 2 or 1 (one wave) with GS_FLAG_BWD_TWO_BRICKS or GS_FLAG_BWD_ONE_BRICK.
 __host__ __device__ inline int bwd_bricks_of(uint32_t flags) {
   return (flags & GS_FLAG_BWD_ONE_BRICK) ? 1 : (flags & GS_FLAG_BWD_TWO_BRICKS) ? 2 : 8;
 }

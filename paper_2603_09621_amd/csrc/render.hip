@@ -14,7 +14,7 @@
 // (numerator S, denominator W).  The four slots' partial sums of a voxel are added in a fixed order
 // at the end, so the result is bitwise deterministic.
 //
-// Backward: one workgroup per group of G consecutive bricks (eight bricks and four waves, or two or
+// Backward: one workgroup per group of G consecutive bricks (eight bricks and eight waves, or two or
 // one brick and one wave), one Gaussian (key) per lane.  The bricks' per-voxel factors
 // c_p = dL/dI(p) / (W(p) + eps) and I(p) are staged in LDS; the keys of the group's bricks are ordered
 // together by their number of rows in their brick so that the lanes of a wave run similar numbers of
@@ -386,8 +386,11 @@ constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 // workgroup shape).  The keys of all G bricks are ordered together, WIN at a time, by their number of
 // rows; the waves take the ordered keys 64 at a time, in a snake order over the waves (batch r NW + w,
 // then (r + 1) NW + NW - 1 - w, ...) so that the heaviest and the lightest batches are shared out.
+// (eight-wave groups of bricks up to 8 wide: registers capped for 8 waves per SIMD, i.e. four
+// workgroups per CU, so that the memory-bound phases of some workgroups (staging, ordering, the
+// partial sums' stores) overlap the VALU-bound row loops of others)
 template <int BX, int MODE, int G, int WIN, int NW>
-__global__ __launch_bounds__(kBwdWave *NW) void k_bwd(const ScanTable T, float cutoff, float eps,
+__global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && BX <= 8 ? 8 : 1))) void k_bwd(const ScanTable T, float cutoff, float eps,
                                                       const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
                                                       const uint32_t *__restrict__ list_gid,
                                                       const uint32_t *__restrict__ list_slot,
@@ -646,8 +649,9 @@ static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, cons
   }
 }
 
-// Group shapes: (G bricks, NW waves) = (8, 4) by default, (2, 1) or (1, 1) by flag; the ordering
-// window is 512 (or 256) keys per wave.
+// Group shapes: (G bricks, NW waves) = (8, 8) by default (a wave stages one brick), (2, 1) or (1, 1)
+// by flag.  The ordering window holds 2048 keys for the eight-brick group and 512 for the others, or
+// half as many with GS_FLAG_BWD_WINDOW_256.
 template <int MODE>
 static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, const void *ws,
                                const WsLayout &L, const float *I, const float *W, const float *gI, const float *obs,
@@ -672,8 +676,8 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float
       else bwd_launch<MODE, 2, 512, 1>(GS_BWD_ARGS);
       break;
     default:
-      if (w256) bwd_launch<MODE, 8, 1024, 4>(GS_BWD_ARGS);
-      else bwd_launch<MODE, 8, 2048, 4>(GS_BWD_ARGS);
+      if (w256) bwd_launch<MODE, 8, 1024, 8>(GS_BWD_ARGS);
+      else bwd_launch<MODE, 8, 2048, 8>(GS_BWD_ARGS);
       break;
   }
 #undef GS_BWD_ARGS

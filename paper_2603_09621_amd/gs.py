@@ -229,9 +229,10 @@ class Opts:
     cutoff: float = 3.0
     eps: float = 1e-8
     forward_only: bool = False  # workspace without the backward's partial sums
-    # tuning (speed only): bricks per backward workgroup (8: four waves; 2 or 1: one wave), the
-    # backward's ordering window per wave (512 or 256 keys), the emit's LDS stage (0: chosen from the
-    # key capacity, else 4096 or 6144 keys)
+    # tuning (speed only): bricks per backward workgroup (8: eight waves; 2 or 1: one wave), the
+    # backward's ordering window (512: the default size, 2048 keys for eight bricks and 512 for one or
+    # two; 256: half of it), the emit's LDS stage (0: chosen from the key capacity, else 4096 or 6144
+    # keys)
     bwd_bricks: int = 8
     bwd_window: int = 512
     emit_stage: int = 0
