@@ -301,7 +301,9 @@ hipError_t launch_count_pairs(const ScanTable &T, int bx, float cutoff, const vo
 // with c = dL/dI / (W + eps), k = c (A - I) w = dL/dw * w.
 
 constexpr int kBwdWave = 64;  // lanes per wave; a backward workgroup has NW waves
-constexpr int kBwdBuckets = 34;  // rows per key in its brick: 32 .. 0 (bucket 0 = 32 rows), then empty
+// ordering buckets: full-row keys by rows in the brick (32 .. 0, bucket 0 = 32 rows), half-row keys
+// likewise (buckets 33 ..), then empty boxes
+constexpr int kBwdBuckets = 67;
 
 // Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
 __device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
@@ -377,6 +379,95 @@ __device__ __forceinline__ void bwd_stage(const ScanDesc &sd, int64_t b, int x0,
   }
 }
 
+// The 11 brick-local sums of one key (see the partial record above), with the x moments kept as
+// moments of ck, the voxel's x offset from the centre of the evaluated row segment.
+struct KeySums {
+  float sA, sk, sc, sky, skz, scc, myy, mzz, scy, scz, myz;
+};
+
+// The rows of one key's box in its brick (nrows rows, y fastest over [yl, yh] x [zl, zh]), each
+// evaluated over W voxels starting at the global voxel index xw: the whole brick row (W = BX), or a
+// window of BX/2 voxels that holds the key's x-range in the brick (the voxels left out lie outside
+// its box, so they hold no pair).  Per row, the quadratic's maximum along x (at dx* = -b / 2a) is
+// compared with the cutoff with a rounding allowance, so a row holding a pair with d^2 <= 9 is never
+// skipped; a live row's voxels are evaluated unrolled with the forward's per-pair predicate into
+// sum c w, sum k, sum k ck, sum k ck^2, which are folded with the row's (dy, dz).  ck = kk - (W-1)/2
+// is a compile-time constant, so dx = dxc + ck h with one dxc per key (returned): the x moments follow
+// from the ck moments (sum k dx = dxc sum k + h sum k ck, ...), a multiply per voxel less than
+// accumulating k dx and k dx^2.  COUNT: only counts the evaluated and issued voxel slots.
+template <int W, bool COUNT>
+__device__ __forceinline__ float key_rows(const BrickGrid &bg, const EvalRec &R, int xw, const float2 *sC, int RP,
+                                          const float *sPy, const float *sPz, int yl, int yh, int zl, int nrows,
+                                          KeySums &s, uint32_t &c_eval, uint32_t &c_issued) {
+  const float mx = R.r0.x, A = R.r0.w;
+  const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
+  float px[W];
+#pragma unroll
+  for (int kk = 0; kk < W; ++kk) px[kk] = centre(bg.ox, bg.hx, xw + kk);
+  s = KeySums{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const float inv4a = 0.25f * __builtin_amdgcn_rcpf(a);
+  const float thr_lo = thr - 1e-5f * (1.f + fabsf(thr));  // the row test's allowance, key part
+  int iy = yl, iz = zl;
+  for (int r = 0; r < nrows; ++r) {
+    const float py = sPy[iy], pz = sPz[iz];
+    float dy, dz, bq, cq;
+    row_coeffs(R, py, pz, dy, dz, bq, cq);
+    // the row's maximum of q (at dx* = -b / (2a)) is c - b^2 / (4a); rows whose maximum is clearly
+    // below the cutoff hold no pair
+    const float qmax = fmaf(-(bq * bq), inv4a, cq);
+    const bool live = qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo);
+    if (COUNT) {
+      c_eval += live ? (uint32_t)W : 0u;
+      c_issued += __ballot(live) != 0ull && lane_id() == __builtin_amdgcn_readfirstlane(lane_id())
+                      ? (uint32_t)(64 * W)
+                      : 0u;
+    } else if (live) {
+      const int rb = (iz * 8 + iy) * RP;
+      float tA, m0, m1, m2;
+#pragma unroll
+      for (int kk = 0; kk < W; ++kk) {
+        constexpr float half = 0.5f * (W - 1);
+        const float ck = (float)kk - half;
+        const float dx = px[kk] - mx;
+        const float qv = row_q(a, bq, cq, dx);
+        float wt = fast_exp2(qv);
+        wt = qv >= thr ? wt : 0.f;
+        const float2 ci = sC[rb + kk];
+        const float tt = ci.x * wt;
+        const float kap = (A - ci.y) * tt;
+        if (kk == 0) {  // the row's sums start from the first voxel's terms
+          tA = tt;
+          m0 = kap;
+          m1 = ck * kap;
+          m2 = (ck * ck) * kap;
+        } else {
+          tA += tt;
+          m0 += kap;
+          m1 = fmaf(ck, kap, m1);
+          m2 = fmaf(ck * ck, kap, m2);
+        }
+      }
+      s.sA += tA;
+      s.sk += m0;
+      s.sc += m1;
+      s.sky = fmaf(m0, dy, s.sky);
+      s.skz = fmaf(m0, dz, s.skz);
+      s.scc += m2;
+      s.scy = fmaf(m1, dy, s.scy);
+      s.scz = fmaf(m1, dz, s.scz);
+      const float m0dy = m0 * dy;
+      s.myy = fmaf(m0dy, dy, s.myy);
+      s.myz = fmaf(m0dy, dz, s.myz);
+      s.mzz = fmaf(m0 * dz, dz, s.mzz);
+    }
+    if (++iy > yh) {
+      iy = yl;
+      ++iz;
+    }
+  }
+  return fmaf(0.5f * (W - 1), bg.hx, px[0] - mx);  // dxc: the segment centre's x offset
+}
+
 // Backward modes: plain (dL/dI given), fit (loss fused into the staging), count (the ordering and
 // the row tests only, counting evaluated and issued voxel slots; nothing is written but the counts).
 constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
@@ -411,9 +502,9 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
   __shared__ float2 sCI[G * BV];
   __shared__ uint16_t sorder[WIN];
   __shared__ uint8_t sbucket[WIN];
-  // key's row box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the group
-  // (bits 10-12), empty (bit 13)
-  __shared__ uint16_t sbox[WIN];
+  // key's box in its brick: yl, yh (3 bits each), zl, zh (2 bits each), brick of the group (bits
+  // 10-12), xl, xh (4 bits each, bits 13-20), empty (bit 21)
+  __shared__ uint32_t sbox[WIN];
   __shared__ uint32_t bcount[kBwdBuckets], bcursor[kBwdBuckets];
   __shared__ int sorg[G][3];  // brick origins (voxel indices)
   __shared__ float spy[G][8], spz[G][4];  // voxel-centre coordinates of the bricks' rows and slices
@@ -470,7 +561,7 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
     // order the window's keys (of all bricks of the group) by their number of rows in their brick,
     // most first, so that the lanes of a wave run similar numbers of row iterations (each key's
     // result is independent of where it runs, so the order does not change any result)
-    if (t < kBwdBuckets) bcount[t] = 0u;
+    for (int k = t; k < kBwdBuckets; k += NT) bcount[k] = 0u;
     __syncthreads();
     for (int j = t; j < L; j += NT) {
       const uint32_t k = w0 + j;
@@ -481,13 +572,16 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
       const int xb = sorg[kb][0], yb = sorg[kb][1], zb = sorg[kb][2];
       const int xeb = min(xb + BX - 1, bg.nx - 1), yeb = min(yb + 7, bg.ny - 1), zeb = min(zb + 3, bg.nz - 1);
       int bk = kBwdBuckets - 1;
-      uint16_t box = (uint16_t)((1u << 13) | (kb << 10));  // empty
+      uint32_t box = (1u << 21) | ((uint32_t)kb << 10);  // empty
       if (gid < T.n_total) {
         int xl, xh, yl, yh, zl, zh;
         key_box(bg, er[gid], cr[gid], cutoff, xb, yb, zb, xeb, yeb, zeb, xl, xh, yl, yh, zl, zh);
         if (xl <= xh && yl <= yh && zl <= zh) {
-          bk = 32 - (yh - yl + 1) * (zh - zl + 1);
-          box = (uint16_t)((yl - yb) | ((yh - yb) << 3) | ((zl - zb) << 6) | ((zh - zb) << 8) | (kb << 10));
+          // full-row keys first, then the half-row keys (each class by rows, most first)
+          const bool narrow = BX > 4 && xh - xl < BX / 2;
+          bk = (narrow ? 33 : 0) + 32 - (yh - yl + 1) * (zh - zl + 1);
+          box = (uint32_t)((yl - yb) | ((yh - yb) << 3) | ((zl - zb) << 6) | ((zh - zb) << 8) | (kb << 10) |
+                           ((xl - xb) << 13) | ((xh - xb) << 17));
         }
       }
       sbucket[j] = (uint8_t)bk;
@@ -516,8 +610,6 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
       const uint32_t slot = list_slot[k];
       if (gid >= T.n_total || (int64_t)slot >= cap) continue;
       const EvalRec R = er[gid];
-      const float mx = R.r0.x, A = R.r0.w;
-      const float a = R.r1.x, thr = R.r1.w;  // Q_xx < 0
       const uint32_t box = sbox[jj];
       const int kb = (box >> 10) & 7;
       const int bx0 = sorg[kb][0];
@@ -525,90 +617,31 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
       const float *sPy = spy[kb], *sPz = spz[kb];
       // the box in brick-local rows and slices
       const int yl = box & 7, yh = (box >> 3) & 7, zl = (box >> 6) & 3, zh = (box >> 8) & 3;
-      float px[BX];
-#pragma unroll
-      for (int kk = 0; kk < BX; ++kk) px[kk] = centre(bg.ox, bg.hx, bx0 + kk);
-      // sc, scc, scy, scz: sums of k ck, k ck^2, k ck dy, k ck dz (ck: the voxel's x offset from the
-      // brick row's centre in voxels, see below); the other sums are those of the partial record
-      float sA = 0.f, sk = 0.f, sc = 0.f, sky = 0.f, skz = 0.f;
-      float scc = 0.f, myy = 0.f, mzz = 0.f, scy = 0.f, scz = 0.f, myz = 0.f;
-      const float inv4a = 0.25f * __builtin_amdgcn_rcpf(a);
-      const float thr_lo = thr - 1e-5f * (1.f + fabsf(thr));  // the row test's allowance, key part
-      const int ny_k = yh - yl + 1;
-      const int nrows = (box >> 13) ? 0 : ny_k * (zh - zl + 1);
-      int iy = yl, iz = zl;
+      // keys whose x-range in the brick fits half a brick row evaluate that half only (one of two
+      // code paths per key, whatever the batch: a key's sums do not depend on where it runs)
+      const int xl = (box >> 13) & 15, xh = (box >> 17) & 15;
+      const bool narrow = BX > 4 && xh - xl < BX / 2;
+      const int nrows = (box >> 21) ? 0 : (yh - yl + 1) * (zh - zl + 1);
       if (COUNT) c_rows += (uint32_t)nrows;
-      for (int r = 0; r < nrows; ++r) {
-        const float py = sPy[iy], pz = sPz[iz];
-        float dy, dz, bq, cq;
-        row_coeffs(R, py, pz, dy, dz, bq, cq);
-        // the row's maximum of q (at dx* = -b / (2a)) is c - b^2 / (4a); rows whose maximum is
-        // clearly below the cutoff hold no pair
-        const float qmax = fmaf(-(bq * bq), inv4a, cq);
-        const bool live = qmax >= fmaf(-1e-5f, fabsf(cq), thr_lo);
-        if (COUNT) {
-          c_eval += live ? (uint32_t)BX : 0u;
-          c_issued += __ballot(live) != 0ull && lane_id() == __builtin_amdgcn_readfirstlane(lane_id())
-                          ? (uint32_t)(64 * BX)
-                          : 0u;
-        } else if (live) {
-          const int rb = (iz * 8 + iy) * RP;
-          // dx of voxel kk is dxc + ck h with ck = kk - (BX - 1) / 2 (offset from the row's centre):
-          // the row sums of k dx and k dx^2 follow from m1 = sum ck k and m2 = sum ck^2 k
-          float tA, m0, m1, m2;
-#pragma unroll
-          for (int kk = 0; kk < BX; ++kk) {
-            constexpr float half = 0.5f * (BX - 1);
-            const float ck = (float)kk - half;
-            const float dx = px[kk] - mx;
-            const float qv = row_q(a, bq, cq, dx);
-            float wt = fast_exp2(qv);
-            wt = qv >= thr ? wt : 0.f;
-            const float2 ci = sC[rb + kk];
-            const float tt = ci.x * wt;
-            const float kap = (A - ci.y) * tt;
-            if (kk == 0) {  // the row's sums start from the first voxel's terms
-              tA = tt;
-              m0 = kap;
-              m1 = ck * kap;
-              m2 = (ck * ck) * kap;
-            } else {
-              tA += tt;
-              m0 += kap;
-              m1 = fmaf(ck, kap, m1);
-              m2 = fmaf(ck * ck, kap, m2);
-            }
-          }
-          sA += tA;
-          sk += m0;
-          sc += m1;
-          sky = fmaf(m0, dy, sky);
-          skz = fmaf(m0, dz, skz);
-          scc += m2;
-          scy = fmaf(m1, dy, scy);
-          scz = fmaf(m1, dz, scz);
-          const float m0dy = m0 * dy;
-          myy = fmaf(m0dy, dy, myy);
-          myz = fmaf(m0dy, dz, myz);
-          mzz = fmaf(m0 * dz, dz, mzz);
-        }
-        if (++iy > yh) {
-          iy = yl;
-          ++iz;
-        }
-      }
+      KeySums s;
+      float dxc;
+      if (narrow)
+        dxc = key_rows<BX / 2, COUNT>(bg, R, bx0 + min(xl, BX / 2), sC + min(xl, BX / 2), RP, sPy, sPz, yl, yh, zl,
+                                      nrows, s, c_eval, c_issued);
+      else
+        dxc = key_rows<BX, COUNT>(bg, R, bx0, sC, RP, sPy, sPz, yl, yh, zl, nrows, s, c_eval, c_issued);
       if (COUNT) continue;
-      // back from row-centre offsets to dx: sum k dx = dxc sum k + h sum ck k, sum k dx^2 =
+      // back from segment-centre offsets to dx: sum k dx = dxc sum k + h sum ck k, sum k dx^2 =
       // dxc^2 sum k + 2 dxc h sum ck k + h^2 sum ck^2 k, sum k dx d = dxc sum k d + h sum ck k d
-      const float hx = bg.hx, dxc = fmaf(0.5f * (BX - 1), hx, px[0] - mx);
-      const float skx = fmaf(hx, sc, dxc * sk);
-      const float mxx = fmaf(dxc, fmaf(dxc, sk, 2.f * hx * sc), (hx * hx) * scc);
-      const float mxy = fmaf(hx, scy, dxc * sky);
-      const float mxz = fmaf(hx, scz, dxc * skz);
+      const float hx = bg.hx;
+      const float skx = fmaf(hx, s.sc, dxc * s.sk);
+      const float mxx = fmaf(dxc, fmaf(dxc, s.sk, 2.f * hx * s.sc), (hx * hx) * s.scc);
+      const float mxy = fmaf(hx, s.scy, dxc * s.sky);
+      const float mxz = fmaf(hx, s.scz, dxc * s.skz);
       float4 *o = part + (int64_t)slot * 3;
-      o[0] = make_float4(sA, sk, skx, sky);
-      o[1] = make_float4(skz, mxx, myy, mzz);
-      o[2] = make_float4(mxy, mxz, myz, 0.f);
+      o[0] = make_float4(s.sA, s.sk, skx, s.sky);
+      o[1] = make_float4(s.skz, mxx, s.myy, s.mzz);
+      o[2] = make_float4(mxy, mxz, s.myz, 0.f);
     }
     __syncthreads();
   }
