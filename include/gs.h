@@ -61,7 +61,8 @@ typedef struct {
   const float *relax;     /* [n]    relaxation factor r_i > 0, or NULL meaning r_i = 1 */
 } gs_gaussians_t;
 
-/* Output grid (any shape and resolution: rendering at an arbitrary target shape, §4.2). */
+/* Output grid (any shape and resolution: rendering at an arbitrary target shape, §4.2).  Each
+ * dimension is at most 65535 voxels (GS_ERR_UNSUPPORTED beyond). */
 typedef struct {
   int32_t nx, ny, nz;
   float origin[3];  /* centre of voxel (0,0,0) */

@@ -128,6 +128,7 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
   L.cullrec = take(sizeof(CullRec) * (size_t)n);
   L.off = take(sizeof(uint32_t) * (size_t)(n + 1));
   L.runs = take(sizeof(uint32_t) * kRuns * (size_t)n);
+  L.gbox = take(sizeof(uint32_t) * 4 * (size_t)n);
   L.key_brick = take(sizeof(uint32_t) * (size_t)cap);
   L.key_gid = take(sizeof(uint32_t) * (size_t)cap);
   L.keys_alt = take(sizeof(uint32_t) * (size_t)cap);
@@ -155,6 +156,8 @@ static int check_grid(const gs_grid_t *grid) {
     return fail(GS_ERR_INVALID_ARG, "grid dims must be positive (got %d x %d x %d)", grid->nx, grid->ny, grid->nz);
   if ((int64_t)grid->nx * grid->ny * grid->nz > ((int64_t)1 << 40))
     return fail(GS_ERR_INVALID_ARG, "grid too large");
+  if (grid->nx > kMaxGridDim || grid->ny > kMaxGridDim || grid->nz > kMaxGridDim)
+    return fail(GS_ERR_UNSUPPORTED, "grid dims above %d per axis are not supported", kMaxGridDim);
   for (int k = 0; k < 3; ++k) {
     if (!(grid->spacing[k] > 0.f) || !std::isfinite(grid->spacing[k]) || !std::isfinite(grid->origin[k]))
       return fail(GS_ERR_INVALID_ARG, "grid spacing must be positive and finite, origin finite");

@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_eu(6)
                                                              EvalRec *__restrict__ er, CullRec *__restrict__ cr,
                                                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ runs,
 uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
-    uint32_t *__restrict__ brick_se, int64_t se_len) {
+    uint32_t *__restrict__ brick_se, int64_t se_len, uint4 *__restrict__ gbox) {
   __shared__ uint64_t wsum[kPrepThreads / 64];
   __shared__ int sbad;
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
@@ -284,7 +284,10 @@ uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
     int nr = 0;
     bool redo = false;
     GaussBox B;
+    uint4 vb = make_uint4(1u, 1u, 1u, 0u);  // empty (xl = 1 > xh = 0)
     if (gauss_box(sd.bg, e, r, cutoff, B)) {
+      vb = make_uint4((uint32_t)B.xl | ((uint32_t)B.xh << 16), (uint32_t)B.yl | ((uint32_t)B.yh << 16),
+                      (uint32_t)B.zl | ((uint32_t)B.zh << 16), 0u);
       uint32_t nky;
       wide_rows = box_rows(sd.bg, B, nky);
       wide = wide_rows > kWaveRows;
@@ -300,6 +303,7 @@ uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
           }
         });
     }
+    gbox[i] = vb;
     if (wide) rr[0] = kRunWave;
     else if (redo) rr[0] = kRunRedo;
     uint4 *rc = reinterpret_cast<uint4 *>(runs + (int64_t)kRuns * i);
@@ -345,7 +349,7 @@ hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const W
                                                (uint32_t *)(b + L.off), (uint32_t *)(b + L.runs),
                                                (uint64_t *)(b + L.scan_tmp),
                                                (uint32_t *)(b + L.hist), (int64_t)kRadix * L.sort_blocks,
-                                               (uint32_t *)(b + L.brick_se), 2 * L.nbricks);
+                                               (uint32_t *)(b + L.brick_se), 2 * L.nbricks, (uint4 *)(b + L.gbox));
   prof_end(s, "prep_count");
   return hipGetLastError();
 }

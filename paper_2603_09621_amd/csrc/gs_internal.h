@@ -110,10 +110,15 @@ constexpr int kRadix = 1 << kRadixBits;
 // or r <= 0).
 constexpr int kPrepThreads = 256;
 constexpr int kRuns = 8;  // brick runs cached per Gaussian between the count and the emit pass
+// Voxel box of a Gaussian (its padded 3-sigma extent in voxel indices), written by the prep kernel for
+// the backward's ordering pass: uint4 (xl | xh << 16, yl | yh << 16, zl | zh << 16, 0), empty
+// (xl > xh) for a Gaussian without keys.  16-bit indices: grid dimensions are at most kMaxGridDim.
+constexpr int kMaxGridDim = 65535;
 static_assert(kRuns % 4 == 0, "the run cache is read and written as 16-byte words");
 constexpr uint64_t kBadBlock = 1ull << 63;
 
 // Workspace layout, all offsets in bytes from the workspace base, 256-B aligned.
+//   gbox: uint4 [n] voxel boxes (see kMaxGridDim).
 //   off: uint32 [n + 1]: key counts per Gaussian, after the emit the first key slot of each
 //        Gaussian (keys are numbered Gaussian-major); off[n] = the key count.
 //   scan_tmp: per-block key totals of the count scan (uint64), later the radix digit totals.
@@ -126,7 +131,7 @@ struct WsLayout {
   int64_t n = 0, cap = 0, nbricks = 0;
   int sort_blocks = 0;  // tiles per radix pass (covers cap keys)
   int sort_passes = 0;  // ceil(bits(nbricks) / 8), at least 1
-  size_t status = 0, evalrec = 0, cullrec = 0, off = 0, runs = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
+  size_t status = 0, evalrec = 0, cullrec = 0, off = 0, runs = 0, gbox = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
          vals_b = 0, list_gid = 0, list_slot = 0, brick_se = 0, hist = 0, scan_tmp = 0, partials = 0, total = 0;
   size_t sorted_keys = 0;  // where the brick ids end up after the last pass
 };

@@ -305,25 +305,6 @@ constexpr int kBwdWave = 64;  // lanes per wave; a backward workgroup has NW wav
 // likewise (buckets 33 ..), then empty boxes
 constexpr int kBwdBuckets = 67;
 
-// Voxel box of a Gaussian's padded 3-sigma extent, clipped to the brick [x0..xe] x [y0..ye] x [z0..ze].
-__device__ __forceinline__ void key_box(const BrickGrid &bg, const EvalRec &R, const CullRec &C, float cutoff, int x0,
-                                        int y0, int z0, int xe, int ye, int ze, int &xl, int &xh, int &yl, int &yh,
-                                        int &zl, int &zh) {
-  const float mx = R.r0.x, my = R.r0.y, mz = R.r0.z;
-  const float ex = cutoff * __builtin_amdgcn_sqrtf(C.c0.x), ey = cutoff * __builtin_amdgcn_sqrtf(C.c0.y),
-              ez = cutoff * __builtin_amdgcn_sqrtf(C.c0.z);
-  const float tx = extent_tol(mx, ex, bg.hx), ty = extent_tol(my, ey, bg.hy), tz = extent_tol(mz, ez, bg.hz);
-  world_to_index(mx - ex - tx, mx + ex + tx, bg.ox, bg.ihx, bg.nx, xl, xh);
-  world_to_index(my - ey - ty, my + ey + ty, bg.oy, bg.ihy, bg.ny, yl, yh);
-  world_to_index(mz - ez - tz, mz + ez + tz, bg.oz, bg.ihz, bg.nz, zl, zh);
-  xl = max(xl, x0);
-  xh = min(xh, xe);
-  yl = max(yl, y0);
-  yh = min(yh, ye);
-  zl = max(zl, z0);
-  zh = min(zh, ze);
-}
-
 // FIT: the fit's loss is fused into the staging.  The brick's 4 z slices are one group of the
 // z-mean (LR slice z0 / 4): per (x, y) column, LR = (((I0 + I1) + I2) + I3) * 1/4 (the loss kernel's
 // order), dL/dI = sign(LR - obs) * gscale on the column's 4 voxels, and the brick's sum of |LR - obs|
@@ -482,7 +463,7 @@ constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 // partial sums' stores) overlap the VALU-bound row loops of others)
 template <int BX, int MODE, int G, int WIN, int NW>
 __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && BX <= 8 ? 8 : 1))) void k_bwd(const ScanTable T, float cutoff, float eps,
-                                                      const EvalRec *__restrict__ er, const CullRec *__restrict__ cr,
+                                                      const EvalRec *__restrict__ er, const uint4 *__restrict__ gbox,
                                                       const uint32_t *__restrict__ list_gid,
                                                       const uint32_t *__restrict__ list_slot,
                                                       const uint2 *__restrict__ brick_se, const DevStatus *st,
@@ -574,8 +555,11 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
       int bk = kBwdBuckets - 1;
       uint32_t box = (1u << 21) | ((uint32_t)kb << 10);  // empty
       if (gid < T.n_total) {
-        int xl, xh, yl, yh, zl, zh;
-        key_box(bg, er[gid], cr[gid], cutoff, xb, yb, zb, xeb, yeb, zeb, xl, xh, yl, yh, zl, zh);
+        // the Gaussian's voxel box (its padded 3-sigma extent, from the prep) clipped to the brick
+        const uint4 vb = gbox[gid];
+        const int xl = max((int)(vb.x & 0xFFFFu), xb), xh = min((int)(vb.x >> 16), xeb);
+        const int yl = max((int)(vb.y & 0xFFFFu), yb), yh = min((int)(vb.y >> 16), yeb);
+        const int zl = max((int)(vb.z & 0xFFFFu), zb), zh = min((int)(vb.z >> 16), zeb);
         if (xl <= xh && yl <= yh && zl <= zh) {
           // full-row keys first, then the half-row keys (each class by rows, most first)
           const bool narrow = BX > 4 && xh - xl < BX / 2;
@@ -661,22 +645,22 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
 }
 
 template <int MODE, int G, int WIN, int NW>
-static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, const EvalRec *er, const CullRec *cr,
+static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, const EvalRec *er, const uint4 *gb,
                        const uint32_t *lg, const uint32_t *ls, const uint2 *bo, const DevStatus *st, const float *I,
                        const float *W, const float *gI, const float *obs, float *loss_part, int64_t cap, float4 *part,
                        unsigned long long *evals, hipStream_t s) {
   const unsigned nb = (unsigned)T.ngroups_total;  // one workgroup per group of bricks
   switch (bx) {
     case 4:
-      k_bwd<4, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+      k_bwd<4, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
                                                                loss_part, cap, part, evals);
       break;
     case 8:
-      k_bwd<8, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+      k_bwd<8, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
                                                                loss_part, cap, part, evals);
       break;
     default:
-      k_bwd<16, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs,
+      k_bwd<16, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
                                                                 loss_part, cap, part, evals);
       break;
   }
@@ -692,13 +676,13 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float
   char *b = (char *)ws;
   if (T.ngroups_total == 0) return hipSuccess;
   const EvalRec *er = (const EvalRec *)(b + L.evalrec);
-  const CullRec *cr = (const CullRec *)(b + L.cullrec);
+  const uint4 *gb = (const uint4 *)(b + L.gbox);
   const uint32_t *lg = (const uint32_t *)(b + L.list_gid), *ls = (const uint32_t *)(b + L.list_slot);
   const uint2 *bo = (const uint2 *)(b + L.brick_se);
   const DevStatus *st = (const DevStatus *)(b + L.status);
   float4 *part = MODE == kBwdCount ? nullptr : (float4 *)(b + L.partials);
   const bool w256 = (flags & GS_FLAG_BWD_WINDOW_256) != 0;
-#define GS_BWD_ARGS T, bx, cutoff, eps, er, cr, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s
+#define GS_BWD_ARGS T, bx, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s
   switch (T.bwd_bricks) {
     case 1:
       if (w256) bwd_launch<MODE, 1, 256, 1>(GS_BWD_ARGS);

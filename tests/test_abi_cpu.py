@@ -43,6 +43,11 @@ def test_invalid_arguments_are_rejected():
         gs.gs_workspace_size(10, g, gs.Opts(bx=5), 10)
     assert e.value.code == gs.GS_ERR_UNSUPPORTED
     assert "not supported" in gs.gs_last_error()
+    # voxel boxes are kept in 16-bit indices: at most 65535 voxels per axis
+    assert gs.gs_workspace_size(10, gs.Grid(65535, 4, 4), gs.Opts(), 10) > 0
+    with pytest.raises(gs.GSError) as e:
+        gs.gs_workspace_size(10, gs.Grid(4, 65536, 4), gs.Opts(), 10)
+    assert e.value.code == gs.GS_ERR_UNSUPPORTED
 
 
 def test_workspace_grows_with_n_and_capacity():
@@ -127,7 +132,7 @@ def test_noalloc_rejects_sets_beyond_the_static_scratch():
     """The no-allocation render refuses, before touching any device, a set whose per-Gaussian
     workspace alone exceeds the static scratch (the pointers are never dereferenced)."""
     fake = ctypes.c_void_p(256)
-    n = 2_000_000  # 2M x (48 + 32 + 4 + 32) B of records, offsets and run cache > 64 MiB
+    n = 2_000_000  # 2M x (48 + 32 + 4 + 32 + 16) B of records, offsets, run cache and boxes > 64 MiB
     g = gs.gs_gaussians_t(n, fake, fake, fake, fake, None)
     grid = gs.Grid(64, 64, 32).c()
     opts = gs.Opts().c()
