@@ -143,7 +143,6 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
   const bool rowin = iy < bg.ny && iz < bg.nz;
   const uint2 se = brick_se[b];
   const uint32_t start = se.x, end = se.y;
-  const uint64_t lt = lanemask_lt();
 
   if (t == 0) {
     srec[NT].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -177,7 +176,10 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
       for (int g = 0; g < 4; ++g) {
         const bool has = (qm >> g) & 1u;
         const uint64_t bal = __ballot(has);
-        if (has) wlist[w][g][n[g] + __popcll(bal & lt)] = (uint16_t)(j * sizeof(EvalRec));
+        // the lane's rank among the wave's lanes that have the cell (lanes below it with the bit set)
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (has) wlist[w][g][n[g] + rank] = (uint16_t)(j * sizeof(EvalRec));
         n[g] += __popcll(bal);
       }
     }
