@@ -464,7 +464,7 @@ constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 // workgroups per CU, so that the memory-bound phases of some workgroups (staging, ordering, the
 // partial sums' stores) overlap the VALU-bound row loops of others)
 template <int BX, int MODE, int G, int WIN, int NW>
-__global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && BX <= 8 ? 8 : 1))) void k_bwd(const ScanTable T, float cutoff, float eps,
+__global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && BX <= 8 ? 8 : 1))) void k_bwd(const ScanTable T, float eps,
                                                       const EvalRec *__restrict__ er, const uint4 *__restrict__ gbox,
                                                       const uint32_t *__restrict__ list_gid,
                                                       const uint32_t *__restrict__ list_slot,
@@ -647,22 +647,22 @@ __global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW
 }
 
 template <int MODE, int G, int WIN, int NW>
-static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, const EvalRec *er, const uint4 *gb,
+static void bwd_launch(const ScanTable &T, int bx, float eps, const EvalRec *er, const uint4 *gb,
                        const uint32_t *lg, const uint32_t *ls, const uint2 *bo, const DevStatus *st, const float *I,
                        const float *W, const float *gI, const float *obs, float *loss_part, int64_t cap, float4 *part,
                        unsigned long long *evals, hipStream_t s) {
   const unsigned nb = (unsigned)T.ngroups_total;  // one workgroup per group of bricks
   switch (bx) {
     case 4:
-      k_bwd<4, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
+      k_bwd<4, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
                                                                loss_part, cap, part, evals);
       break;
     case 8:
-      k_bwd<8, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
+      k_bwd<8, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
                                                                loss_part, cap, part, evals);
       break;
     default:
-      k_bwd<16, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
+      k_bwd<16, MODE, G, WIN, NW><<<nb, kBwdWave * NW, 0, s>>>(T, eps, er, gb, lg, ls, bo, st, I, W, gI, obs,
                                                                 loss_part, cap, part, evals);
       break;
   }
@@ -672,7 +672,7 @@ static void bwd_launch(const ScanTable &T, int bx, float cutoff, float eps, cons
 // by flag.  The ordering window holds 2048 keys for the eight-brick group and 512 for the others, or
 // half as many with GS_FLAG_BWD_WINDOW_256.
 template <int MODE>
-static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, const void *ws,
+static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float eps, const void *ws,
                                const WsLayout &L, const float *I, const float *W, const float *gI, const float *obs,
                                float *loss_part, hipStream_t s, unsigned long long *evals = nullptr) {
   char *b = (char *)ws;
@@ -684,7 +684,7 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float
   const DevStatus *st = (const DevStatus *)(b + L.status);
   float4 *part = MODE == kBwdCount ? nullptr : (float4 *)(b + L.partials);
   const bool w256 = (flags & GS_FLAG_BWD_WINDOW_256) != 0;
-#define GS_BWD_ARGS T, bx, cutoff, eps, er, gb, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s
+#define GS_BWD_ARGS T, bx, eps, er, gb, lg, ls, bo, st, I, W, gI, obs, loss_part, L.cap, part, evals, s
   switch (T.bwd_bricks) {
     case 1:
       if (w256) bwd_launch<MODE, 1, 256, 1>(GS_BWD_ARGS);
@@ -706,7 +706,7 @@ static hipError_t bwd_dispatch(const ScanTable &T, int bx, uint32_t flags, float
 hipError_t launch_bwd(const ScanTable &T, int bx, uint32_t flags, float cutoff, float eps, void *ws, const WsLayout &L,
                       const float *I, const float *W, const float *dLdI, hipStream_t s) {
   prof_begin(s);
-  hipError_t e = bwd_dispatch<kBwdPlain>(T, bx, flags, cutoff, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
+  hipError_t e = bwd_dispatch<kBwdPlain>(T, bx, flags, eps, ws, L, I, W, dLdI, nullptr, nullptr, s);
   prof_end(s, "render_bwd");
   return e;
 }
@@ -715,7 +715,7 @@ hipError_t launch_bwd_fit(const ScanTable &T, int bx, uint32_t flags, float cuto
                           const WsLayout &L, const float *I, const float *W, const float *obs, float *loss_part,
                           hipStream_t s) {
   prof_begin(s);
-  hipError_t e = bwd_dispatch<kBwdFit>(T, bx, flags, cutoff, eps, ws, L, I, W, nullptr, obs, loss_part, s);
+  hipError_t e = bwd_dispatch<kBwdFit>(T, bx, flags, eps, ws, L, I, W, nullptr, obs, loss_part, s);
   prof_end(s, "render_bwd");
   return e;
 }
@@ -732,7 +732,7 @@ hipError_t launch_count_evals(const ScanTable &T, int bx, uint32_t flags, float 
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = fwd_dispatch<true>(T, bx, cutoff, 0.f, ws, L, nullptr, nullptr, c, s, c + 1);
   if (e == hipSuccess)
-    e = bwd_dispatch<kBwdCount>(T, bx, flags, cutoff, 0.f, ws, L, nullptr, nullptr, nullptr, nullptr, nullptr, s,
+    e = bwd_dispatch<kBwdCount>(T, bx, flags, 0.f, ws, L, nullptr, nullptr, nullptr, nullptr, nullptr, s,
                                 c + 3);
   prof_end(s, "count_evals");
   return e;
