@@ -473,3 +473,30 @@ def test_wide_gaussians_enumerated_by_the_wave(n_wide, n_small):
                        torch.from_numpy(g32).to(d))
         for k in oracle.GROUPS:
             assert_grad_close(gg[k], ref[k], f"wide d_{k} bx={bx}")
+
+
+def test_grid_at_the_dimension_limit():
+    """A grid 65535 voxels long, the largest per axis (voxel boxes are kept in 16-bit indices):
+    forward and stage-wise gradients against the oracle, with Gaussians at both ends of the axis
+    (some of them reaching past it)."""
+    dims = (65535, 6, 8)
+    p = synth.gaussians_uniform(131, 400, dims, ls_std=0.3)
+    p["mu"][:20, 0] = np.linspace(65520.0, 65535.5, 20, dtype=np.float32)
+    p["mu"][20:40, 0] = np.linspace(-1.0, 12.0, 20, dtype=np.float32)
+    grid = oracle.Grid(*dims)
+    p = cases.condition(p, grid, seed=138)
+    say("dimension limit", grid.shape, p["amp"].shape[0])
+    g, ggrid, opts, bins, I, W = gpu_render(p, grid)
+    Io, Wo, _ = oracle.render(p, grid)
+    assert_fwd_close(np64(W), Wo, "limit W")
+    assert_fwd_close(np64(I), Io, "limit I")
+    assert Wo[:, :, -4:].max() > 0 and Wo[:, :, :4].max() > 0  # both ends are covered
+    T = synth.uniform_volume(9, dims)
+    _, go = oracle.mse_loss(Io, T)
+    I32, W32, g32 = (x.astype(np.float32) for x in (Io, Wo, go))
+    d = torch.device("cuda")
+    gg = gpu_grads(g, ggrid, opts, bins, torch.from_numpy(I32).to(d), torch.from_numpy(W32).to(d),
+                   torch.from_numpy(g32).to(d))
+    ref = oracle.grad(p, grid, I32.astype(np.float64), W32.astype(np.float64), g32.astype(np.float64))
+    for k in oracle.GROUPS:
+        assert_grad_close(gg[k], ref[k], f"limit d_{k}")
