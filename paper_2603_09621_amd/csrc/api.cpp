@@ -94,6 +94,15 @@ bool make_brick_grid(const gs_grid_t *grid, const gs_opts_t *opts, BrickGrid *bg
   bg->nby = (grid->ny + opts->by - 1) / opts->by;
   bg->nbz = (grid->nz + opts->bz - 1) / opts->bz;
   bg->nbricks = (int64_t)bg->nbx * bg->nby * bg->nbz;
+  // division constants: s = ceil(log2 d), m = floor(2^(32 + s) / d) - 2^32 + 1
+  auto magic = [](uint32_t d, uint32_t &m, uint8_t &s) {
+    int l = 0;
+    while (((uint64_t)1 << l) < d) ++l;
+    s = (uint8_t)l;
+    m = (uint32_t)((((uint64_t)1 << (32 + l)) / d) - ((uint64_t)1 << 32) + 1);
+  };
+  magic((uint32_t)bg->nbx, bg->mbx, bg->sbx);
+  magic((uint32_t)bg->nby, bg->mby, bg->sby);
   bg->ox = grid->origin[0];
   bg->oy = grid->origin[1];
   bg->oz = grid->origin[2];

@@ -40,8 +40,13 @@ struct DevStatus {
 // Brick grid geometry of one scan.  Brick shape (bx, 8, 4) with bx in {4, 8, 16}.
 struct BrickGrid {
   int nx, ny, nz;    // voxels
-  int lbx, lby, lbz; // log2 of the brick shape (bricks are powers of two on every axis)
   int nbx, nby, nbz; // bricks per axis
+  uint8_t lbx, lby, lbz;  // log2 of the brick shape (bricks are powers of two on every axis)
+  // n / nbx and n / nby for n < 2^31 as (umulhi(n, m) + n) >> s (multiply-high division by an
+  // invariant divisor, constants from the host), so that a workgroup's brick coordinates need no
+  // vector instructions
+  uint8_t sbx, sby;
+  uint32_t mbx, mby;
   int64_t nbricks;
   float ox, oy, oz;  // origin
   float hx, hy, hz;  // spacing

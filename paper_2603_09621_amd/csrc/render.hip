@@ -96,10 +96,10 @@ __device__ __forceinline__ uint32_t cell_mask(const BrickGrid &bg, const EvalRec
 }
 
 // Origin (voxel indices) of the scan-local brick lb; brick counts are below 2^31 (checked when the
-// scan table is built), so 32-bit division suffices.
+// scan table is built), so the 32-bit multiply-high division of the brick grid applies.
 __device__ __forceinline__ void brick_coords(const BrickGrid &bg, int64_t lb, int &x0, int &y0, int &z0) {
   const uint32_t l = (uint32_t)lb, nbx = (uint32_t)bg.nbx, nby = (uint32_t)bg.nby;
-  const uint32_t row = l / nbx, kz = row / nby;
+  const uint32_t row = (__umulhi(l, bg.mbx) + l) >> bg.sbx, kz = (__umulhi(row, bg.mby) + row) >> bg.sby;
   const int kx = (int)(l - row * nbx), ky = (int)(row - kz * nby);
   x0 = kx << bg.lbx;
   y0 = ky * 8;
