@@ -457,23 +457,20 @@ constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 
 // One workgroup of NW waves per group of G consecutive bricks of a scan.  Wave w stages the bricks
 // j = w, w + NW, ... of the group (as a single wave: the fit's per-brick loss sums do not depend on the
-// workgroup shape).  The keys of all G bricks are ordered together, WIN at a time, by their number of
-// rows; the waves take the ordered keys 64 at a time, in a snake order over the waves (batch r NW + w,
-// then (r + 1) NW + NW - 1 - w, ...) so that the heaviest and the lightest batches are shared out.
-// (eight-wave groups of bricks up to 8 wide: registers capped for 8 waves per SIMD, i.e. four
-// workgroups per CU, so that the memory-bound phases of some workgroups (staging, ordering, the
-// partial sums' stores) overlap the VALU-bound row loops of others)
+// workgroup shape).  The keys of all G bricks are ordered together, WIN at a time, by class (full
+// rows, then half rows) and number of rows; the waves take the ordered keys 64 at a time, in a snake
+// order over the waves (batch r NW + w, then (r + 1) NW + NW - 1 - w, ...) so that the heaviest and
+// the lightest batches are shared out.  Eight-wave groups of bricks up to 8 wide have their registers
+// capped for 8 waves per SIMD, i.e. four workgroups per CU, so that the memory-bound phases of some
+// workgroups (staging, ordering, the partial sums' stores) overlap the VALU-bound row loops of others.
 template <int BX, int MODE, int G, int WIN, int NW>
-__global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && BX <= 8 ? 8 : 1))) void k_bwd(const ScanTable T, float eps,
-                                                      const EvalRec *__restrict__ er, const uint4 *__restrict__ gbox,
-                                                      const uint32_t *__restrict__ list_gid,
-                                                      const uint32_t *__restrict__ list_slot,
-                                                      const uint2 *__restrict__ brick_se, const DevStatus *st,
-                                                      const float *__restrict__ Iv, const float *__restrict__ Wv,
-                                                      const float *__restrict__ gI, const float *__restrict__ obs,
-                                                      float *__restrict__ loss_part, int64_t cap,
-                                                      float4 *__restrict__ part,
-                                                      unsigned long long *__restrict__ eval_count) {
+__global__ __launch_bounds__(kBwdWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && BX <= 8 ? 8 : 1)))
+void k_bwd(const ScanTable T, float eps, const EvalRec *__restrict__ er, const uint4 *__restrict__ gbox,
+           const uint32_t *__restrict__ list_gid, const uint32_t *__restrict__ list_slot,
+           const uint2 *__restrict__ brick_se, const DevStatus *st, const float *__restrict__ Iv,
+           const float *__restrict__ Wv, const float *__restrict__ gI, const float *__restrict__ obs,
+           float *__restrict__ loss_part, int64_t cap, float4 *__restrict__ part,
+           unsigned long long *__restrict__ eval_count) {
   constexpr bool FIT = MODE == kBwdFit, COUNT = MODE == kBwdCount;
   constexpr int NT = kBwdWave * NW;
   constexpr int RP = BX + 1;  // LDS row stride in voxels (pad: rows of a wave hit different banks)
