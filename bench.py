@@ -53,7 +53,7 @@ def alu_roofline(name, ms, pairs, flops_per_pair, slots_per_pair, traffic=None):
                       "frac": round(tslots / VALU_PEAK_TOPS, 4), "slots_per_pair": slots_per_pair}}
 
 
-def hbm_fractions(kern, K, N, B, V, nLR, passes):
+def hbm_fractions(kern, K, N, passes):
     """Algorithmic HBM bytes per launch of the binning, reduction and Adam kernels (what each must
     read and write once) over the launch's mean duration, against 8 TB/s."""
     per_launch = {
@@ -63,10 +63,10 @@ def hbm_fractions(kern, K, N, B, V, nLR, passes):
         "emit": (32 + 4) * N + 8 * K,
         # one digit histogram pass: brick ids read
         "radix_hist": 4 * K,
-        # a scatter pass: brick ids and slots read and written (the last pass also reads the
-        # Gaussian id by slot: 4 B per key in one of the passes)
+        # a scatter pass: brick ids and slots read and written; the last pass writes the Gaussian id
+        # (read by slot) instead of the brick id, i.e. 4 B more per key in one of the passes (the
+        # brick list bounds it also writes are 8 B per brick)
         "radix_scatter": 16 * K + 4 * K / passes,
-        "brick_offsets": 4 * K + 4 * B,
         # partials 48 B per key and key offsets read; 12 parameters, m, v read and written, the
         # 12 gradients written
         "reduce_adam": 48 * K + 4 * N + 12 * 4 * (3 + 3 + 1) * N,
@@ -482,7 +482,6 @@ def main():
     gs.gs_count_evals(g, grid, fo.opts, bins, ev)
     ev = dict(zip(gs.EVAL_COUNTS, (int(x) for x in ev.cpu())))
     K_end = status["n_keys"]
-    nvox = dims[0] * dims[1] * dims[2]
     cull = {
         "keys": K_end,
         "useful_pairs": ev["useful_pairs"],
@@ -497,7 +496,7 @@ def main():
     }
     nbricks = -(-dims[0] // fo.opts.bx) * -(-dims[1] // 8) * -(-dims[2] // 4)
     passes = max(1, -(-max(1, (nbricks - 1).bit_length()) // 8))
-    hbm = hbm_fractions(kern, K_end, args.n, nbricks, nvox, nvox // 4, passes)
+    hbm = hbm_fractions(kern, K_end, args.n, passes)
 
     # the same steps replayed from a HIP graph (one captured fit step per replay)
     ms_graph = None

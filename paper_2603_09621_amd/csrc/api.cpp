@@ -152,8 +152,6 @@ WsLayout make_layout(int64_t n, int64_t nbricks, int64_t cap, bool partials) {
                              sizeof(uint32_t) * (size_t)kRadix));
   L.partials = take(partials ? sizeof(float) * 12 * (size_t)cap : 0);
   L.total = o;
-  // pass p writes keys to keys_alt when p is even, key_brick when odd
-  L.sorted_keys = ((L.sort_passes - 1) & 1) ? L.key_brick : L.keys_alt;
   return L;
 }
 

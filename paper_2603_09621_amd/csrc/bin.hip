@@ -6,7 +6,8 @@
 // bricks its ellipsoid may meet: a count pass (fused with the record computation), an exclusive scan
 // that numbers the keys Gaussian-major, and an emit pass that writes (brick id, Gaussian) at each key's
 // slot.  A stable LSD radix sort on brick id (8-bit digits) then yields per-brick lists in ascending
-// Gaussian order together with each key's slot, which the backward uses to store its partial sums.
+// Gaussian order together with each key's slot, which the backward uses to store its partial sums;
+// its last pass also records where each brick's list starts and ends.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -260,8 +261,9 @@ uint64_t *__restrict__ bsum, uint32_t *__restrict__ hist, int64_t hist_len,
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
   // the first radix pass's histogram is accumulated by the emit kernel: clear it here
   for (int64_t k = i; k < hist_len; k += (int64_t)gridDim.x * kPrepThreads) hist[k] = 0u;
-  // bricks without keys keep (0, 0) as their list bounds
-  for (int64_t k = i; k < se_len; k += (int64_t)gridDim.x * kPrepThreads) brick_se[k] = 0u;
+  // brick list bounds start as (2^32 - 1, 0), which the last sort pass lowers and raises with atomic
+  // min / max; bricks without keys keep them (start > end: an empty list)
+  for (int64_t k = i; k < se_len; k += (int64_t)gridDim.x * kPrepThreads) brick_se[k] = (k & 1) ? 0u : 0xFFFFFFFFu;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   __shared__ uint32_t wcount[kPrepThreads];  // key counts of the wide Gaussians, by lane
@@ -627,7 +629,8 @@ hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *w
 //            wave ballots + a per-wave running count), the four waves' counts are combined into
 //            per-digit tile offsets, the tile is reordered by digit in LDS and written out in
 //            order, so consecutive threads store consecutive positions of a digit's run.  The last
-//            pass writes the Gaussian index of each key (looked up by slot) and the slot.
+//            pass writes the Gaussian index of each key (looked up by slot) and the slot, and in
+//            place of the sorted brick ids each brick's list bounds (§3.3 per-brick lists).
 
 __device__ __forceinline__ int64_t live_keys(const DevStatus *st, int64_t cap) {
   return st->overflow ? 0 : (st->n_keys < cap ? st->n_keys : cap);
@@ -737,7 +740,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ key_gid, uint32_t *__restrict__ gout,
     const DevStatus *st, int64_t cap, int shift, const uint32_t *__restrict__ offsets, int ntiles,
-    const uint32_t *__restrict__ dtot) {
+    const uint32_t *__restrict__ dtot, uint32_t *__restrict__ brick_se) {
   __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];  // per-wave running counts, then per-wave offsets
   __shared__ uint32_t tdo[kRadix];                      // digit offsets within the tile
   __shared__ uint32_t goff[kRadix];                     // global offset of the tile's first key of each digit
@@ -846,7 +849,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
   __syncthreads();
   // the tile in digit order: positions t, t + 256, ... per thread; in the last pass every Gaussian-index
-  // lookup of the thread is issued before the first store
+  // lookup of the thread is issued before the first store.  The last pass writes no brick ids: the
+  // tile is now in brick-id order (its keys came sorted by the lower digits and the reorder is
+  // stable), and a run of equal ids goes to consecutive positions, so the run's first and last
+  // positions bound its brick's list; a brick's runs in different tiles are adjacent in the output,
+  // so the minimum of their starts and the maximum of their ends give the whole list (atomic min and
+  // max: the result does not depend on the order of the tiles).
   uint32_t gid[kSortItems];
   if (LAST) {
 #pragma unroll
@@ -859,41 +867,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       const uint32_t key = skey[i], val = sval[i];
       const uint32_t d = (key >> shift) & (kRadix - 1);
       const uint32_t pos = goff[d] + ((uint32_t)i - tdo[d]);
-      kout[pos] = key;
       vout[pos] = val;
-      if (LAST) gout[pos] = gid[j];
+      if (LAST) {
+        gout[pos] = gid[j];
+        if (i == 0 || skey[i - 1] != key) atomicMin(&brick_se[2 * (int64_t)key], pos);
+        if (i == n_tile - 1 || skey[i + 1] != key) atomicMax(&brick_se[2 * (int64_t)key + 1], pos + 1u);
+      } else {
+        kout[pos] = key;
+      }
     }
-  }
-}
-
-// Brick lists in the sorted keys: every brick with keys gets (first position, end) from the positions
-// where the sorted brick id changes (each entry is written by exactly one thread: the one at its
-// list's first key, or at the next list's first key / the end).  Bricks without keys keep the
-// (0, 0) the prep kernel wrote.
-__global__ __launch_bounds__(256) void k_brick_bounds(const uint32_t *__restrict__ sorted_brick, const DevStatus *st,
-                                                      int64_t cap, uint32_t *__restrict__ brick_se) {
-  const int64_t K = live_keys(st, cap);
-  // four consecutive positions per thread (one 16-byte load) and the key before them
-  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (k0 > K) return;
-  uint32_t v[5];
-  v[0] = k0 > 0 ? sorted_brick[k0 - 1] : 0xFFFFFFFFu;
-  if (k0 + 4 <= K) {
-    const uint4 q = *reinterpret_cast<const uint4 *>(sorted_brick + k0);
-    v[1] = q.x;
-    v[2] = q.y;
-    v[3] = q.z;
-    v[4] = q.w;
-  } else {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[1 + j] = k0 + j < K ? sorted_brick[k0 + j] : 0xFFFFFFFFu;
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t k = k0 + j;
-    const uint32_t cur = v[1 + j], prev = v[j];
-    if (k < K && (k == 0 || cur != prev)) brick_se[2 * (int64_t)cur] = (uint32_t)k;
-    if (k > 0 && k <= K && (k == K || cur != prev)) brick_se[2 * (int64_t)prev + 1] = (uint32_t)k;
   }
 }
 
@@ -921,21 +903,17 @@ hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStrea
       prof_end(s, "radix_scan");
       prof_begin(s);
       if (last)
-        k_radix_scatter<true><<<nt, kSortThreads, 0, s>>>(kin, vin, kout, vout, (const uint32_t *)(b + L.key_gid),
+        k_radix_scatter<true><<<nt, kSortThreads, 0, s>>>(kin, vin, nullptr, vout, (const uint32_t *)(b + L.key_gid),
                                                           (uint32_t *)(b + L.list_gid), st, L.cap, p * kRadixBits,
-                                                          hist, nt, dtot);
+                                                          hist, nt, dtot, (uint32_t *)(b + L.brick_se));
       else
         k_radix_scatter<false><<<nt, kSortThreads, 0, s>>>(kin, vin, kout, vout, nullptr, nullptr, st, L.cap,
-                                                           p * kRadixBits, hist, nt, dtot);
+                                                           p * kRadixBits, hist, nt, dtot, nullptr);
       prof_end(s, "radix_scatter");
       kin = kout;
       vin = vout;
     }
   }
-  const int ob = (int)((L.cap + 1 + 1023) / 1024);
-  prof_begin(s);
-  k_brick_bounds<<<ob, 256, 0, s>>>((const uint32_t *)(b + L.sorted_keys), st, L.cap, (uint32_t *)(b + L.brick_se));
-  prof_end(s, "brick_offsets");
   return hipGetLastError();
 }
 

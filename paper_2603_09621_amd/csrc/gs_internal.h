@@ -129,8 +129,8 @@ constexpr uint64_t kBadBlock = 1ull << 63;
 //   scan_tmp: per-block key totals of the count scan (uint64), later the radix digit totals.
 //   key_brick, key_gid: uint32 [cap] keys in slot order; keys_alt, vals_a, vals_b: radix ping-pong.
 //   list_gid, list_slot: uint32 [cap] the keys sorted by brick: Gaussian index and key slot.
-//   brick_se: uint32 [B][2] each brick's list bounds (first position, end) in the sorted keys, (0, 0)
-//   for a brick without keys.  partials: 48 B per key slot (backward; absent in a forward-only
+//   brick_se: uint32 [B][2] each brick's list bounds (first position, end) in the sorted keys,
+//   (2^32 - 1, 0) for a brick without keys (any start >= end is an empty list).  partials: 48 B per key slot (backward; absent in a forward-only
 //   workspace).
 struct WsLayout {
   int64_t n = 0, cap = 0, nbricks = 0;
@@ -138,7 +138,6 @@ struct WsLayout {
   int sort_passes = 0;  // ceil(bits(nbricks) / 8), at least 1
   size_t status = 0, evalrec = 0, cullrec = 0, off = 0, runs = 0, gbox = 0, key_brick = 0, key_gid = 0, keys_alt = 0, vals_a = 0,
          vals_b = 0, list_gid = 0, list_slot = 0, brick_se = 0, hist = 0, scan_tmp = 0, partials = 0, total = 0;
-  size_t sorted_keys = 0;  // where the brick ids end up after the last pass
 };
 
 // Host-side helpers (api.cpp).
