@@ -395,11 +395,12 @@ int gs_workspace_size(int64_t n, const gs_grid_t *grid, const gs_opts_t *opts, i
 size_t gs_loss_scratch_bytes(int64_t nvox) { return sizeof(float) * (size_t)std::max(1, loss_blocks(nvox)); }
 
 // step: the fit's per-scan step counters (advanced by the count scan), or NULL outside a fit step
+// scan: run the count scan's second level (the emit does it for small sets when it follows)
 static int bin_front(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
-                     const WsLayout &L, hipStream_t s, int32_t *step = nullptr) {
+                     const WsLayout &L, hipStream_t s, int32_t *step = nullptr, bool scan = true) {
   hipError_t e;
   if ((e = launch_prep_count(T, opts->cutoff, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "prep_count");
-  if ((e = launch_scan_counts(bins->ws, L, step, T.ns, s)) != hipSuccess) return hip_fail(e, "scan_counts");
+  if (scan && (e = launch_scan_counts(bins->ws, L, step, T.ns, s)) != hipSuccess) return hip_fail(e, "scan_counts");
   return GS_OK;
 }
 
@@ -430,9 +431,11 @@ int gs_bin_query(const gs_gaussians_t *g, const gs_grid_t *grid, const gs_opts_t
 static int bin_all(const gs_gaussians_t *g, const ScanTable &T, const gs_opts_t *opts, const gs_bins_t *bins,
                    const WsLayout &L, hipStream_t s, int32_t *step = nullptr) {
   int rc;
-  if ((rc = bin_front(g, T, opts, bins, L, s, step))) return rc;
+  const bool fused = emit_scans(T.n_total);
+  if ((rc = bin_front(g, T, opts, bins, L, s, step, !fused))) return rc;
   hipError_t e;
-  if ((e = launch_emit(T, opts->cutoff, opts->flags, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "emit");
+  if ((e = launch_emit(T, opts->cutoff, opts->flags, bins->ws, L, fused ? step : nullptr, s)) != hipSuccess)
+    return hip_fail(e, "emit");
   if ((e = launch_sort(T, bins->ws, L, s)) != hipSuccess) return hip_fail(e, "sort");
   return GS_OK;
 }

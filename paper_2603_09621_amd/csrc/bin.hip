@@ -449,23 +449,88 @@ hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns
 constexpr int kEmitStageSmall = 4096, kEmitStageLarge = 6144;
 
 
-template <int kEmitStage>
+// FUSED (at most kFusedScanBlocks blocks): the count scan's second level is done here too.  bex then
+// holds the per-block key totals as the prep kernel wrote them, and every block sums them itself: the
+// totals of the blocks before it (its offset), all of them (the key count) and their non-finite
+// flags; block 0 writes the status block, off[n] and the step counters as the scan kernel would.
+// Otherwise bex holds the scanned block offsets and the status block is already written.
+constexpr int kFusedScanBlocks = 2048;
+static_assert(kFusedScanBlocks % kPrepThreads == 0, "whole loads per thread");
+
+template <int kEmitStage, bool FUSED>
 __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float cutoff,
                                                        const EvalRec *__restrict__ er,
                                                        const CullRec *__restrict__ cr,
                                                        const uint32_t *__restrict__ runs, uint32_t *__restrict__ off,
                                                        const uint64_t *__restrict__ bex, int64_t cap,
-                                                       const DevStatus *st, uint32_t *__restrict__ key_brick,
+                                                       DevStatus *st, uint32_t *__restrict__ key_brick,
                                                        uint32_t *__restrict__ key_gid, uint32_t *__restrict__ hist,
-                                                       int ntiles) {
+                                                       int ntiles, int32_t *__restrict__ step) {
   __shared__ uint32_t sbrick[kEmitStage], sgid[kEmitStage];
   __shared__ uint32_t wtot[kPrepThreads / 64];
+  __shared__ uint64_t fpre[kPrepThreads / 64], ftot[kPrepThreads / 64];
+  __shared__ int fbad;
   // digit counts of the sort tiles a staged range meets (a range of kEmitStage keys meets at most
   // kEmitTiles tiles)
   constexpr int kEmitTiles = (kEmitStage + kSortTile - 2) / kSortTile + 1;
   __shared__ uint32_t tcnt[kEmitTiles][kRadix];
-  if (st->overflow) return;
   const int64_t n = T.n_total;
+  uint64_t blk_off;
+  if (FUSED) {
+    if (threadIdx.x == 0) fbad = 0;
+    __syncthreads();
+    // (all of the thread's loads issued at once: at most kFusedScanBlocks / kPrepThreads of them)
+    constexpr int kPer = kFusedScanBlocks / kPrepThreads;
+    uint64_t vv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = (int)threadIdx.x + q * kPrepThreads;
+      vv[q] = k < (int)gridDim.x ? bex[k] : 0ull;
+    }
+    uint64_t pre = 0, tot = 0;
+    int bad = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = (int)threadIdx.x + q * kPrepThreads;
+      const uint64_t v = vv[q];
+      bad |= (v & kBadBlock) ? 1 : 0;
+      tot += v & ~kBadBlock;
+      pre += k < (int)blockIdx.x ? v & ~kBadBlock : 0ull;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      pre += __shfl_down(pre, d, 64);
+      tot += __shfl_down(tot, d, 64);
+    }
+    if (bad) atomicOr(&fbad, 1);
+    if (lane_id() == 0) {
+      fpre[threadIdx.x >> 6] = pre;
+      ftot[threadIdx.x >> 6] = tot;
+    }
+    __syncthreads();
+    pre = 0;
+    tot = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kPrepThreads / 64; ++w2) {
+      pre += fpre[w2];
+      tot += ftot[w2];
+    }
+    const bool over = (int64_t)tot > cap;
+    if (blockIdx.x == 0) {
+      if (threadIdx.x == 0) {
+        st->n_keys = (int64_t)tot;
+        st->overflow = over ? 1 : 0;
+        st->nonfinite = fbad;
+        off[n] = over ? (uint32_t)cap : (uint32_t)tot;
+      }
+      if (step && (int)threadIdx.x < T.ns && !over) step[threadIdx.x] += 1;
+    }
+    if (over) return;  // uniform per block
+    blk_off = pre;
+  } else {
+    if (st->overflow) return;
+    blk_off = bex[blockIdx.x];
+  }
   const int64_t i = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x;
   // off[i] holds the key count of Gaussian i; turn it into its first slot: the block's offset plus
   // the exclusive scan of the counts within the block
@@ -480,7 +545,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
     woff += k < w ? wtot[k] : 0u;
     btot += wtot[k];
   }
-  const uint32_t blk0 = (uint32_t)bex[blockIdx.x], blk1 = blk0 + btot;
+  const uint32_t blk0 = (uint32_t)blk_off, blk1 = blk0 + btot;
   const uint32_t base = blk0 + woff + incl - c;
   if (i < n) off[i] = base;
   const bool staged = btot <= (uint32_t)kEmitStage;
@@ -602,21 +667,26 @@ __global__ __launch_bounds__(kPrepThreads) void k_emit(const ScanTable T, float 
   }
 }
 
-hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *ws, const WsLayout &L, hipStream_t s) {
+bool emit_scans(int64_t n) { return n > 0 && (n + kPrepThreads - 1) / kPrepThreads <= kFusedScanBlocks; }
+
+hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *ws, const WsLayout &L, int32_t *step,
+                       hipStream_t s) {
   if (T.n_total == 0) return hipSuccess;
   char *b = (char *)ws;
   const int blocks = (int)((T.n_total + kPrepThreads - 1) / kPrepThreads);
+  const bool fused = emit_scans(T.n_total);
   // the capacity is sized from the exact key count (times a headroom): its share per block tells
   // whether blocks typically hold more keys than the small stage (the results do not depend on it)
   const bool large = (flags & GS_FLAG_EMIT_STAGE_6K) ||
                      (!(flags & GS_FLAG_EMIT_STAGE_4K) && L.cap / blocks > (int64_t)(7 * kEmitStageSmall / 8));
-  auto emit = large ? k_emit<kEmitStageLarge> : k_emit<kEmitStageSmall>;
+  auto emit = large ? (fused ? k_emit<kEmitStageLarge, true> : k_emit<kEmitStageLarge, false>)
+                     : (fused ? k_emit<kEmitStageSmall, true> : k_emit<kEmitStageSmall, false>);
   prof_begin(s);
   emit<<<blocks, kPrepThreads, 0, s>>>(T, cutoff, (const EvalRec *)(b + L.evalrec), (const CullRec *)(b + L.cullrec),
                                        (const uint32_t *)(b + L.runs), (uint32_t *)(b + L.off),
-                                       (const uint64_t *)(b + L.scan_tmp), L.cap, (const DevStatus *)(b + L.status),
+                                       (const uint64_t *)(b + L.scan_tmp), L.cap, (DevStatus *)(b + L.status),
                                        (uint32_t *)(b + L.key_brick), (uint32_t *)(b + L.key_gid),
-                                       (uint32_t *)(b + L.hist), L.sort_blocks);
+                                       (uint32_t *)(b + L.hist), L.sort_blocks, step);
   prof_end(s, "emit");
   return hipGetLastError();
 }

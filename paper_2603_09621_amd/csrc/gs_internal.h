@@ -152,7 +152,11 @@ void prof_end(hipStream_t s, const char *name);
 // launches.  `g` / `st` hold the concatenated Gaussians of all scans of T.
 hipError_t launch_prep_count(const ScanTable &T, float cutoff, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_scan_counts(void *ws, const WsLayout &L, int32_t *step, int ns, hipStream_t s);
-hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *ws, const WsLayout &L, hipStream_t s);
+// emit_scans(n): the emit does the count scan's second level itself (a one-block scan kernel is then
+// not launched); step as for launch_scan_counts.
+bool emit_scans(int64_t n);
+hipError_t launch_emit(const ScanTable &T, float cutoff, uint32_t flags, void *ws, const WsLayout &L, int32_t *step,
+                       hipStream_t s);
 hipError_t launch_sort(const ScanTable &T, void *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_fwd(const ScanTable &T, int bx, float cutoff, float eps, const void *ws, const WsLayout &L,
                       float *I, float *W, hipStream_t s);
