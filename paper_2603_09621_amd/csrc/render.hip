@@ -458,9 +458,9 @@ constexpr int kBwdPlain = 0, kBwdFit = 1, kBwdCount = 2;
 // One workgroup of NW waves per group of G consecutive bricks of a scan.  Wave w stages the bricks
 // j = w, w + NW, ... of the group (as a single wave: the fit's per-brick loss sums do not depend on the
 // workgroup shape).  The keys of all G bricks are ordered together, WIN at a time, by class (full
-// rows, then half rows) and number of rows; the waves take the ordered keys 64 at a time, in a snake
-// order over the waves (batch r NW + w, then (r + 1) NW + NW - 1 - w, ...) so that the heaviest and
-// the lightest batches are shared out.  Eight-wave groups of bricks up to 8 wide have their registers
+// rows, then half rows) and number of rows; the waves take the ordered keys 64 at a time, wave w
+// batch w first and then whichever batch is next when it is done (an LDS counter), so that the
+// heaviest batches start first and the lighter ones fill in.  Eight-wave groups of bricks up to 8 wide have their registers
 // capped for 8 waves per SIMD, i.e. four workgroups per CU, so that the memory-bound phases of some
 // workgroups (staging, ordering, the partial sums' stores) overlap the VALU-bound row loops of others.
 template <int BX, int MODE, int G, int WIN, int NW>
@@ -491,6 +491,7 @@ void k_bwd(const ScanTable T, float eps, const EvalRec *__restrict__ er, const u
   // boff[j]: where brick j's keys start in the group's contiguous key range (for a brick without
   // keys, where the next brick's start), boff[G]: the range's end
   __shared__ uint32_t sboff[G + 1];
+  __shared__ uint32_t snext;  // the window's next 64-key batch to hand out (batch w starts wave w)
   __shared__ uint2 sse[G];
   const int64_t q = blockIdx.x;
   const ScanDesc &sd = T.s[T.of_group(q)];
@@ -542,6 +543,7 @@ void k_bwd(const ScanTable T, float eps, const EvalRec *__restrict__ er, const u
     // most first, so that the lanes of a wave run similar numbers of row iterations (each key's
     // result is independent of where it runs, so the order does not change any result)
     for (int k = t; k < kBwdBuckets; k += NT) bcount[k] = 0u;
+    if (t == 0) snext = NW;
     __syncthreads();
     for (int j = t; j < L; j += NT) {
       const uint32_t k = w0 + j;
@@ -583,7 +585,14 @@ void k_bwd(const ScanTable T, float eps, const EvalRec *__restrict__ er, const u
     for (int j = t; j < L; j += NT) sorder[atomicAdd(&bcursor[sbucket[j]], 1u)] = (uint16_t)j;
     __syncthreads();
     for (int r = 0;; ++r) {
-      const int c0 = kBwdWave * (r * NW + ((r & 1) ? NW - 1 - w : w));
+      // batch w first, then whichever batch is next in line when the wave is done with its last:
+      // the batches come heaviest first, so this is longest-first list scheduling over the waves
+      uint32_t bi = (uint32_t)w;
+      if (r > 0) {
+        const uint32_t v = l == 0 ? atomicAdd(&snext, 1u) : 0u;
+        bi = (uint32_t)__shfl((int)v, 0, 64);
+      }
+      const int c0 = kBwdWave * (int)bi;
       if (c0 >= L) break;  // uniform per wave
       const int p = c0 + l;
       if (p >= L) continue;
