@@ -500,3 +500,44 @@ def test_grid_at_the_dimension_limit():
     ref = oracle.grad(p, grid, I32.astype(np.float64), W32.astype(np.float64), g32.astype(np.float64))
     for k in oracle.GROUPS:
         assert_grad_close(gg[k], ref[k], f"limit d_{k}")
+
+
+def test_count_scan_paths_agree():
+    """A set of at most 2048 blocks of 256 Gaussians has its count scan done inside the emit kernel, a
+    larger one by a scan kernel of its own.  Keys and useful pairs belong to single Gaussians, so a set
+    A of 2048 * 256 Gaussians (scan in the emit) and A plus one more Gaussian g (scan kernel) must
+    differ in key and pair count by exactly the counts of g alone; and g, the last Gaussian, ends each
+    of its bricks' lists, so the two renders are bitwise equal at every voxel outside g's box and
+    differ somewhere inside it."""
+    gs = gs_mod()
+    n = 2048 * 256
+    dims = (96, 96, 64)
+    grid = oracle.Grid(*dims)
+    p = synth.gaussians_uniform(71, n + 1, dims, ls_mean=math.log(0.7), ls_std=0.2)
+    ggrid = to_grid(grid)
+    opts = gs.Opts()
+
+    def counts(q):
+        g = gs.Gaussians.from_numpy(q)
+        I, _, bins = gs.render(g, ggrid, opts)
+        st = gs.gs_status(bins)
+        assert st["overflow"] == 0 and st["nonfinite"] == 0
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gs.gs_count_pairs(g, ggrid, opts, bins, cnt)
+        return st["n_keys"], int(cnt.item()), I.cpu().numpy()
+
+    sub = lambda a, b: {k: v[a:b] for k, v in p.items()}
+    say("count scan paths", dims, n, n + 1)
+    kA, pA, IA = counts(sub(0, n))
+    kB, pB, IB = counts(sub(0, n + 1))
+    kg, pg, _ = counts(sub(n, n + 1))
+    assert kg > 0 and pg > 0
+    assert kB == kA + kg and pB == pA + pg
+    # g's voxel box, generously: 3 sigma of its largest axis plus a voxel
+    mu, r = p["mu"][n].astype(np.float64), 3.0 * math.exp(float(p["log_scale"][n].max())) + 1.0
+    lo = np.floor(mu - 0.5 - r).astype(int)
+    hi = np.ceil(mu - 0.5 + r).astype(int)
+    inside = np.zeros(IA.shape, dtype=bool)
+    inside[max(lo[2], 0):hi[2] + 1, max(lo[1], 0):hi[1] + 1, max(lo[0], 0):hi[0] + 1] = True
+    diff = IA != IB
+    assert diff.any() and not (diff & ~inside).any()
