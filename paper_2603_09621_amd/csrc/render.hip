@@ -213,7 +213,9 @@ __global__ __launch_bounds__(32 * BX) void k_fwd(const ScanTable T, float cutoff
         }
       }
     }
-    __syncthreads();
+    // the next chunk reuses the staging areas; after the last one each wave goes on to its own
+    // epilogue (which needs no LDS) without waiting for the others
+    if (c0 + NT < end) __syncthreads();
   }
   if (COUNT) {
     unsigned long long v[3] = {npairs, nevals, nissued};
