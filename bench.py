@@ -497,6 +497,22 @@ def main():
     nbricks = -(-dims[0] // fo.opts.bx) * -(-dims[1] // 8) * -(-dims[2] // 4)
     passes = max(1, -(-max(1, (nbricks - 1).bit_length()) // 8))
     hbm = hbm_fractions(kern, K_end, args.n, passes)
+    # what a plain device-to-device copy reaches here (bytes read + written over its duration): the
+    # practical ceiling of the HBM-bound kernels, beside the published 8 TB/s
+    copy_src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    copy_dst = torch.empty_like(copy_src)
+    copy_dst.copy_(copy_src)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(5):
+        copy_dst.copy_(copy_src)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * copy_src.numel() * 4 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del copy_src, copy_dst
+    for v in hbm.values():
+        v["frac_of_copy"] = round(v["GBps"] / copy_gbps, 4)
+    hbm["device_copy_GBps"] = round(copy_gbps, 1)
 
     # the same steps replayed from a HIP graph (one captured fit step per replay)
     ms_graph = None
